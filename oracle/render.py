@@ -1,0 +1,284 @@
+"""FP64 CPU oracle of the MLP-Splatting render path (test infrastructure only).
+
+This is a plain, slow, direct transcription of what the method computes; it is
+used only by the tests, by the smoke check and by the benchmark's CPU-baseline
+leg.  It shares no code with the HIP library.
+
+Every function works for float64 tensors (with autograd, which gives the
+oracle's analytic gradient) and for complex128 tensors (complex-step
+differentiation).  All discrete decisions -- hit or miss, depth order, sample
+count, ReLU gate, the early-termination cut -- are taken on real parts and are
+held fixed under differentiation.
+
+Readings taken where the paper leaves a choice open (each is listed in
+the design doc):
+  * quaternion order (w, x, y, z), Hamilton product, normalised before use;
+  * the scale vector gives the semi-axes of a hard ellipsoid support; density
+    is zero outside it (no Gaussian falloff inside);
+  * the MLP input is the scale-normalised local position p of a sample, with
+    an identity term in front of the sin/cos encoding;
+  * K stratified samples per hit interval, bin width Delta = L / K used as the
+    thickness in alpha = 1 - exp(-sigma * Delta);
+  * hits are composited one after the other (hit-major), sorted by the
+    unclamped contact depth, ties broken by primitive index;
+  * early termination stops after the first sample whose transmittance falls
+    below the threshold.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from .pcg import sample_offsets
+
+__all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
+           "encode", "mlp_apply", "render"]
+
+
+@dataclasses.dataclass(frozen=True)
+class Model:
+    pe_freqs: int
+    hidden_width: int
+    hidden_layers: int
+    out_dim: int
+
+    @property
+    def in_dim(self) -> int:
+        return 3 + 6 * self.pe_freqs
+
+    def layer_dims(self):
+        dims = [self.in_dim] + [self.hidden_width] * self.hidden_layers + [self.out_dim]
+        return [(dims[i], dims[i + 1]) for i in range(len(dims) - 1)]
+
+    @property
+    def num_params(self) -> int:
+        return sum(i * o + o for i, o in self.layer_dims())
+
+
+@dataclasses.dataclass(frozen=True)
+class Opts:
+    samples_fixed: int = 32          # K per hit; 0 = proportional to chord length
+    samples_min: int = 8
+    samples_max: int = 128
+    samples_per_unit: float = 128.0
+    t_stop: float = 0.0              # 0 = no early termination
+    jitter: int = 1                  # 1 = hashed stratified offsets, 0 = midpoints
+    jitter_seed: int = 0
+    background: Sequence[float] = (0.0, 0.0, 0.0)
+
+
+def _where(cond, a, b):
+    return torch.where(cond, a, b)
+
+
+def quat_to_rotmat(q: torch.Tensor) -> torch.Tensor:
+    """Rotation matrix R(q) of the normalised quaternion (w, x, y, z), Hamilton
+    convention (Sec. 3.1: a unit quaternion gives the primitive's rotation)."""
+    n = torch.sqrt((q * q).sum(-1, keepdim=True))
+    w, x, y, z = (q / n).unbind(-1)
+    r = torch.stack([
+        1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y),
+    ], dim=-1)
+    return r.reshape(q.shape[:-1] + (3, 3))
+
+
+def local_frame(scale: torch.Tensor, quat: torch.Tensor) -> torch.Tensor:
+    """M = diag(s)^-1 R(q)^T, so that p = M (x - mu) is the scale-normalised
+    local position and (x-mu)^T Lambda (x-mu) = |p|^2 with
+    Lambda = R diag(s^-2) R^T (Sec. 3.2, the support metric under Eq. 1)."""
+    r = quat_to_rotmat(quat)
+    return r.transpose(-1, -2) / scale[..., :, None]
+
+
+def intersect(ray_o, ray_d, center, scale, quat):
+    """Ray/support test for every (ray, primitive) pair.
+
+    With o_l = M(o - mu), d_l = M d and a = |d_l|^2 the contact depth is
+    t_c = -(o_l . d_l) / a, which is the unclamped minimiser of Eq. 1 (its
+    clamped form is Eq. 2).  The chord of the ellipsoid |p| <= 1 is
+    [t_c - eta, t_c + eta] with g = 1 - |o_l + t_c d_l|^2 and eta = sqrt(g/a).
+    A pair is a hit iff g > 0 and t_c + eta > 0; the interval starts at
+    max(t_c - eta, 0) (the clamp of Eq. 2).
+    Returns dict of [R, P] tensors.
+    """
+    m = local_frame(scale, quat)                                  # [P,3,3]
+    rel = ray_o[:, None, :].to(m.dtype) - center[None, :, :]     # [R,P,3]
+    ol = torch.einsum("pij,rpj->rpi", m, rel)
+    dl = torch.einsum("pij,rj->rpi", m, ray_d.to(m.dtype))
+    a = (dl * dl).sum(-1)
+    tc = -(ol * dl).sum(-1) / a
+    pc = ol + tc[..., None] * dl
+    g = 1 - (pc * pc).sum(-1)
+    gpos = g.real > 0
+    eta = torch.sqrt(_where(gpos, g, torch.ones_like(g)) / a)
+    eta = _where(gpos, eta, torch.zeros_like(eta))
+    hit = gpos & ((tc + eta).real > 0)
+    ta_raw = tc - eta
+    ta = _where(ta_raw.real > 0, ta_raw, torch.zeros_like(ta_raw))
+    tb = tc + eta
+    return {"ol": ol, "dl": dl, "a": a, "tc": tc, "g": g, "eta": eta,
+            "hit": hit, "ta": ta, "tb": tb}
+
+
+def encode(p: torch.Tensor, n_freqs: int) -> torch.Tensor:
+    """gamma(p) = [p, then per level l: sin(2^l pi p), cos(2^l pi p)] (Sec. 3.2
+    positional encoding, applied per coordinate, with an identity term)."""
+    feats = [p]
+    for lvl in range(n_freqs):
+        arg = (2.0 ** lvl) * math.pi * p
+        feats.append(torch.sin(arg))
+        feats.append(torch.cos(arg))
+    return torch.cat(feats, dim=-1)
+
+
+def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model) -> torch.Tensor:
+    """One primitive's MLP: ReLU hidden layers, linear output (raw values)."""
+    off = 0
+    h = x
+    dims = model.layer_dims()
+    for li, (fi, fo) in enumerate(dims):
+        w = theta[off:off + fi * fo].reshape(fo, fi)
+        off += fi * fo
+        b = theta[off:off + fo]
+        off += fo
+        h = h @ w.transpose(0, 1) + b
+        if li < len(dims) - 1:
+            h = _where(h.real > 0, h, torch.zeros_like(h))
+    return h
+
+
+def _softplus(o):
+    pos = o.real > 0
+    return _where(pos, o + torch.log1p(torch.exp(-o)), torch.log1p(torch.exp(o)))
+
+
+def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
+           ray_index_base: int = 0, keep_samples: bool = False) -> dict:
+    """Render every ray (Sec. 3.3 front-to-back compositing over the depth-
+    sorted hits, each hit sampled at K stratified points of its chord).
+
+    Parameters are float64 (or complex128) tensors; rays are float64.
+    ``ray_index_base`` offsets the ray index fed to the sample-offset hash, so a
+    subset of a batch can be rendered with the batch's own offsets.
+    """
+    dt = center.dtype
+    nr = ray_o.shape[0]
+    npr = center.shape[0]
+    isx = intersect(ray_o, ray_d, center, scale, quat)
+    hit = isx["hit"]
+    # --- depth order: ascending (t_c, primitive index) per ray ---
+    rr, pp = torch.nonzero(hit, as_tuple=True)
+    rr = rr.numpy()
+    pp = pp.numpy()
+    tcr = isx["tc"].real.detach()[rr, pp].numpy() if len(rr) else np.zeros(0)
+    order = np.lexsort((pp, tcr, rr))
+    rr, pp = rr[order], pp[order]
+    nh = len(rr)
+    counts = np.bincount(rr, minlength=nr)
+    ray_off = np.zeros(nr + 1, np.int64)
+    ray_off[1:] = np.cumsum(counts)
+    rank = np.arange(nh) - ray_off[rr]
+    rr_t = torch.from_numpy(rr)
+    pp_t = torch.from_numpy(pp)
+    tc = isx["tc"][rr_t, pp_t]
+    eta = isx["eta"][rr_t, pp_t]
+    ta = isx["ta"][rr_t, pp_t]
+    tb = isx["tb"][rr_t, pp_t]
+    ol = isx["ol"][rr_t, pp_t]
+    dl = isx["dl"][rr_t, pp_t]
+    length = tb - ta
+    # --- samples per hit ---
+    if opts.samples_fixed > 0:
+        kh = np.full(nh, opts.samples_fixed, np.int64)
+    else:
+        kh = np.ceil(opts.samples_per_unit * length.real.detach().numpy()).astype(np.int64)
+        kh = np.clip(kh, opts.samples_min, opts.samples_max)
+    delta = length / torch.from_numpy(kh).to(dt)
+    # flat samples in (ray, rank, k) order
+    hs = np.repeat(np.arange(nh), kh)
+    hoff = np.zeros(nh + 1, np.int64)
+    hoff[1:] = np.cumsum(kh)
+    kk = np.arange(len(hs)) - hoff[hs]
+    if opts.jitter:
+        u = sample_offsets(opts.jitter_seed, rr[hs] + ray_index_base, rank[hs], kk)
+    else:
+        u = np.full(len(hs), 0.5)
+    hs_t = torch.from_numpy(hs)
+    tk = ta[hs_t] + (torch.from_numpy(kk).to(dt) + torch.from_numpy(u).to(dt)) * delta[hs_t]
+    pk = ol[hs_t] + tk[:, None] * dl[hs_t]
+    # --- per-primitive MLPs ---
+    gam = encode(pk, model.pe_freqs)
+    raw = torch.zeros((len(hs), model.out_dim), dtype=dt)
+    sprim = pp[hs]
+    out_rows = []
+    for p in np.unique(sprim):
+        idx = torch.from_numpy(np.nonzero(sprim == p)[0])
+        out_rows.append((idx, mlp_apply(mlp[int(p)], gam[idx], model)))
+    if out_rows:
+        raw = raw.index_put(tuple([torch.cat([i for i, _ in out_rows])]),
+                            torch.cat([v for _, v in out_rows]))
+    col = torch.sigmoid(raw[:, :3])
+    sig = _softplus(raw[:, 3])
+    feat = raw[:, 4:]
+    tau = sig * delta[hs_t]
+    # --- compositing (padded per ray, hit-major sample order) ---
+    sray = rr[hs]
+    sc = np.bincount(sray, minlength=nr) if len(hs) else np.zeros(nr, np.int64)
+    soff = np.zeros(nr + 1, np.int64)
+    soff[1:] = np.cumsum(sc)
+    smax = int(sc.max()) if nr and len(hs) else 0
+    pos = np.arange(len(hs)) - soff[sray]
+    cf = model.out_dim - 4
+    bg = torch.tensor(list(opts.background), dtype=dt)
+    if smax == 0:
+        rgb = torch.zeros((nr, 3), dtype=dt) + bg
+        return _pack(rgb, torch.ones(nr, dtype=dt), torch.zeros((nr, cf), dtype=dt),
+                     np.zeros(nr, np.int64), ray_off, pp, tc, eta, ta, tb, kh, isx, None)
+    tau_pad = torch.zeros((nr, smax), dtype=dt)
+    idx2 = (torch.from_numpy(sray), torch.from_numpy(pos))
+    tau_pad = tau_pad.index_put(idx2, tau)
+    s_incl = torch.cumsum(tau_pad, dim=1)
+    s_excl = s_incl - tau_pad
+    t_before = torch.exp(-s_excl)
+    valid = torch.zeros((nr, smax), dtype=torch.bool)
+    valid[idx2] = True
+    if opts.t_stop > 0:
+        used = valid & (t_before.real >= opts.t_stop)
+    else:
+        used = valid
+    alpha = 1 - torch.exp(-tau_pad)
+    w = _where(used, t_before * alpha, torch.zeros_like(alpha))
+    c_pad = torch.zeros((nr, smax, 3), dtype=dt).index_put(idx2, col)
+    rgb = (w[..., None] * c_pad).sum(1)
+    s_used = _where(used, tau_pad, torch.zeros_like(tau_pad)).sum(1)
+    trans = torch.exp(-s_used)
+    rgb = rgb + trans[:, None] * bg
+    if cf > 0:
+        f_pad = torch.zeros((nr, smax, cf), dtype=dt).index_put(idx2, feat)
+        fout = (w[..., None] * f_pad).sum(1)
+    else:
+        fout = torch.zeros((nr, 0), dtype=dt)
+    n_used = used.sum(1).numpy()
+    samples = None
+    if keep_samples:
+        samples = {"hit": hs, "k": kk, "u": u, "t": tk, "p": pk, "c": col, "sigma": sig,
+                   "f": feat, "tau": tau, "ray": sray}
+    return _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples)
+
+
+def _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples):
+    g = isx["g"].real.detach()
+    front = (isx["tc"] + isx["eta"]).real.detach() > 0
+    cand = g[front] if front.any() else g.flatten()
+    return {
+        "rgb": rgb, "trans": trans, "feat": fout, "n_used": n_used,
+        "ray_off": ray_off, "prim": pp, "t_c": tc, "eta": eta, "t_a": ta, "t_b": tb,
+        "K": kh, "min_abs_g": float(cand.abs().min()) if cand.numel() else float("inf"),
+        "samples": samples,
+    }

@@ -1,0 +1,510 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine (scipy rotations, numpy polynomial roots, a numpy MLP chain), a closed
+form, an invariant, brute-force marching, or complex-step derivatives.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial.transform import Rotation
+
+import oracle
+import synth
+
+F64 = torch.float64
+
+
+def t64(x):
+    return torch.from_numpy(np.array(x, np.float64))
+
+
+def render_np(scene, o, d, model, opts, **kw):
+    p = oracle.to_tensors(scene)
+    return oracle.render(p["center"], p["scale"], p["quat"], p["mlp"], t64(o), t64(d), model, opts, **kw)
+
+
+def scipy_rot(q_wxyz):
+    q = np.asarray(q_wxyz, np.float64)
+    return Rotation.from_quat(np.stack([q[..., 1], q[..., 2], q[..., 3], q[..., 0]], -1)).as_matrix()
+
+
+def lam(scale, q):
+    r = scipy_rot(q)
+    return r @ np.diag(1.0 / np.asarray(scale, np.float64) ** 2) @ r.T
+
+
+def const_params(model, rgb, sigma):
+    """MLP parameters whose output is constant: every output weight is zero,
+    output bias = (logit(rgb), softplus^-1(sigma), 0...)."""
+    th = np.zeros(model.num_params)
+    dims = model.layer_dims()
+    off = sum(i * o + o for i, o in dims[:-1])
+    fi, fo = dims[-1]
+    off += fi * fo
+    rgb = np.asarray(rgb, np.float64)
+    th[off:off + 3] = np.log(rgb / (1 - rgb))
+    th[off + 3] = math.log(math.expm1(sigma))
+    return th
+
+
+SMALL = oracle.Model(pe_freqs=2, hidden_width=8, hidden_layers=2, out_dim=4)
+
+
+def chord(o, d, mu, scale, q):
+    """Entry/exit of the ray in the ellipsoid from the quadratic
+    (o + t d - mu)^T Lambda (o + t d - mu) = 1, by numpy.roots."""
+    L = lam(scale, q)
+    r = np.asarray(o, np.float64) - np.asarray(mu, np.float64)
+    d = np.asarray(d, np.float64)
+    roots = np.roots([d @ L @ d, 2 * d @ L @ r, r @ L @ r - 1])
+    roots = np.sort(roots.real) if np.all(np.isreal(roots)) else None
+    return roots
+
+
+# ---------------------------------------------------------------- geometry --
+
+def test_rotation_matches_scipy_hamilton():
+    rng = np.random.default_rng(0)
+    q = rng.standard_normal((50, 4)) * rng.uniform(0.2, 3.0, (50, 1))
+    r = oracle.quat_to_rotmat(t64(q)).numpy()
+    np.testing.assert_allclose(r, scipy_rot(q), atol=1e-14)
+    np.testing.assert_allclose(np.linalg.det(r), 1.0, atol=1e-13)
+    np.testing.assert_allclose(r @ np.swapaxes(r, 1, 2), np.broadcast_to(np.eye(3), r.shape), atol=1e-13)
+    np.testing.assert_allclose(oracle.quat_to_rotmat(t64(-q)).numpy(), r, atol=1e-14)
+
+
+def test_local_frame_metric():
+    rng = np.random.default_rng(1)
+    s = rng.uniform(0.05, 0.5, (10, 3))
+    q = rng.standard_normal((10, 4))
+    m = oracle.local_frame(t64(s), t64(q)).numpy()
+    for i in range(10):
+        np.testing.assert_allclose(m[i].T @ m[i], lam(s[i], q[i]), rtol=1e-12, atol=1e-9)
+
+
+def test_contact_depth_is_argmin_of_eq1():
+    """t_c (clamped at 0) minimises |o + t d - mu|^2_Lambda over t >= 0."""
+    from scipy.optimize import minimize_scalar
+    rng = np.random.default_rng(2)
+    for _ in range(40):
+        mu = rng.uniform(-1, 1, 3)
+        s = rng.uniform(0.05, 0.5, 3)
+        q = rng.standard_normal(4)
+        o = rng.standard_normal(3)
+        o = 3 * o / np.linalg.norm(o)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        L = lam(s, q)
+        f = lambda t: (o + t * d - mu) @ L @ (o + t * d - mu)
+        res = minimize_scalar(f, bounds=(0.0, 20.0), method="bounded", options={"xatol": 1e-12})
+        isx = oracle.intersect(t64(o[None]), t64(d[None]), t64(mu[None]), t64(s[None]), t64(q[None]))
+        tc = float(isx["tc"][0, 0])
+        assert abs(max(tc, 0.0) - res.x) < 1e-6
+
+
+def test_chord_matches_quadratic_roots_and_midpoint():
+    rng = np.random.default_rng(3)
+    n_hit = 0
+    for _ in range(300):
+        mu = rng.uniform(-1, 1, 3)
+        s = rng.uniform(0.05, 0.5, 3)
+        q = rng.standard_normal(4)
+        o = rng.standard_normal(3)
+        o = 3 * o / np.linalg.norm(o)
+        d = (mu + rng.uniform(-0.3, 0.3, 3)) - o
+        d /= np.linalg.norm(d)
+        isx = oracle.intersect(t64(o[None]), t64(d[None]), t64(mu[None]), t64(s[None]), t64(q[None]))
+        roots = chord(o, d, mu, s, q)
+        hit = bool(isx["hit"][0, 0])
+        if roots is None or roots[1] <= 0:
+            assert not hit
+            continue
+        assert hit
+        n_hit += 1
+        np.testing.assert_allclose(float(isx["ta"][0, 0]), max(roots[0], 0.0), atol=1e-10)
+        np.testing.assert_allclose(float(isx["tb"][0, 0]), roots[1], atol=1e-10)
+        np.testing.assert_allclose(float(isx["tc"][0, 0]), 0.5 * (roots[0] + roots[1]), atol=1e-10)
+    assert n_hit > 50
+
+
+def test_sphere_through_center_has_chord_2r():
+    r = 0.37
+    o = np.array([[0.0, -3.0, 0.5]])
+    d = np.array([[0.0, 1.0, 0.0]])
+    isx = oracle.intersect(t64(o), t64(d), t64([[0.2 * 0, 0.4, 0.5]]), t64([[r, r, r]]),
+                           t64([[0.3, -0.2, 0.9, 0.1]]))
+    assert abs(float(isx["tb"][0, 0] - isx["ta"][0, 0]) - 2 * r) < 1e-13
+    assert abs(float(isx["tc"][0, 0]) - 3.4) < 1e-13
+
+
+def test_hit_set_matches_bruteforce_marching():
+    """Point-in-ellipsoid marching along each ray brackets [t_a, t_b]."""
+    rng = np.random.default_rng(4)
+    npr, nr = 6, 160
+    mu = rng.uniform(-1, 1, (npr, 3))
+    s = np.exp(rng.uniform(np.log(0.1), np.log(0.5), (npr, 3)))
+    q = rng.standard_normal((npr, 4))
+    eye = np.array([0.3, -3.0, 0.4])
+    tgt = rng.uniform(-1, 1, (nr, 3))
+    d = tgt - eye
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    isx = oracle.intersect(t64(o), t64(d), t64(mu), t64(s), t64(q))
+    h = 2e-4
+    ts = np.arange(0.0, 6.0, h)
+    checked = 0
+    for p in range(npr):
+        L = lam(s[p], q[p])
+        for r in range(nr):
+            x = o[r][None, :] + ts[:, None] * d[r][None, :] - mu[p][None, :]
+            inside = np.einsum("ti,ij,tj->t", x, L, x) <= 1.0
+            hit = bool(isx["hit"][r, p])
+            if inside.sum() >= 3:
+                assert hit
+                t_in, t_out = ts[inside][0], ts[inside][-1]
+                assert abs(t_in - float(isx["ta"][r, p])) <= h
+                assert abs(t_out - float(isx["tb"][r, p])) <= h
+                checked += 1
+            elif inside.sum() == 0 and float(isx["g"][r, p]) < -1e-3:
+                assert not hit
+    assert checked > 30
+
+
+# ------------------------------------------------------------------ network --
+
+def test_mlp_matches_numpy_chain():
+    rng = np.random.default_rng(5)
+    m = oracle.Model(pe_freqs=6, hidden_width=64, hidden_layers=3, out_dim=20)
+    th = rng.standard_normal(m.num_params)
+    x = rng.standard_normal((37, m.in_dim))
+    h = x
+    off = 0
+    dims = m.layer_dims()
+    for li, (fi, fo) in enumerate(dims):
+        w = th[off:off + fi * fo].reshape(fo, fi)
+        b = th[off + fi * fo:off + fi * fo + fo]
+        off += fi * fo + fo
+        h = np.einsum("oi,ni->no", w, h) + b
+        if li < len(dims) - 1:
+            h = np.maximum(h, 0)
+    got = oracle.mlp_apply(t64(th), t64(x), m).numpy()
+    np.testing.assert_allclose(got, h, rtol=1e-12, atol=1e-12)
+
+
+def test_encoding_closed_forms():
+    p = t64([[0.5, 0.25, -1.0]])
+    g = oracle.encode(p, 3).numpy()[0]
+    assert g.shape == (3 + 18,)
+    np.testing.assert_allclose(g[:3], [0.5, 0.25, -1.0])
+    # level 0: sin(pi p), cos(pi p)
+    np.testing.assert_allclose(g[3:6], [1.0, math.sqrt(0.5), 0.0], atol=1e-15)
+    np.testing.assert_allclose(g[6:9], [0.0, math.sqrt(0.5), -1.0], atol=1e-15)
+    # level 1: sin(2 pi p), cos(2 pi p)
+    np.testing.assert_allclose(g[9:12], [0.0, 1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(g[12:15], [-1.0, 0.0, 1.0], atol=1e-15)
+    # doubling identities between consecutive levels on random points
+    rng = np.random.default_rng(6)
+    pr = rng.uniform(-1, 1, (100, 3))
+    ge = oracle.encode(t64(pr), 5).numpy()
+    for lv in range(4):
+        s0, c0 = ge[:, 3 + 6 * lv:6 + 6 * lv], ge[:, 6 + 6 * lv:9 + 6 * lv]
+        s1, c1 = ge[:, 9 + 6 * lv:12 + 6 * lv], ge[:, 12 + 6 * lv:15 + 6 * lv]
+        np.testing.assert_allclose(s1, 2 * s0 * c0, atol=1e-13)
+        np.testing.assert_allclose(c1, c0 ** 2 - s0 ** 2, atol=1e-13)
+
+
+# -------------------------------------------------------------- compositing --
+
+def _one_prim_scene(model, mu, s, q, rgb, sigma):
+    return {"center": np.asarray([mu], np.float64), "scale": np.asarray([s], np.float64),
+            "quat": np.asarray([q], np.float64), "mlp": const_params(model, rgb, sigma)[None]}
+
+
+@pytest.mark.parametrize("K", [1, 7, 32])
+@pytest.mark.parametrize("jitter", [0, 1])
+def test_constant_density_opacity_closed_form(K, jitter):
+    """A constant-density primitive gives opacity 1 - exp(-sigma L) for any K."""
+    rng = np.random.default_rng(7)
+    mu, s, q = [0.1, -0.2, 0.3], [0.3, 0.15, 0.4], rng.standard_normal(4)
+    sc = _one_prim_scene(SMALL, mu, s, q, [0.2, 0.5, 0.9], 3.7)
+    eye = np.array([2.0, -2.5, 0.7])
+    tg = np.asarray(mu) + rng.uniform(-0.2, 0.2, (40, 3))
+    d = tg - eye
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    out = render_np(sc, o, d, SMALL, oracle.Opts(samples_fixed=K, jitter=jitter, jitter_seed=3))
+    for r in range(len(d)):
+        roots = chord(o[r], d[r], mu, s, q)
+        if roots is None or roots[1] <= 0:
+            np.testing.assert_allclose(out["rgb"][r].numpy(), 0.0)
+            continue
+        L = roots[1] - max(roots[0], 0.0)
+        a = 1 - math.exp(-3.7 * L)
+        np.testing.assert_allclose(out["rgb"][r].numpy(), a * np.array([0.2, 0.5, 0.9]), rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(float(out["trans"][r]), 1 - a, rtol=1e-12)
+
+
+def test_two_disjoint_constant_primitives_compose_in_depth_order():
+    m = SMALL
+    c1, c2 = np.array([0.9, 0.1, 0.2]), np.array([0.1, 0.8, 0.3])
+    th = np.stack([const_params(m, c1, 2.0), const_params(m, c2, 5.0)])
+    # primitive 1 is listed second but lies in front of primitive 0
+    sc = {"center": np.array([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0]]),
+          "scale": np.array([[0.3, 0.3, 0.3], [0.2, 0.2, 0.2]]),
+          "quat": np.array([[1.0, 0, 0, 0], [0.7, 0.1, 0.2, 0.3]]), "mlp": th[::-1].copy()}
+    o = np.array([[0.0, -4.0, 0.0]])
+    d = np.array([[0.0, 1.0, 0.0]])
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=5, jitter=1))
+    # front: primitive 1 (radius 0.2) carries th[0] = (c1, sigma 2);
+    # back: primitive 0 (radius 0.3) carries th[1] = (c2, sigma 5)
+    a_front = 1 - math.exp(-2.0 * 0.4)
+    a_back = 1 - math.exp(-5.0 * 0.6)
+    want = a_front * c1 + (1 - a_front) * a_back * c2
+    np.testing.assert_allclose(out["rgb"][0].numpy(), want, rtol=1e-12)
+    assert list(out["prim"]) == [1, 0]
+
+
+def test_misses_give_background_and_unit_transmittance():
+    sc = synth.make_scene(synth.CONFIGS[0])
+    m = oracle.Model(4, 32, 2, 4)
+    o = np.array([[0.0, 0.0, 3.0], [3.0, 0.0, 0.0]])
+    d = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])     # pointing away from the scene
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=8, background=(0.25, 0.5, 0.75)))
+    np.testing.assert_allclose(out["rgb"].numpy(), [[0.25, 0.5, 0.75]] * 2)
+    np.testing.assert_allclose(out["trans"].numpy(), 1.0)
+
+
+def _frame(ci, res=32):
+    cfg = synth.CONFIGS[ci]
+    sc = synth.make_scene(cfg)
+    rng = np.random.default_rng(1000 * ci + 1)
+    cam = synth.make_camera(rng, res, res, cfg.camera_radius)
+    o, d, _ = synth.camera_rays(cam)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    return cfg, sc, o.astype(np.float64), d.astype(np.float64), m
+
+
+def test_white_primitives_give_rgb_equal_one_minus_T():
+    """With every colour 1 the pixel equals sum of weights = 1 - T (Sec. 3.3)."""
+    cfg, sc, o, d, m = _frame(0)
+    rng = np.random.default_rng(9)
+    th = np.stack([const_params(m, [1 - 1e-15] * 3, s) for s in rng.uniform(0.5, 8, cfg.num_prims)])
+    sc = dict(sc, mlp=th)
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=16))
+    rgb, tr = out["rgb"].numpy(), out["trans"].numpy()
+    assert np.all((tr >= 0) & (tr <= 1))
+    np.testing.assert_allclose(rgb, np.repeat(1 - tr[:, None], 3, 1), atol=1e-12)
+
+
+def test_transmittance_monotone_and_weights_bounded():
+    cfg, sc, o, d, m = _frame(1, 48)
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=16, jitter=1), keep_samples=True)
+    smp = out["samples"]
+    tau = smp["tau"].numpy()
+    assert np.all(tau >= 0)
+    ray = smp["ray"]
+    for r in np.unique(ray)[:200]:
+        t = np.exp(-np.cumsum(tau[ray == r]))
+        assert np.all(np.diff(t) <= 1e-15) and np.all((t >= 0) & (t <= 1))
+    assert np.all(out["rgb"].numpy() <= 1 + 1e-12) and np.all(out["rgb"].numpy() >= 0)
+
+
+def test_relabeling_primitives_leaves_image_unchanged():
+    cfg, sc, o, d, m = _frame(1, 40)
+    opts = oracle.Opts(samples_fixed=16, jitter=1, jitter_seed=11, t_stop=1e-4)
+    a = render_np(sc, o, d, m, opts)
+    perm = np.random.default_rng(10).permutation(cfg.num_prims)
+    sc2 = {k: np.asarray(v)[perm] for k, v in sc.items()}
+    b = render_np(sc2, o, d, m, opts)
+    np.testing.assert_allclose(a["rgb"].numpy(), b["rgb"].numpy(), atol=1e-13)
+    np.testing.assert_array_equal(perm[b["prim"]], a["prim"])
+
+
+def test_rigid_motion_of_scene_and_camera_leaves_image_unchanged():
+    cfg, sc, o, d, m = _frame(0, 32)
+    rot = Rotation.from_euler("xyz", [0.3, -1.1, 2.0])
+    tr = np.array([0.4, -0.7, 1.3])
+    qs = sc["quat"].astype(np.float64)
+    qr = (rot * Rotation.from_quat(np.c_[qs[:, 1:], qs[:, :1]])).as_quat()
+    sc2 = dict(sc, center=rot.apply(sc["center"].astype(np.float64)) + tr, quat=np.c_[qr[:, 3:], qr[:, :3]])
+    opts = oracle.Opts(samples_fixed=32, jitter=1, jitter_seed=2)
+    a = render_np(sc, o, d, m, opts)
+    b = render_np(sc2, rot.apply(o) + tr, rot.apply(d), m, opts)
+    np.testing.assert_allclose(a["rgb"].numpy(), b["rgb"].numpy(), atol=1e-11)
+
+
+def test_samples_are_stratified_in_their_bins():
+    cfg, sc, o, d, m = _frame(0, 32)
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=32, jitter=1, jitter_seed=5), keep_samples=True)
+    smp = out["samples"]
+    h, k = smp["hit"], smp["k"]
+    ta, tb = out["t_a"].numpy()[h], out["t_b"].numpy()[h]
+    dl = (tb - ta) / 32
+    t = smp["t"].numpy()
+    assert np.all(t >= ta + k * dl - 1e-12) and np.all(t < ta + (k + 1) * dl + 1e-12)
+    u = smp["u"]
+    assert np.all((u >= 0) & (u < 1)) and np.all(u * 2 ** 24 == np.floor(u * 2 ** 24))
+    hist = np.histogram(u, bins=16, range=(0, 1))[0]
+    e = len(u) / 16
+    assert ((hist - e) ** 2 / e).sum() < 60          # chi2(15) far tail
+
+
+def test_early_termination_stops_after_first_sample_below_threshold():
+    m = SMALL
+    nprim = 12
+    th = np.stack([const_params(m, [0.5, 0.5, 0.5], 40.0) for _ in range(nprim)])
+    sc = {"center": np.c_[np.zeros(nprim), np.linspace(-1.5, 1.5, nprim), np.zeros(nprim)],
+          "scale": np.full((nprim, 3), 0.1), "quat": np.tile([1.0, 0, 0, 0], (nprim, 1)), "mlp": th}
+    o = np.array([[0.0, -4.0, 0.0]])
+    d = np.array([[0.0, 1.0, 0.0]])
+    full = render_np(sc, o, d, m, oracle.Opts(samples_fixed=10, jitter=0))
+    cut = render_np(sc, o, d, m, oracle.Opts(samples_fixed=10, jitter=0, t_stop=1e-4))
+    tau = 40.0 * 0.2 / 10
+    n_exp = int(math.floor(-math.log(1e-4) / tau)) + 1    # first sample with T_after < 1e-4
+    assert int(cut["n_used"][0]) == n_exp
+    assert math.exp(-(n_exp - 1) * tau) >= 1e-4 > math.exp(-n_exp * tau)
+    assert abs(float(cut["trans"][0]) - math.exp(-n_exp * tau)) < 1e-15
+    assert np.all(np.abs(cut["rgb"].numpy() - full["rgb"].numpy()) < 1e-4)
+
+
+def _numpy_field(sc, model, x, p):
+    """Independent density/colour of primitive p at world points x (numpy)."""
+    r = scipy_rot(np.asarray(sc["quat"][p], np.float64))
+    loc = (x - np.asarray(sc["center"][p], np.float64)) @ r / np.asarray(sc["scale"][p], np.float64)
+    feats = [loc]
+    for lv in range(model.pe_freqs):
+        feats += [np.sin(2 ** lv * np.pi * loc), np.cos(2 ** lv * np.pi * loc)]
+    h = np.concatenate(feats, 1)
+    th = np.asarray(sc["mlp"][p], np.float64)
+    off = 0
+    dims = model.layer_dims()
+    for li, (fi, fo) in enumerate(dims):
+        w = th[off:off + fi * fo].reshape(fo, fi)
+        b = th[off + fi * fo:off + fi * fo + fo]
+        off += fi * fo + fo
+        h = h @ w.T + b
+        if li < len(dims) - 1:
+            h = np.maximum(h, 0)
+    return 1 / (1 + np.exp(-h[:, :3])), np.logaddexp(0, h[:, 3])
+
+
+def test_converges_to_dense_marching_on_disjoint_supports():
+    """At large K the oracle agrees with fine uniform marching of the summed
+    field sum_i 1[x in E_i] sigma_i(x) (the continuous operator of the
+    rendering definition; the discrete form converges as the step shrinks)."""
+    m = oracle.Model(pe_freqs=2, hidden_width=16, hidden_layers=2, out_dim=4)
+    rng = np.random.default_rng(12)
+    th = rng.uniform(-0.6, 0.6, (2, m.num_params))
+    sc = {"center": np.array([[0.0, -0.6, 0.0], [0.1, 0.6, 0.05]]),
+          "scale": np.array([[0.35, 0.25, 0.3], [0.3, 0.4, 0.2]]),
+          "quat": rng.standard_normal((2, 4)), "mlp": th}
+    eye = np.array([0.05, -4.0, 0.02])
+    tg = np.c_[rng.uniform(-0.15, 0.15, 12), np.zeros(12), rng.uniform(-0.1, 0.1, 12)]
+    d = tg - eye
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=2048, jitter=0))
+    h = 2.5e-5
+    ts = np.arange(0.0, 6.0, h) + 0.5 * h
+    for r in range(len(d)):
+        x = o[r][None] + ts[:, None] * d[r][None]
+        sig = np.zeros(len(ts))
+        col = np.zeros((len(ts), 3))
+        for p in range(2):
+            rel = x - sc["center"][p]
+            L = lam(sc["scale"][p], sc["quat"][p])
+            inside = np.einsum("ti,ij,tj->t", rel, L, rel) <= 1
+            if inside.any():
+                c, s = _numpy_field(sc, m, x[inside], p)
+                sig[inside] += s
+                col[inside] = c
+        tau = sig * h
+        t_before = np.exp(-np.concatenate([[0.0], np.cumsum(tau)[:-1]]))
+        ref = ((t_before * (1 - np.exp(-tau)))[:, None] * col).sum(0)
+        np.testing.assert_allclose(out["rgb"][r].numpy(), ref, atol=2e-3)
+
+
+def test_discrete_stability_bound_for_perturbed_samples():
+    """|dC| <= max|dc| + 2 max|c| sum|dtau| (discrete form of the rendering
+    operator's stability lemma), checked on a perturbed network."""
+    cfg, sc, o, d, m = _frame(1, 32)
+    opts = oracle.Opts(samples_fixed=16, jitter=1)
+    a = render_np(sc, o, d, m, opts, keep_samples=True)
+    rng = np.random.default_rng(13)
+    sc2 = dict(sc, mlp=sc["mlp"] + 1e-3 * rng.standard_normal(sc["mlp"].shape).astype(np.float32))
+    b = render_np(sc2, o, d, m, opts, keep_samples=True)
+    sa, sb = a["samples"], b["samples"]
+    dc = np.abs(sa["c"].numpy() - sb["c"].numpy()).max(1)
+    dt = np.abs(sa["tau"].numpy() - sb["tau"].numpy())
+    for r in np.unique(sa["ray"]):
+        sel = sa["ray"] == r
+        bound = dc[sel].max() + 2 * dt[sel].sum()
+        assert np.abs(a["rgb"][r].numpy() - b["rgb"][r].numpy()).max() <= bound + 1e-15
+
+
+# ---------------------------------------------------------------- gradients --
+
+def _grad_case():
+    cfg = synth.CONFIGS[0]
+    sc = synth.make_scene(cfg)
+    keep = [0, 3, 5]
+    sc = {k: np.asarray(v, np.float64)[keep] for k, v in sc.items()}
+    sc["mlp"] *= 1.3
+    rng = np.random.default_rng(1)
+    cam = synth.make_camera(rng, 24, 24, 3.0)
+    o, d, _ = synth.camera_rays(cam)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    opts = oracle.Opts(samples_fixed=8, jitter=1, jitter_seed=4, t_stop=1e-3)
+    w = np.random.default_rng(2).standard_normal((len(o), 3))
+    return sc, o.astype(np.float64), d.astype(np.float64), m, opts, w
+
+
+def test_autograd_matches_complex_step():
+    sc, o, d, m, opts, w = _grad_case()
+    _, _, _, g, _ = oracle.loss_and_grads(sc, o, d, m, opts, grad_rgb=w)
+    rng = np.random.default_rng(3)
+    picks = [("center", (i, j)) for i in range(3) for j in range(3)]
+    picks += [("scale", (i, j)) for i in range(3) for j in range(3)]
+    picks += [("quat", (i, j)) for i in range(3) for j in range(4)]
+    picks += [("mlp", (i, int(j))) for i in range(3) for j in rng.choice(m.num_params, 8, replace=False)]
+    nz = 0
+    for key, idx in picks:
+        cs = oracle.complex_step(sc, o, d, m, opts, key, idx, w)
+        ad = float(g[key][idx])
+        assert abs(cs - ad) <= 1e-9 * max(1.0, abs(cs)), (key, idx, cs, ad)
+        nz += abs(cs) > 1e-8
+    assert nz > 30
+
+
+def test_central_differences_agree_with_autograd():
+    # without the termination cut, so that the step does not move a discrete
+    # decision (complex step above covers the cut)
+    sc, o, d, m, opts, w = _grad_case()
+    opts = oracle.Opts(samples_fixed=opts.samples_fixed, jitter=1, jitter_seed=4)
+    _, _, _, g, _ = oracle.loss_and_grads(sc, o, d, m, opts, grad_rgb=w)
+    def L(s2):
+        out = render_np(s2, o, d, m, opts)
+        return float((out["rgb"].numpy() * w).sum())
+    for key, idx in [("center", (0, 1)), ("scale", (1, 2)), ("quat", (2, 0)), ("mlp", (0, 5)),
+                     ("mlp", (1, 1500)), ("mlp", (2, m.num_params - 1))]:
+        h = 1e-7      # a near-grazing ray makes the truncation term large at 1e-6
+        sp = {k: v.copy() for k, v in sc.items()}
+        sm = {k: v.copy() for k, v in sc.items()}
+        sp[key][idx] += h
+        sm[key][idx] -= h
+        fd = (L(sp) - L(sm)) / (2 * h)
+        assert abs(fd - g[key][idx]) <= 1e-5 * max(1.0, abs(fd)), (key, idx, fd, g[key][idx])
+
+
+def test_quaternion_gradient_is_orthogonal_to_q_and_missed_primitive_gets_zero():
+    sc, o, d, m, opts, w = _grad_case()
+    sc["center"][2] = [40.0, 40.0, 40.0]          # out of every ray's reach
+    _, _, _, g, _ = oracle.loss_and_grads(sc, o, d, m, opts, grad_rgb=w)
+    for i in range(3):
+        assert abs(g["quat"][i] @ sc["quat"][i]) < 1e-12 * max(1, np.abs(g["quat"][i]).max())
+    for k in ("center", "scale", "quat", "mlp"):
+        assert np.all(g[k][2] == 0)
+    assert np.abs(g["mlp"][0]).max() > 0
