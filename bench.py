@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Throughput of the MLP-Splatting render path on one MI355X.
+
+One step = the whole hot path over one 800x800 frame of the 64-primitive
+scene (39-64-64-64-4 networks, 64 stratified samples per hit, early
+termination at T < 1e-4): ray binning and depth sort, grouped per-primitive
+networks with hit-local compositing, per-ray compositing, the MSE loss
+against a target frame rendered from a second seeded scene, and the backward
+pass to every primitive parameter through the autograd Function.
+
+Prints ONE JSON line.  `value` is forward+backward rays/s in the BF16 matrix-
+core form; the FP32 form, forward-only rates, the error against the FP64
+oracle on sampled rays, per-kernel times from HIP events recorded on the
+launch stream, the dominant kernel's roofline and the oracle's CPU rate are
+reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rays/s fwd and fwd+bwd, bf16-MFMA vs fp32 plain, at ≤2e-3 RGB err vs FP64"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}     # MI355X dense matrix-core peaks
+HBM_PEAK_GBS = 8000.0
+
+
+def mlp_flops_per_sample(cfg) -> int:
+    import synth
+    return sum(2 * i * o for i, o in synth.layer_dims(cfg))
+
+
+def setup(cfg, precision, t_stop=None):
+    import torch
+    import synth
+    from paper_2606_03877_amd import NetSpec, RenderOpts, Renderer
+    spec = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim, precision)
+    opts = RenderOpts(samples_fixed=cfg.samples_fixed, samples_min=cfg.samples_min,
+                      samples_max=cfg.samples_max, samples_per_unit=cfg.samples_per_unit,
+                      t_stop=cfg.t_stop if t_stop is None else t_stop, jitter=cfg.jitter, jitter_seed=7)
+    return Renderer(spec, opts), opts
+
+
+def device_inputs(cfg):
+    import torch
+    import synth
+    sc = synth.make_scene(cfg)
+    o, d, _ = synth.make_rays(cfg)
+    dev = torch.device("cuda", 0)
+    prm = {k: torch.from_numpy(v).to(dev) for k, v in sc.items()}
+    return sc, o, d, prm, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+
+
+def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True):
+    """Time fwd+bwd training steps and forward-only renders of one precision."""
+    import torch
+    from paper_2606_03877_amd import render, msplat_profile_enable, msplat_profile_read
+    r, opts = setup(cfg, precision)
+    leaf = {k: v.clone().requires_grad_(True) for k, v in prm.items()}
+
+    def step():
+        for v in leaf.values():
+            v.grad = None
+        rgb, trans, feat = render(r, leaf["center"], leaf["scale"], leaf["quat"], leaf["mlp"], ro, rd)
+        loss = ((rgb - target) ** 2).mean()
+        loss.backward()
+        return loss
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if profile:
+        msplat_profile_enable(r.ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = msplat_profile_read(r.ctx) if profile else {}
+    if profile:
+        msplat_profile_enable(r.ctx, False)
+    # forward only
+    with torch.no_grad():
+        for _ in range(max(1, warmup)):
+            r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(steps):
+            rgb, trans, feat, ws = r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+    stats = r.stats(ws)
+    R = ro.shape[0]
+    return {
+        "fwdbwd_ms": 1e3 * (t1 - t0) / steps,
+        "fwd_ms": 1e3 * (f1 - f0) / steps,
+        "fwdbwd_rays_per_s": R * steps / (t1 - t0),
+        "fwd_rays_per_s": R * steps / (f1 - f0),
+        "stages": stages,
+        "stats": stats,
+        "rgb": rgb,
+    }
+
+
+def oracle_check(cfg, sc, o, d, rgb_gpu, opts, n=256, seed=11):
+    """Max |rgb - rgb_fp64| over n seeded rays (the oracle renders them)."""
+    import torch
+    import oracle
+    idx = np.sort(np.random.default_rng(seed).choice(len(o), n, replace=False))
+    p = oracle.to_tensors(sc)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    oo = oracle.Opts(samples_fixed=opts.samples_fixed, samples_min=opts.samples_min,
+                     samples_max=opts.samples_max, samples_per_unit=opts.samples_per_unit,
+                     t_stop=opts.t_stop, jitter=opts.jitter, jitter_seed=opts.jitter_seed)
+    out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"],
+                        torch.from_numpy(o[idx].astype(np.float64)),
+                        torch.from_numpy(d[idx].astype(np.float64)), m, oo, ray_ids=idx)
+    g = rgb_gpu.detach().cpu().numpy()[idx]
+    return float(np.abs(g - out["rgb"].numpy()).max())
+
+
+def cpu_baseline(cfg, sc, o, d, target, opts, budget_s=12.0, chunk=2048, seed=5):
+    """The FP64 oracle's forward+backward rate on host cores over a bounded
+    seeded sample of the same rays (chunks until the time budget is spent)."""
+    import torch
+    import oracle
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    oo = oracle.Opts(samples_fixed=opts.samples_fixed, samples_min=opts.samples_min,
+                     samples_max=opts.samples_max, samples_per_unit=opts.samples_per_unit,
+                     t_stop=opts.t_stop, jitter=opts.jitter, jitter_seed=opts.jitter_seed)
+    order = np.random.default_rng(seed).permutation(len(o))
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < len(o):
+        idx = np.sort(order[done:done + chunk])
+        oracle.loss_and_grads(sc, o[idx].astype(np.float64), d[idx].astype(np.float64), m, oo,
+                              target_rgb=target[idx].astype(np.float64), chunk=chunk, ray_ids=idx)
+        done += len(idx)
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "rays/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{done} seeded rays of the same frame in chunks of {chunk}, forward+backward "
+                      f"(autograd FP64), {dt:.1f} s"}
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch from a committed counter summary, if one matches."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        e = rec.get(workload, {}).get(kernel)
+        return None if e is None else float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    cfg = synth.CONFIGS[args.config]
+    sc, o, d, prm, ro, rd = device_inputs(cfg)
+    R = len(o)
+    # target frame: a second, independently seeded scene of the same law
+    r_t, _ = setup(cfg, "fp32")
+    sc_t = synth.make_scene(cfg, seed=1000 * cfg.idx + 10)
+    pt = {k: torch.from_numpy(v).cuda() for k, v in sc_t.items()}
+    with torch.no_grad():
+        target, _, _, _ = r_t.forward(pt["center"], pt["scale"], pt["quat"], pt["mlp"], ro, rd)
+    torch.cuda.synchronize()
+    print(f"# config {cfg.idx} {cfg.name}: {R} rays, {cfg.num_prims} primitives", file=sys.stderr, flush=True)
+
+    legs = {}
+    legs["bf16"] = run_leg(cfg, "bf16", prm, ro, rd, target, args.steps, args.warmup)
+    print(f"# bf16 fwd+bwd {legs['bf16']['fwdbwd_ms']:.3f} ms fwd {legs['bf16']['fwd_ms']:.3f} ms",
+          file=sys.stderr, flush=True)
+    if not args.no_fp32:
+        legs["fp32"] = run_leg(cfg, "fp32", prm, ro, rd, target, max(3, args.steps // 4), 1)
+        print(f"# fp32 fwd+bwd {legs['fp32']['fwdbwd_ms']:.3f} ms fwd {legs['fp32']['fwd_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+
+    _, opts = setup(cfg, "bf16")
+    errs = {k: oracle_check(cfg, sc, o, d, v["rgb"], opts) for k, v in legs.items()}
+
+    # dominant kernel of the bf16 step and its roofline
+    b = legs["bf16"]
+    st = b["stats"]
+    fps = mlp_flops_per_sample(cfg)
+    stages = {k: v for k, v in b["stages"].items() if v[1] > 0}
+    dom = max(stages, key=lambda k: stages[k][0])
+    avg_ms = stages[dom][0] / stages[dom][1]
+    flops = {"mlp_forward": fps * st["num_samples"], "mlp_backward": 2 * fps * st["num_samples"]}
+    if dom in flops:
+        achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16"],
+                "traffic": traffic_from_profiles(dom, f"config{cfg.idx}"),
+                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops[dom]}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, sc, o, d, target.cpu().numpy(), opts, budget_s=args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": b["fwdbwd_rays_per_s"],
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": b["fwdbwd_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded scene, 800x800 pinhole frame, target frame from a second seeded scene)",
+        "config": {"workload": f"config{cfg.idx}-{cfg.name}: {cfg.views[0][0]}x{cfg.views[0][1]} frame, "
+                               f"{cfg.num_prims} primitives, {cfg.in_dim}-{cfg.hidden_width}x{cfg.hidden_layers}-"
+                               f"{cfg.out_dim} MLPs, K={cfg.samples_fixed}, T_stop={cfg.t_stop}",
+                   "rays": R, "hits": int(st["num_hits"]), "samples": int(st["num_samples"]),
+                   "terminated_rays": int(st["num_terminated"]), "mlp_precision": "bf16 operands, fp32 accumulate"},
+        "fwd_rays_per_s": b["fwd_rays_per_s"],
+        "fwdbwd_rays_per_s": b["fwdbwd_rays_per_s"],
+        "rgb_max_err_vs_fp64": errs,
+        "roofline": roof,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "cpu_baseline": cpu,
+    }
+    if "fp32" in legs:
+        f = legs["fp32"]
+        out["fp32"] = {"fwd_rays_per_s": f["fwd_rays_per_s"], "fwdbwd_rays_per_s": f["fwdbwd_rays_per_s"],
+                       "ms_per_step": f["fwdbwd_ms"]}
+        out["bf16_speedup"] = {"fwd": b["fwd_rays_per_s"] / f["fwd_rays_per_s"],
+                               "fwdbwd": b["fwdbwd_rays_per_s"] / f["fwdbwd_rays_per_s"]}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

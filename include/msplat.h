@@ -1,0 +1,199 @@
+/*
+ * msplat.h -- C ABI of the MLP-Splatting render path on AMD MI355X (gfx950).
+ *
+ * The library renders camera rays against a set of neural primitives
+ * (Sec. 3 of "MLP Splatting: Object-Centric Neural Fields"): every ray is
+ * intersected with each primitive's ellipsoidal support, the hits are sorted by
+ * contact depth, each primitive's own MLP is evaluated at stratified samples of
+ * its hit interval, and the samples are composited front to back with early
+ * termination.  The backward pass returns the gradients of a scalar loss with
+ * respect to every primitive parameter.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers owned by the caller, dense, row-major,
+ *     float32 unless stated.  The library never allocates device memory and
+ *     never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *     it; a call returns once its work is enqueued, except that
+ *     msplat_render_forward synchronises `stream` once (to size its launches)
+ *     and msplat_get_stats / msplat_debug_hits synchronise before returning.
+ *   - Every entry point returns an msplat_status; arguments are validated on
+ *     the host before anything is enqueued.  NaN or non-positive scales in the
+ *     data are not checked on the device; NaN propagates to the outputs.
+ *   - Calls that share a workspace must be serialised by the caller.
+ */
+#ifndef MSPLAT_H
+#define MSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum msplat_status {
+  MSPLAT_OK = 0,
+  MSPLAT_E_INVALID = 1,     /* null pointer, bad size or option (host check) */
+  MSPLAT_E_CAPACITY = 2,    /* workspace too small; *need_bytes tells how much */
+  MSPLAT_E_UNSUPPORTED = 3, /* network shape or precision that is not compiled */
+  MSPLAT_E_HIP = 4,         /* a HIP runtime call failed */
+  MSPLAT_E_STATE = 5        /* backward or debug call without a matching forward */
+} msplat_status;
+
+typedef enum msplat_precision {
+  MSPLAT_FP32 = 0, /* MLP products and sums in float32 (matrix cores, f32 operands) */
+  MSPLAT_BF16 = 1  /* MLP operands in bfloat16 on the matrix cores, float32 accumulation */
+} msplat_precision;
+
+/*
+ * Per-primitive network (Sec. 3.2).  The input of a sample is its local
+ * position p (the scale-normalised ellipsoid frame) encoded as
+ * [p, sin(2^l pi p), cos(2^l pi p) for l < pe_freqs]: 3 + 6*pe_freqs values.
+ * Hidden layers use ReLU; outputs are RGB (sigmoid), density (softplus) and
+ * out_dim-4 feature channels (identity), composited like RGB.
+ * Compiled shapes (pe_freqs, hidden_width, hidden_layers, out_dim):
+ *   (4, 32, 2, 4), (6, 64, 3, 4), (6, 64, 3, 20).  Others: MSPLAT_E_UNSUPPORTED.
+ */
+typedef struct msplat_model {
+  int32_t num_prims;     /* P >= 1 */
+  int32_t pe_freqs;      /* L */
+  int32_t hidden_width;
+  int32_t hidden_layers;
+  int32_t out_dim;       /* 4 (RGB + density) or 4 + feature channels */
+  int32_t precision;     /* msplat_precision */
+} msplat_model;
+
+/* Sampling and compositing options (Sec. 3.3). */
+typedef struct msplat_opts {
+  int32_t samples_fixed;    /* K samples per hit; 0 = ceil(samples_per_unit * chord)
+                               clamped to [samples_min, samples_max] */
+  int32_t samples_min;
+  int32_t samples_max;      /* <= 128 */
+  float samples_per_unit;
+  float t_stop;             /* stop after the first sample with transmittance
+                               below t_stop; 0 disables early termination */
+  int32_t jitter;           /* 0: bin midpoints; 1: hashed stratified offsets */
+  uint32_t jitter_seed;
+  float background[3];      /* added as T_final * background */
+} msplat_opts;
+
+/* Counters filled by the forward pass (read with msplat_get_stats). */
+typedef struct msplat_stats {
+  int64_t num_rays;
+  int64_t num_hits;           /* ray/primitive intersections */
+  int64_t num_samples;        /* network evaluations scheduled */
+  int64_t num_work_items;     /* primitive-grouped launches of the MLP kernel */
+  int64_t num_terminated;     /* rays that stopped early */
+  int64_t num_fallbacks;      /* hit tests decided in double-float arithmetic */
+  float min_abs_g;            /* smallest |1 - |p_c|^2| seen among tested pairs */
+  float reserved;
+} msplat_stats;
+
+typedef struct msplat_ctx msplat_ctx;
+
+/* Create a context bound to HIP device `device` (it becomes current on the
+ * calling thread while the library works).  *out receives the handle. */
+int msplat_create(int device, msplat_ctx** out);
+/* Destroy a context (NULL is a no-op). */
+void msplat_destroy(msplat_ctx* ctx);
+/* Static English text for a status code. */
+const char* msplat_status_string(int status);
+
+/* Number of float32 weights per primitive for the model (layout per layer:
+ * W[out][in] row-major, then b[out]); 0 if the shape is invalid. */
+int64_t msplat_num_params(const msplat_model* model);
+
+/*
+ * Workspace bytes needed for `num_rays` rays producing at most `max_hits`
+ * ray/primitive hits.  The workspace holds the hit lists, per-hit partial
+ * colours and everything the backward pass reads; it must stay untouched
+ * between a forward call and the backward call that uses it.
+ */
+int msplat_workspace_size(const msplat_model* model, int64_t num_rays, int64_t max_hits,
+                          uint64_t* bytes);
+
+/*
+ * Forward render (Sec. 3.2-3.3).
+ *   center [P,3], scale [P,3] (semi-axes, > 0), quat [P,4] (w,x,y,z, any
+ *   non-zero norm), mlp [P, num_params]; ray_o [R,3], ray_d [R,3] (unit).
+ *   Rays are best given in coherent groups of 64 (e.g. 8x8 pixel tiles);
+ *   any order is correct.
+ * Outputs: rgb [R,3], trans [R] (final transmittance), feat [R, out_dim-4]
+ *   (may be NULL when out_dim == 4).
+ * The workspace `ws` (ws_bytes, 256-byte aligned) is written.  If it is too
+ * small for the hits found, returns MSPLAT_E_CAPACITY with *need_bytes set and
+ * outputs untouched; the caller grows the workspace and calls again.
+ * need_bytes may be NULL.
+ */
+int msplat_render_forward(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                          const float* center, const float* scale, const float* quat,
+                          const float* mlp, const float* ray_o, const float* ray_d,
+                          int64_t num_rays, float* rgb, float* trans, float* feat,
+                          void* ws, uint64_t ws_bytes, uint64_t* need_bytes, void* stream);
+
+/*
+ * Backward of the forward call that last wrote `ws` with the same arguments.
+ * grad_rgb [R,3] = dL/drgb, grad_trans [R] = dL/dtrans (NULL = zero),
+ * grad_feat [R,out_dim-4] (NULL = zero).
+ * Outputs (overwritten, not accumulated): g_center [P,3], g_scale [P,3],
+ * g_quat [P,4], g_mlp [P,num_params].  Hit sets, depth order, sample counts,
+ * sample offsets and the termination cut are held fixed.  The recomputed
+ * network activations are not stored.  Weight gradients are accumulated with
+ * atomics, so their low bits may differ between runs.
+ */
+int msplat_render_backward(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                           const float* center, const float* scale, const float* quat,
+                           const float* mlp, const float* ray_o, const float* ray_d,
+                           int64_t num_rays, const float* grad_rgb, const float* grad_trans,
+                           const float* grad_feat, void* ws, uint64_t ws_bytes, float* g_center,
+                           float* g_scale,
+                           float* g_quat, float* g_mlp, void* stream);
+
+/*
+ * Per-stage timing (instrumentation; not part of the rendering method).
+ * When enabled, every kernel launch of the context is bracketed by a pair of
+ * HIP events recorded on the launch's own stream.  Enabling (or disabling)
+ * resets the totals.  msplat_profile_read waits for the recorded events and
+ * returns, per stage, a static name, the summed GPU time in milliseconds and
+ * the number of timed launches; *num_stages receives the stage count, and
+ * at most max_stages entries of each non-NULL array are written.
+ */
+int msplat_profile_enable(msplat_ctx* ctx, int enable);
+int msplat_profile_read(msplat_ctx* ctx, int max_stages, const char** names, double* total_ms,
+                        int64_t* launches, int* num_stages);
+
+/* Counters of the last forward that used `ws` (synchronises `stream`). */
+int msplat_get_stats(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, msplat_stats* out,
+                     void* stream);
+
+/*
+ * Depth-sorted hit lists of the last forward that used `ws`, copied to HOST
+ * memory (synchronises `stream`): ray_off [R+1] (int64, prefix offsets),
+ * prim [num_hits] (int32, primitive of each hit in per-ray depth order),
+ * t_c [num_hits] (float64, contact depth, double-float accurate),
+ * n_used [num_hits] (int32, samples composited per hit).  Capacities are
+ * given in elements; MSPLAT_E_CAPACITY if num_hits exceeds them.
+ */
+int msplat_debug_hits(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, int64_t num_rays,
+                      int64_t* ray_off, int32_t* prim, double* t_c, int32_t* n_used,
+                      int64_t capacity, void* stream);
+
+/*
+ * Float64 forward of the same render (finite-difference gradient checker
+ * only; not a product path).  Same arguments as msplat_render_forward with
+ * float64 inputs and outputs; the workspace is sized by
+ * msplat_workspace_size for the same num_rays and hit count.  The network is
+ * evaluated in float64 on the vector units.
+ */
+int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                              const double* center, const double* scale, const double* quat,
+                              const double* mlp, const double* ray_o, const double* ray_d,
+                              int64_t num_rays, double* rgb, double* trans, double* feat,
+                              void* ws, uint64_t ws_bytes, uint64_t* need_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSPLAT_H */

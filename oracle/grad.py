@@ -28,7 +28,8 @@ def to_tensors(scene: dict, dtype=torch.float64, requires_grad=False) -> dict:
 
 
 def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
-                   grad_rgb=None, grad_feat=None, target_rgb=None, chunk: int = 4096):
+                   grad_rgb=None, grad_feat=None, target_rgb=None, chunk: int = 4096,
+                   grad_trans=None, ray_ids=None):
     """Vector-Jacobian product of the render with upstream gradients.
 
     Either ``grad_rgb`` ([R,3], optionally ``grad_feat``) is given, giving
@@ -46,7 +47,8 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
     for s in range(0, nr, chunk):
         e = min(nr, s + chunk)
         out = render(prm["center"], prm["scale"], prm["quat"], prm["mlp"], o[s:e], d[s:e],
-                     model, opts, ray_index_base=s)
+                     model, opts, ray_index_base=s,
+                     ray_ids=None if ray_ids is None else ray_ids[s:e])
         if target_rgb is not None:
             tgt = torch.from_numpy(np.asarray(target_rgb[s:e], np.float64))
             loss = ((out["rgb"] - tgt) ** 2).sum() / (3.0 * nr)
@@ -56,6 +58,9 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
             if grad_feat is not None and out["feat"].shape[1] > 0:
                 gf = torch.from_numpy(np.asarray(grad_feat[s:e], np.float64))
                 loss = loss + (out["feat"] * gf).sum()
+            if grad_trans is not None:
+                gt = torch.from_numpy(np.asarray(grad_trans[s:e], np.float64))
+                loss = loss + (out["trans"] * gt).sum()
         if loss.requires_grad:
             loss.backward()
         loss_total += float(loss.detach())

@@ -159,13 +159,14 @@ def _softplus(o):
 
 
 def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
-           ray_index_base: int = 0, keep_samples: bool = False) -> dict:
+           ray_index_base: int = 0, keep_samples: bool = False, ray_ids=None) -> dict:
     """Render every ray (Sec. 3.3 front-to-back compositing over the depth-
     sorted hits, each hit sampled at K stratified points of its chord).
 
     Parameters are float64 (or complex128) tensors; rays are float64.
     ``ray_index_base`` offsets the ray index fed to the sample-offset hash, so a
-    subset of a batch can be rendered with the batch's own offsets.
+    subset of a batch can be rendered with the batch's own offsets; ``ray_ids``
+    (one index per ray) overrides it for scattered subsets.
     """
     dt = center.dtype
     nr = ray_o.shape[0]
@@ -206,7 +207,9 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     hoff[1:] = np.cumsum(kh)
     kk = np.arange(len(hs)) - hoff[hs]
     if opts.jitter:
-        u = sample_offsets(opts.jitter_seed, rr[hs] + ray_index_base, rank[hs], kk)
+        gid = (np.asarray(ray_ids, np.int64)[rr[hs]] if ray_ids is not None
+               else rr[hs] + ray_index_base)
+        u = sample_offsets(opts.jitter_seed, gid, rank[hs], kk)
     else:
         u = np.full(len(hs), 0.5)
     hs_t = torch.from_numpy(hs)

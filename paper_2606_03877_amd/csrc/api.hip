@@ -1,0 +1,477 @@
+// C ABI of the msplat library: argument checks, workspace layout and the
+// launch sequence of the forward and backward passes.
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+
+using namespace msplat;
+
+// Optional per-stage timing with HIP events recorded on the caller's stream
+// around each launch; pairs are harvested when read (or when a ring fills).
+enum Stage {
+  ST_ZERO, ST_PREPROCESS, ST_PACK, ST_BIN_COUNT, ST_SCAN, ST_BIN_FILL, ST_MLP_FWD, ST_COMPOSITE,
+  ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_GEO_FINAL, ST_COUNT
+};
+static const char* kStageNames[ST_COUNT] = {
+    "zero", "preprocess", "pack_weights", "bin_count", "scan", "bin_fill", "mlp_forward",
+    "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "geo_finalize"};
+constexpr int kRing = 64;
+struct StageTimer {
+  hipEvent_t a[kRing], b[kRing];
+  int head = 0, pending = 0;
+  double total_ms = 0.0;
+  int64_t count = 0;
+  bool created = false;
+};
+
+struct msplat_ctx {
+  int device;
+  bool profiling = false;
+  StageTimer timers[ST_COUNT];
+  DevCounters* host_ctr;   // pinned host mirror of the device counters
+  // record of the last successful forward (used to size the backward launch)
+  const void* last_ws;
+  int64_t last_items;
+  int64_t last_hits;
+  int64_t last_rays;
+  uint64_t last_bytes;
+  NetShape last_shape;
+};
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool shape_of(const msplat_model* m, NetShape* n) {
+  if (!m) return false;
+  n->P = m->num_prims;
+  n->L = m->pe_freqs;
+  n->W = m->hidden_width;
+  n->D = m->hidden_layers;
+  n->NOUT = m->out_dim;
+  n->prec = m->precision;
+  if (n->P < 1 || n->L < 1 || n->W < 1 || n->D < 1 || n->NOUT < 4 || n->NOUT > 20) return false;
+  if (n->prec != MSPLAT_FP32 && n->prec != MSPLAT_BF16) return false;
+  int64_t in = 3 + 6 * n->L, np = 0, prev = in;
+  for (int j = 0; j < n->D; ++j) {
+    np += prev * n->W + n->W;
+    prev = n->W;
+  }
+  np += prev * n->NOUT + n->NOUT;
+  n->n_params = (int)np;
+  return true;
+}
+
+// Lay out the workspace at `base` (may be null to measure).  Returns the bytes
+// used for hit capacity `hcap`.
+uint64_t layout(const NetShape& n, int64_t R, int64_t hcap, uint8_t* base, Workspace* w) {
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o = off;
+    off = align_up(off + bytes);
+    return base ? base + o : nullptr;
+  };
+  Workspace ws{};
+  int P = n.P;
+  ws.counters = (DevCounters*)take(sizeof(DevCounters));
+  ws.geo = (float*)take((uint64_t)P * kGeoStride * 4);
+  ws.wpack_bytes = mlp_wpack_bytes(n);
+  ws.wpack = (uint8_t*)take((uint64_t)P * ws.wpack_bytes);
+  ws.prim_nhit = (int32_t*)take((uint64_t)P * 4);
+  ws.prim_off = (int32_t*)take((uint64_t)(P + 1) * 4);
+  ws.prim_cursor = (int32_t*)take((uint64_t)P * 4);
+  ws.wi_off = (int32_t*)take((uint64_t)(P + 1) * 4);
+  ws.geo_grad = (float*)take((uint64_t)P * 12 * 4);
+  ws.ray_off = (int32_t*)take((uint64_t)(R + 1) * 4);
+  int64_t nb = (R + 1023) / 1024;
+  ws.scan_tmp = (int32_t*)take((uint64_t)(nb + 1) * 4);
+  ws.ray_tf = (float*)take((uint64_t)R * 4);
+  int nc = n.NOUT - 1;
+  uint64_t H = (uint64_t)hcap;
+  ws.hit_prim = (int32_t*)take(H * 4);
+  ws.hit_ray = (int32_t*)take(H * 4);
+  ws.hit_k = (int32_t*)take(H * 4);
+  ws.hit_nused = (int32_t*)take(H * 4);
+  ws.hit_tc_hi = (float*)take(H * 4);
+  ws.hit_tc_lo = (float*)take(H * 4);
+  ws.hit_eta = (float*)take(H * 4);
+  ws.hit_sa = (float*)take(H * 4);
+  ws.hit_dlt = (float*)take(H * 4);
+  ws.hit_pc = (float*)take(H * 12);
+  ws.hit_e = (float*)take(H * 12);
+  ws.hit_tau = (float*)take(H * 4);
+  ws.hit_cloc = (float*)take(H * 4 * nc);
+  ws.hit_sb_hi = (float*)take(H * 4);
+  ws.hit_sb_lo = (float*)take(H * 4);
+  ws.hit_gsa = (float*)take(H * 4);
+  ws.hit_tb = (float*)take(H * 4);
+  ws.hit_gtot = (float*)take(H * 4);
+  ws.phit = (int32_t*)take(H * 4);
+  ws.num_rays = R;
+  ws.hit_cap = hcap;
+  ws.nc = nc;
+  if (w) *w = ws;
+  return off;
+}
+
+// bytes per hit and fixed bytes (for capacity from a given size)
+void size_model(const NetShape& n, int64_t R, uint64_t* fixed, uint64_t* per_hit) {
+  uint64_t a = layout(n, R, 0, nullptr, nullptr);
+  uint64_t b = layout(n, R, 1 << 20, nullptr, nullptr);
+  *fixed = a;
+  *per_hit = (b - a + (1 << 20) - 1) >> 20;
+}
+
+int64_t capacity_of(const NetShape& n, int64_t R, uint64_t bytes) {
+  uint64_t fixed, ph;
+  size_model(n, R, &fixed, &ph);
+  if (bytes <= fixed + 32 * kAlign) return 0;
+  int64_t h = (int64_t)((bytes - fixed - 32 * kAlign) / ph);
+  while (h > 0 && layout(n, R, h, nullptr, nullptr) > bytes) h -= 1 + h / 1000;
+  return h;
+}
+
+#define HIPCHK(expr)                       \
+  do {                                     \
+    hipError_t e_ = (expr);                \
+    if (e_ != hipSuccess) return MSPLAT_E_HIP; \
+  } while (0)
+
+hipError_t harvest_one(StageTimer& t) {
+  int idx = (t.head - t.pending + kRing) % kRing;
+  hipError_t e = hipEventSynchronize(t.b[idx]);
+  if (e != hipSuccess) return e;
+  float ms = 0.f;
+  e = hipEventElapsedTime(&ms, t.a[idx], t.b[idx]);
+  if (e != hipSuccess) return e;
+  t.total_ms += ms;
+  t.count += 1;
+  t.pending -= 1;
+  return hipSuccess;
+}
+
+hipError_t stage_begin(msplat_ctx* c, int id, hipStream_t s) {
+  if (!c->profiling) return hipSuccess;
+  StageTimer& t = c->timers[id];
+  if (!t.created) {
+    for (int i = 0; i < kRing; ++i) {
+      if (hipEventCreate(&t.a[i]) != hipSuccess || hipEventCreate(&t.b[i]) != hipSuccess)
+        return hipErrorOutOfMemory;
+    }
+    t.created = true;
+  }
+  if (t.pending == kRing) {
+    hipError_t e = harvest_one(t);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(t.a[t.head], s);
+}
+
+hipError_t stage_end(msplat_ctx* c, int id, hipStream_t s) {
+  if (!c->profiling) return hipSuccess;
+  StageTimer& t = c->timers[id];
+  hipError_t e = hipEventRecord(t.b[t.head], s);
+  t.head = (t.head + 1) % kRing;
+  t.pending += 1;
+  return e;
+}
+
+// launch `call` as stage `id` (timed when profiling is on)
+#define STAGE(ctx, id, s, call)           \
+  do {                                    \
+    HIPCHK(stage_begin(ctx, id, s));      \
+    HIPCHK(call);                         \
+    HIPCHK(stage_end(ctx, id, s));        \
+  } while (0)
+
+bool opts_ok(const msplat_opts* o) {
+  if (!o) return false;
+  if (o->samples_fixed < 0 || o->samples_fixed > kMaxSamplesPerHit) return false;
+  if (o->samples_fixed == 0) {
+    if (o->samples_min < 1 || o->samples_max > kMaxSamplesPerHit || o->samples_min > o->samples_max)
+      return false;
+    if (!(o->samples_per_unit > 0.f)) return false;
+  }
+  if (!(o->t_stop >= 0.f && o->t_stop < 1.f)) return false;
+  return true;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char* msplat_status_string(int s) {
+  switch (s) {
+    case MSPLAT_OK: return "ok";
+    case MSPLAT_E_INVALID: return "invalid argument";
+    case MSPLAT_E_CAPACITY: return "workspace too small";
+    case MSPLAT_E_UNSUPPORTED: return "unsupported network shape or precision";
+    case MSPLAT_E_HIP: return "HIP runtime error";
+    case MSPLAT_E_STATE: return "no matching forward pass";
+    default: return "unknown status";
+  }
+}
+
+int msplat_create(int device, msplat_ctx** out) {
+  if (!out) return MSPLAT_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) return MSPLAT_E_HIP;
+  if (device < 0 || device >= ndev) return MSPLAT_E_INVALID;
+  DeviceGuard dg(device);
+  msplat_ctx* c = new msplat_ctx();
+  c->device = device;
+  c->last_ws = nullptr;
+  c->last_items = -1;
+  c->last_hits = -1;
+  if (hipHostMalloc((void**)&c->host_ctr, sizeof(DevCounters), hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return MSPLAT_E_HIP;
+  }
+  *out = c;
+  return MSPLAT_OK;
+}
+
+void msplat_destroy(msplat_ctx* c) {
+  if (!c) return;
+  {
+    DeviceGuard dg(c->device);
+    for (auto& t : c->timers)
+      if (t.created)
+        for (int i = 0; i < kRing; ++i) {
+          (void)hipEventDestroy(t.a[i]);
+          (void)hipEventDestroy(t.b[i]);
+        }
+    (void)hipHostFree(c->host_ctr);
+  }
+  delete c;
+}
+
+int msplat_profile_enable(msplat_ctx* c, int enable) {
+  if (!c) return MSPLAT_E_INVALID;
+  DeviceGuard dg(c->device);
+  for (auto& t : c->timers) {
+    while (t.pending > 0)
+      if (harvest_one(t) != hipSuccess) return MSPLAT_E_HIP;
+    t.total_ms = 0.0;
+    t.count = 0;
+  }
+  c->profiling = enable != 0;
+  return MSPLAT_OK;
+}
+
+int msplat_profile_read(msplat_ctx* c, int max_stages, const char** names, double* total_ms,
+                        int64_t* launches, int* num_stages) {
+  if (!c || !num_stages || max_stages < 0) return MSPLAT_E_INVALID;
+  DeviceGuard dg(c->device);
+  *num_stages = ST_COUNT;
+  for (int i = 0; i < ST_COUNT; ++i) {
+    StageTimer& t = c->timers[i];
+    while (t.pending > 0)
+      if (harvest_one(t) != hipSuccess) return MSPLAT_E_HIP;
+    if (i < max_stages) {
+      if (names) names[i] = kStageNames[i];
+      if (total_ms) total_ms[i] = t.total_ms;
+      if (launches) launches[i] = t.count;
+    }
+  }
+  return MSPLAT_OK;
+}
+
+int64_t msplat_num_params(const msplat_model* m) {
+  NetShape n;
+  if (!shape_of(m, &n)) return 0;
+  return n.n_params;
+}
+
+int msplat_workspace_size(const msplat_model* m, int64_t num_rays, int64_t max_hits, uint64_t* bytes) {
+  NetShape n;
+  if (!bytes || !shape_of(m, &n) || num_rays < 0 || max_hits < 0) return MSPLAT_E_INVALID;
+  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  *bytes = layout(n, num_rays, max_hits, nullptr, nullptr) + 32 * kAlign;
+  return MSPLAT_OK;
+}
+
+int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                          const float* center, const float* scale, const float* quat, const float* mlp,
+                          const float* ray_o, const float* ray_d, int64_t R, float* rgb, float* trans,
+                          float* feat, void* wsp, uint64_t ws_bytes, uint64_t* need_bytes, void* stream) {
+  NetShape n;
+  if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  if (!center || !scale || !quat || !mlp || !wsp || R < 0 || R >= (int64_t)1 << 31) return MSPLAT_E_INVALID;
+  if (R > 0 && (!ray_o || !ray_d || !rgb || !trans)) return MSPLAT_E_INVALID;
+  int cf = n.NOUT - 4;
+  if (cf > 0 && R > 0 && !feat) return MSPLAT_E_INVALID;
+  if (((uintptr_t)wsp) % kAlign) return MSPLAT_E_INVALID;
+  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  int64_t hcap = capacity_of(n, R, ws_bytes);
+  uint64_t need0 = layout(n, R, 0, nullptr, nullptr) + 32 * kAlign;
+  if (ws_bytes < need0) {
+    if (need_bytes) *need_bytes = need0;
+    return MSPLAT_E_CAPACITY;
+  }
+  Workspace ws;
+  layout(n, R, hcap, (uint8_t*)wsp, &ws);
+  ctx->last_ws = nullptr;
+  STAGE(ctx, ST_ZERO, s, launch_zero(ws.counters, sizeof(DevCounters), s));
+  STAGE(ctx, ST_ZERO, s, launch_zero(ws.prim_nhit, (size_t)n.P * 4, s));
+  STAGE(ctx, ST_ZERO, s, launch_zero(ws.ray_off, 4, s));
+  // min |g| starts at +inf
+  {
+    static const uint32_t inf_bits = 0x7f800000u;
+    HIPCHK(hipMemcpyAsync(&ws.counters->min_abs_g_bits, &inf_bits, 4, hipMemcpyHostToDevice, s));
+  }
+  STAGE(ctx, ST_PREPROCESS, s, launch_preprocess(ws, center, scale, quat, n.P, s));
+  STAGE(ctx, ST_PACK, s, launch_pack_weights(n, ws, mlp, s));
+  STAGE(ctx, ST_BIN_COUNT, s, launch_bin_count(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
+  STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n.P, s));
+  HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t nh = ctx->host_ctr->num_hits;
+  int64_t items = ctx->host_ctr->num_work_items;
+  if (nh > hcap) {
+    if (need_bytes) *need_bytes = layout(n, R, nh, nullptr, nullptr) + 32 * kAlign;
+    return MSPLAT_E_CAPACITY;
+  }
+  if (need_bytes) *need_bytes = layout(n, R, nh, nullptr, nullptr) + 32 * kAlign;
+  STAGE(ctx, ST_BIN_FILL, s, launch_bin_fill(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
+  STAGE(ctx, ST_MLP_FWD, s, launch_mlp_forward(n, ws, *o, (int)items, 0, rgb, trans, feat, s));
+  STAGE(ctx, ST_COMPOSITE, s, launch_composite(ws, R, *o, rgb, trans, feat, cf, s));
+  if (o->t_stop > 0.f)
+    STAGE(ctx, ST_MLP_FIXUP, s, launch_mlp_forward(n, ws, *o, (int)items, 1, rgb, trans, feat, s));
+  ctx->last_ws = wsp;
+  ctx->last_items = items;
+  ctx->last_hits = nh;
+  ctx->last_rays = R;
+  ctx->last_bytes = ws_bytes;
+  ctx->last_shape = n;
+  return MSPLAT_OK;
+}
+
+int msplat_render_backward(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                           const float* center, const float* scale, const float* quat, const float* mlp,
+                           const float* ray_o, const float* ray_d, int64_t R, const float* grad_rgb,
+                           const float* grad_trans, const float* grad_feat, void* wsp,
+                           uint64_t ws_bytes, float* g_center, float* g_scale, float* g_quat,
+                           float* g_mlp, void* stream) {
+  NetShape n;
+  if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
+  if (!g_center || !g_scale || !g_quat || !g_mlp) return MSPLAT_E_INVALID;
+  if (R > 0 && (!ray_o || !ray_d || !grad_rgb)) return MSPLAT_E_INVALID;
+  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  int64_t hcap = capacity_of(n, R, ws_bytes);
+  Workspace ws;
+  layout(n, R, hcap, (uint8_t*)wsp, &ws);
+  int64_t items, nh;
+  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes) {
+    items = ctx->last_items;
+    nh = ctx->last_hits;
+  } else {
+    // workspace of an earlier forward: read its counters
+    HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->host_ctr->magic != kCountersMagic) return MSPLAT_E_STATE;
+    items = ctx->host_ctr->num_work_items;
+    nh = ctx->host_ctr->num_hits;
+  }
+  if (nh > hcap) return MSPLAT_E_STATE;
+  int cf = n.NOUT - 4;
+  STAGE(ctx, ST_ZERO, s, launch_zero(g_mlp, (size_t)n.P * n.n_params * 4, s));
+  STAGE(ctx, ST_ZERO, s, launch_zero(ws.geo_grad, (size_t)n.P * 12 * 4, s));
+  STAGE(ctx, ST_COMP_ADJ, s,
+        launch_composite_adjoint(ws, R, *o, grad_rgb, grad_trans, cf > 0 ? grad_feat : nullptr, cf,
+                                 ws.ray_tf, s));
+  STAGE(ctx, ST_MLP_BWD, s,
+        launch_mlp_backward(n, ws, *o, (int)items, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr,
+                            g_mlp, s));
+  STAGE(ctx, ST_GEO_FINAL, s, launch_geo_finalize(ws, n.P, g_center, g_scale, g_quat, s));
+  return MSPLAT_OK;
+}
+
+int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat_stats* out, void* stream) {
+  if (!ctx || !wsp || !out) return MSPLAT_E_INVALID;
+  if (ctx->last_ws != wsp) return MSPLAT_E_STATE;
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(hipMemcpyAsync(ctx->host_ctr, wsp, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const DevCounters& c = *ctx->host_ctr;
+  std::memset(out, 0, sizeof(*out));
+  out->num_rays = ctx->last_rays;
+  out->num_hits = c.num_hits;
+  out->num_samples = c.num_samples;
+  out->num_work_items = c.num_work_items;
+  out->num_terminated = c.num_terminated;
+  out->num_fallbacks = c.num_fallbacks;
+  float mg;
+  std::memcpy(&mg, &c.min_abs_g_bits, 4);
+  out->min_abs_g = mg;
+  (void)ws_bytes;
+  return MSPLAT_OK;
+}
+
+int msplat_debug_hits(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, int64_t num_rays,
+                      int64_t* ray_off, int32_t* prim, double* t_c, int32_t* n_used, int64_t capacity,
+                      void* stream) {
+  if (!ctx || !wsp || !ray_off || !prim || !t_c || !n_used || capacity < 0) return MSPLAT_E_INVALID;
+  if (ctx->last_ws != wsp || ctx->last_rays != num_rays || ctx->last_bytes != ws_bytes)
+    return MSPLAT_E_STATE;
+  int64_t nh = ctx->last_hits;
+  if (nh > capacity) return MSPLAT_E_CAPACITY;
+  DeviceGuard dg(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  Workspace ws;
+  layout(ctx->last_shape, num_rays, capacity_of(ctx->last_shape, num_rays, ws_bytes), (uint8_t*)wsp, &ws);
+  int32_t* off32 = new int32_t[num_rays + 1];
+  float* hi = new float[nh > 0 ? nh : 1];
+  float* lo = new float[nh > 0 ? nh : 1];
+  int rc = MSPLAT_OK;
+  if (hipMemcpyAsync(off32, ws.ray_off, (num_rays + 1) * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      (nh > 0 && (hipMemcpyAsync(prim, ws.hit_prim, nh * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipMemcpyAsync(n_used, ws.hit_nused, nh * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipMemcpyAsync(hi, ws.hit_tc_hi, nh * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipMemcpyAsync(lo, ws.hit_tc_lo, nh * 4, hipMemcpyDeviceToHost, s) != hipSuccess)) ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    rc = MSPLAT_E_HIP;
+  } else {
+    for (int64_t i = 0; i <= num_rays; ++i) ray_off[i] = off32[i];
+    for (int64_t i = 0; i < nh; ++i) t_c[i] = (double)hi[i] + (double)lo[i];
+  }
+  delete[] off32;
+  delete[] hi;
+  delete[] lo;
+  return rc;
+}
+
+int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                              const double* center, const double* scale, const double* quat,
+                              const double* mlp, const double* ray_o, const double* ray_d,
+                              int64_t R, double* rgb, double* trans, double* feat, void* wsp,
+                              uint64_t ws_bytes, uint64_t* need_bytes, void* stream) {
+  (void)ctx; (void)m; (void)o; (void)center; (void)scale; (void)quat; (void)mlp; (void)ray_o;
+  (void)ray_d; (void)R; (void)rgb; (void)trans; (void)feat; (void)wsp; (void)ws_bytes;
+  (void)need_bytes; (void)stream;
+  return MSPLAT_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,815 @@
+// Ray/support geometry, binning, depth sort, per-ray compositing and their
+// adjoints for the MLP-Splatting render path on gfx950.
+//
+// Hit test (Sec. 3.2, Eq. 1-2): with M = diag(s)^-1 R(q)^T, v = mu - o and
+// e = M d, the contact depth t_c = (e . M v) / (e . e) is the unclamped
+// minimiser of the Lambda-distance of Eq. 1; p_c = -M (v - t_c d) is the local
+// contact point, g = 1 - |p_c|^2 and eta = sqrt(g / |e|^2) the half chord.  A
+// pair is a hit iff g > 0 and t_c + eta > 0; the chord starts at
+// max(t_c - eta, 0) (the clamp of Eq. 2).
+//
+// Every discrete decision (hit, front, clipped start, sample count, depth
+// order) is taken in float32 when its margin is large and recomputed in
+// double-float arithmetic otherwise, so the hit lists equal those of exact
+// arithmetic except for margins below ~1e-12.
+#include "common.h"
+
+namespace msplat {
+
+namespace {
+
+constexpr float kEpsG = 1e-4f;       // |g| below this: decide in double-float
+constexpr float kEpsT = 1e-5f;       // relative margin of the front / clip tests
+constexpr float kEpsK = 1e-3f;       // distance of K*L to an integer
+constexpr float kEpsKey = 1e-6f;     // relative depth gap below which keys are recomputed
+
+__device__ __forceinline__ float3 ld3(const float* p, int64_t i) {
+  return make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+}
+
+// ----------------------------------------------------------- preprocessing --
+
+__global__ void preprocess_kernel(const float* __restrict__ center, const float* __restrict__ scale,
+                                  const float* __restrict__ quat, float* __restrict__ geo, int P) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float* g = geo + (int64_t)i * kGeoStride;
+  float q[4] = {quat[4 * i], quat[4 * i + 1], quat[4 * i + 2], quat[4 * i + 3]};
+  float s[3] = {scale[3 * i], scale[3 * i + 1], scale[3 * i + 2]};
+  // normalised quaternion and rotation, double-float
+  df n2 = two_prod(q[0], q[0]);
+  for (int k = 1; k < 4; ++k) n2 = df_add(n2, two_prod(q[k], q[k]));
+  df nrm = df_sqrt(n2);
+  df qn[4];
+  for (int k = 0; k < 4; ++k) qn[k] = df_div(df_from(q[k]), nrm);
+  const df& w = qn[0];
+  const df& x = qn[1];
+  const df& y = qn[2];
+  const df& z = qn[3];
+  df one = df_from(1.f), two = df_from(2.f);
+  df r[9];
+  r[0] = df_sub(one, df_mul(two, df_add(df_mul(y, y), df_mul(z, z))));
+  r[1] = df_mul(two, df_sub(df_mul(x, y), df_mul(w, z)));
+  r[2] = df_mul(two, df_add(df_mul(x, z), df_mul(w, y)));
+  r[3] = df_mul(two, df_add(df_mul(x, y), df_mul(w, z)));
+  r[4] = df_sub(one, df_mul(two, df_add(df_mul(x, x), df_mul(z, z))));
+  r[5] = df_mul(two, df_sub(df_mul(y, z), df_mul(w, x)));
+  r[6] = df_mul(two, df_sub(df_mul(x, z), df_mul(w, y)));
+  r[7] = df_mul(two, df_add(df_mul(y, z), df_mul(w, x)));
+  r[8] = df_sub(one, df_mul(two, df_add(df_mul(x, x), df_mul(y, y))));
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      df m = df_div(r[3 * b + a], df_from(s[a]));   // M[a][b] = R[b][a] / s[a]
+      g[G_M_HI + 3 * a + b] = m.hi;
+      g[G_M_LO + 3 * a + b] = m.lo;
+    }
+  for (int k = 0; k < 9; ++k) g[G_R + k] = r[k].hi;
+  for (int k = 0; k < 3; ++k) g[G_MU + k] = center[3 * i + k];
+  for (int k = 0; k < 4; ++k) g[G_QN + k] = qn[k].hi;
+  for (int k = 0; k < 3; ++k) g[G_S + k] = s[k];
+  g[G_INVQ] = 1.f / nrm.hi;
+  float rad = fmaxf(fmaxf(s[0], s[1]), s[2]);
+  g[G_RAD] = rad * (1.f + 1e-4f) + 1e-6f;
+}
+
+// ------------------------------------------------------------ hit testing --
+
+struct HitF {
+  bool hit, uncertain;
+  bool clipped;
+  float tc_hi, tc_lo, eta, g, a;
+};
+
+// float32 test with one refinement step of the contact depth.
+__device__ __forceinline__ HitF hit_test_f32(const float* __restrict__ g, float3 o, float3 d,
+                                             const msplat_opts& opt, int* k_out) {
+  HitF h;
+  const float* M = g + G_M_HI;
+  float v[3], vlo[3];
+  {
+    df t0 = two_sum(g[G_MU + 0], -o.x);
+    df t1 = two_sum(g[G_MU + 1], -o.y);
+    df t2 = two_sum(g[G_MU + 2], -o.z);
+    v[0] = t0.hi; v[1] = t1.hi; v[2] = t2.hi;
+    vlo[0] = t0.lo; vlo[1] = t1.lo; vlo[2] = t2.lo;
+  }
+  float dd[3] = {d.x, d.y, d.z};
+  float m[3], e[3];
+  for (int r = 0; r < 3; ++r) {
+    m[r] = M[3 * r] * v[0] + M[3 * r + 1] * v[1] + M[3 * r + 2] * v[2];
+    e[r] = M[3 * r] * dd[0] + M[3 * r + 1] * dd[1] + M[3 * r + 2] * dd[2];
+  }
+  float a = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  float t0 = (e[0] * m[0] + e[1] * m[1] + e[2] * m[2]) / a;
+  float dl0[3];
+  for (int k = 0; k < 3; ++k) dl0[k] = __builtin_fmaf(-t0, dd[k], v[k]) + vlo[k];
+  float md[3];
+  for (int r = 0; r < 3; ++r) md[r] = M[3 * r] * dl0[0] + M[3 * r + 1] * dl0[1] + M[3 * r + 2] * dl0[2];
+  float dt = (e[0] * md[0] + e[1] * md[1] + e[2] * md[2]) / a;
+  float pc[3];
+  for (int r = 0; r < 3; ++r) pc[r] = dt * e[r] - md[r];   // -M (dl0 - dt d)
+  float gg = __builtin_fmaf(-pc[0], pc[0], __builtin_fmaf(-pc[1], pc[1], __builtin_fmaf(-pc[2], pc[2], 1.f)));
+  df tc = fast_two_sum(t0, dt);
+  h.tc_hi = tc.hi;
+  h.tc_lo = tc.lo;
+  h.g = gg;
+  h.a = a;
+  float eta = sqrtf(fmaxf(gg, 0.f) / a);
+  h.eta = eta;
+  float front = tc.hi + eta;
+  float back = tc.hi - eta;
+  float tscale = kEpsT * (1.f + fabsf(tc.hi));
+  h.hit = gg > 0.f && front > 0.f;
+  h.clipped = back <= 0.f;
+  h.uncertain = fabsf(gg) < kEpsG || (gg > 0.f && (fabsf(front) < tscale || fabsf(back) < tscale));
+  if (h.hit && !h.uncertain && k_out) {
+    if (opt.samples_fixed > 0) {
+      *k_out = opt.samples_fixed;
+    } else {
+      float L = h.clipped ? (tc.hi + eta) : 2.f * eta;
+      float xk = opt.samples_per_unit * L;
+      float c = ceilf(xk);
+      if (fabsf(xk - rintf(xk)) < kEpsK) h.uncertain = true;
+      int k = (int)c;
+      k = k < opt.samples_min ? opt.samples_min : (k > opt.samples_max ? opt.samples_max : k);
+      *k_out = k;
+    }
+  }
+  return h;
+}
+
+struct HitDF {
+  bool hit, clipped;
+  df tc, eta;
+  float g;
+  int K;
+};
+
+// the same test evaluated entirely in double-float from the raw inputs
+__device__ HitDF hit_test_df(const float* __restrict__ center, const float* __restrict__ scale,
+                             const float* __restrict__ quat, int p, float3 o, float3 d,
+                             const msplat_opts& opt) {
+  float q[4] = {quat[4 * p], quat[4 * p + 1], quat[4 * p + 2], quat[4 * p + 3]};
+  df n2 = two_prod(q[0], q[0]);
+  for (int k = 1; k < 4; ++k) n2 = df_add(n2, two_prod(q[k], q[k]));
+  df nrm = df_sqrt(n2);
+  df w = df_div(df_from(q[0]), nrm), x = df_div(df_from(q[1]), nrm);
+  df y = df_div(df_from(q[2]), nrm), z = df_div(df_from(q[3]), nrm);
+  df one = df_from(1.f), two = df_from(2.f);
+  df r[9];
+  r[0] = df_sub(one, df_mul(two, df_add(df_mul(y, y), df_mul(z, z))));
+  r[1] = df_mul(two, df_sub(df_mul(x, y), df_mul(w, z)));
+  r[2] = df_mul(two, df_add(df_mul(x, z), df_mul(w, y)));
+  r[3] = df_mul(two, df_add(df_mul(x, y), df_mul(w, z)));
+  r[4] = df_sub(one, df_mul(two, df_add(df_mul(x, x), df_mul(z, z))));
+  r[5] = df_mul(two, df_sub(df_mul(y, z), df_mul(w, x)));
+  r[6] = df_mul(two, df_sub(df_mul(x, z), df_mul(w, y)));
+  r[7] = df_mul(two, df_add(df_mul(y, z), df_mul(w, x)));
+  r[8] = df_sub(one, df_mul(two, df_add(df_mul(x, x), df_mul(y, y))));
+  df v[3] = {two_sum(center[3 * p], -o.x), two_sum(center[3 * p + 1], -o.y),
+             two_sum(center[3 * p + 2], -o.z)};
+  float dd[3] = {d.x, d.y, d.z};
+  df m[3], e[3];
+  for (int a = 0; a < 3; ++a) {
+    df inv_s = df_div(one, df_from(scale[3 * p + a]));
+    df sm = df_from(0.f), se = df_from(0.f);
+    for (int b = 0; b < 3; ++b) {
+      df mab = r[3 * b + a];
+      sm = df_add(sm, df_mul(mab, v[b]));
+      se = df_add(se, df_mulf(mab, dd[b]));
+    }
+    m[a] = df_mul(sm, inv_s);
+    e[a] = df_mul(se, inv_s);
+  }
+  df aa = df_add(df_add(df_mul(e[0], e[0]), df_mul(e[1], e[1])), df_mul(e[2], e[2]));
+  df em = df_add(df_add(df_mul(e[0], m[0]), df_mul(e[1], m[1])), df_mul(e[2], m[2]));
+  df tc = df_div(em, aa);
+  df gsum = df_from(0.f);
+  for (int k = 0; k < 3; ++k) {
+    df pck = df_sub(df_mul(tc, e[k]), m[k]);
+    gsum = df_add(gsum, df_mul(pck, pck));
+  }
+  df g = df_sub(one, gsum);
+  HitDF h;
+  h.tc = tc;
+  h.g = g.hi;
+  h.hit = false;
+  h.clipped = false;
+  h.eta = df_from(0.f);
+  h.K = 0;
+  if (df_sign(g) <= 0) return h;
+  df eta = df_sqrt(df_div(g, aa));
+  h.eta = eta;
+  if (df_sign(df_add(tc, eta)) <= 0) return h;
+  h.hit = true;
+  h.clipped = df_sign(df_sub(tc, eta)) <= 0;
+  if (opt.samples_fixed > 0) {
+    h.K = opt.samples_fixed;
+  } else {
+    df L = h.clipped ? df_add(tc, eta) : df_mul(two, eta);
+    df xk = df_mulf(L, opt.samples_per_unit);
+    float c = ceilf(xk.hi);
+    if (c == xk.hi && xk.lo > 0.f) c += 1.f;
+    int k = (int)c;
+    h.K = k < opt.samples_min ? opt.samples_min : (k > opt.samples_max ? opt.samples_max : k);
+  }
+  return h;
+}
+
+// --------------------------------------------------------- packet culling --
+
+struct Cone {
+  float ox, oy, oz, dx, dy, dz, cos_t, sin_t, rho;
+  bool all;
+};
+
+__device__ __forceinline__ Cone packet_cone(bool valid, float3 o, float3 d) {
+  Cone c;
+  float nv = (float)__popcll(__ballot(valid));
+  float sx = wave_sum(valid ? o.x : 0.f), sy = wave_sum(valid ? o.y : 0.f),
+        sz = wave_sum(valid ? o.z : 0.f);
+  c.ox = sx / nv; c.oy = sy / nv; c.oz = sz / nv;
+  float ex = o.x - c.ox, ey = o.y - c.oy, ez = o.z - c.oz;
+  float r2 = wave_max(valid ? ex * ex + ey * ey + ez * ez : 0.f);
+  c.rho = sqrtf(r2);
+  float ax = wave_sum(valid ? d.x : 0.f), ay = wave_sum(valid ? d.y : 0.f),
+        az = wave_sum(valid ? d.z : 0.f);
+  float an = sqrtf(ax * ax + ay * ay + az * az);
+  c.all = true;
+  c.cos_t = -1.f;
+  c.sin_t = 0.f;
+  c.dx = c.dy = c.dz = 0.f;
+  if (an > 1e-6f * nv) {
+    c.dx = ax / an; c.dy = ay / an; c.dz = az / an;
+    float dn = sqrtf(d.x * d.x + d.y * d.y + d.z * d.z);
+    float cdot = (d.x * c.dx + d.y * c.dy + d.z * c.dz) / dn;
+    float cmin = wave_min(valid ? cdot : 1.f);
+    float ct = cmin - 1e-4f;                  // widen the cone a little
+    if (ct > 0.1f) {
+      c.all = false;
+      c.cos_t = ct;
+      c.sin_t = sqrtf(fmaxf(0.f, 1.f - ct * ct));
+    }
+  }
+  return c;
+}
+
+// conservative test: can any ray of the packet pass within `rad` of `cen`?
+__device__ __forceinline__ bool cone_may_hit(const Cone& c, float cx, float cy, float cz, float rad) {
+  if (c.all) return true;
+  float vx = cx - c.ox, vy = cy - c.oy, vz = cz - c.oz;
+  float a = vx * c.dx + vy * c.dy + vz * c.dz;
+  float v2 = vx * vx + vy * vy + vz * vz;
+  float b = sqrtf(fmaxf(v2 - a * a, 0.f));
+  float dist = (a * c.cos_t + b * c.sin_t >= 0.f) ? (b * c.cos_t - a * c.sin_t) : sqrtf(v2);
+  float r = (rad + c.rho) * (1.f + 1e-4f) + 1e-5f * (1.f + sqrtf(v2));
+  return dist <= r;
+}
+
+// ---------------------------------------------------------- count kernel --
+
+__global__ __launch_bounds__(256) void bin_count_kernel(
+    const float* __restrict__ ray_o, const float* __restrict__ ray_d,
+    const float* __restrict__ center, const float* __restrict__ scale,
+    const float* __restrict__ quat, const float* __restrict__ geo, int64_t R, int P,
+    msplat_opts opt, int32_t* __restrict__ ray_cnt, int32_t* __restrict__ prim_nhit,
+    DevCounters* __restrict__ ctr) {
+  int64_t packet = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = lane_id();
+  int64_t ray = packet * kWave + lane;
+  if (packet * kWave >= R) return;   // whole wave out of range (wave-uniform)
+  bool valid = ray < R;
+  float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
+  float3 d = valid ? ld3(ray_d, ray) : make_float3(0.f, 0.f, 1.f);
+  Cone cone = packet_cone(valid, o, d);
+  int nhit = 0;
+  int64_t nsamp = 0;
+  int nfall = 0;
+  float min_g = 3.0e38f;
+  for (int base = 0; base < P; base += kWave) {
+    int pl = base + lane;
+    bool cand = false;
+    if (pl < P) {
+      const float* gp = geo + (int64_t)pl * kGeoStride;
+      cand = cone_may_hit(cone, gp[G_MU], gp[G_MU + 1], gp[G_MU + 2], gp[G_RAD]);
+    }
+    uint64_t mask = __ballot(cand);
+    while (mask) {
+      int bit = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      int p = __builtin_amdgcn_readfirstlane(base + bit);
+      const float* gp = geo + (int64_t)p * kGeoStride;
+      bool hit = false;
+      int K = 0;
+      if (valid) {
+        HitF h = hit_test_f32(gp, o, d, opt, &K);
+        if (h.tc_hi + h.eta > 0.f) min_g = fminf(min_g, fabsf(h.g));
+        hit = h.hit;
+        if (h.uncertain) {
+          HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
+          hit = hd.hit;
+          K = hd.K;
+          ++nfall;
+        }
+      }
+      if (hit) {
+        ++nhit;
+        nsamp += K;
+      }
+      int cnt = __popcll(__ballot(hit));
+      if (lane == 0 && cnt) atomicAdd(&prim_nhit[p], cnt);
+    }
+  }
+  if (valid) ray_cnt[ray + 1] = nhit;
+  int64_t ws = wave_sum(nsamp);
+  int wf = wave_sum(nfall);
+  float wm = wave_min(min_g);
+  if (lane == 0) {
+    atomicAdd((unsigned long long*)&ctr->num_samples, (unsigned long long)ws);
+    if (wf) atomicAdd(&ctr->num_fallbacks, wf);
+    atomicMin(&ctr->min_abs_g_bits, __float_as_uint(wm));
+  }
+}
+
+// ----------------------------------------------------------------- scans --
+
+constexpr int kScanBlock = 1024;
+
+// inclusive scan of data[0..n) in blocks of 1024, block totals to sums
+__global__ __launch_bounds__(256) void scan_blocks_kernel(int32_t* __restrict__ data, int64_t n,
+                                                          int32_t* __restrict__ sums) {
+  __shared__ int32_t wsum[4];
+  int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  int t = threadIdx.x;
+  int32_t v[4];
+  int32_t acc = 0;
+  for (int k = 0; k < 4; ++k) {
+    int64_t i = base + 4 * t + k;
+    v[k] = i < n ? data[i] : 0;
+    acc += v[k];
+    v[k] = acc;
+  }
+  int incl = wave_incl_scan(acc);
+  int w = t / kWave;
+  if (lane_id() == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  int wo = 0;
+  for (int k = 0; k < w; ++k) wo += wsum[k];
+  int excl = incl - acc + wo;
+  for (int k = 0; k < 4; ++k) {
+    int64_t i = base + 4 * t + k;
+    if (i < n) data[i] = v[k] + excl;
+  }
+  if (t == 255) sums[blockIdx.x] = excl + acc;
+}
+
+// exclusive scan of the (few) block sums by one workgroup, in chunks
+__global__ __launch_bounds__(256) void scan_sums_kernel(int32_t* __restrict__ sums, int64_t nb,
+                                                        int32_t* __restrict__ total) {
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nb; base += 256) {
+    int64_t i = base + threadIdx.x;
+    int32_t v = i < nb ? sums[i] : 0;
+    int incl = wave_incl_scan(v);
+    int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int wo = carry;
+    for (int k = 0; k < w; ++k) wo += wsum[k];
+    if (i < nb) sums[i] = incl - v + wo;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = wo + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(256) void scan_add_kernel(int32_t* __restrict__ data, int64_t n,
+                                                       const int32_t* __restrict__ sums) {
+  int64_t base = (int64_t)blockIdx.x * kScanBlock;
+  int32_t add = sums[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanBlock; k += 256) {
+    int64_t i = base + k;
+    if (i < n) data[i] += add;
+  }
+}
+
+// per-primitive offsets, cursors and work items (one workgroup)
+__global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restrict__ prim_nhit,
+                                                        int32_t* __restrict__ prim_off,
+                                                        int32_t* __restrict__ prim_cursor,
+                                                        int32_t* __restrict__ wi_off, int P,
+                                                        const int32_t* __restrict__ ray_off,
+                                                        int64_t R, DevCounters* __restrict__ ctr) {
+  __shared__ int32_t wsum[2][4];
+  __shared__ int32_t carry[2];
+  if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+  __syncthreads();
+  for (int base = 0; base < P; base += 256) {
+    int i = base + threadIdx.x;
+    int32_t n = i < P ? prim_nhit[i] : 0;
+    int32_t wi = (n + kHitsPerItem - 1) / kHitsPerItem;
+    int in = wave_incl_scan(n);
+    int iw = wave_incl_scan(wi);
+    int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) {
+      wsum[0][w] = in;
+      wsum[1][w] = iw;
+    }
+    __syncthreads();
+    int on = carry[0], ow = carry[1];
+    for (int k = 0; k < w; ++k) {
+      on += wsum[0][k];
+      ow += wsum[1][k];
+    }
+    if (i < P) {
+      prim_off[i] = in - n + on;
+      prim_cursor[i] = in - n + on;
+      wi_off[i] = iw - wi + ow;
+    }
+    __syncthreads();
+    if (threadIdx.x == 255) {
+      carry[0] = on + in;
+      carry[1] = ow + iw;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    prim_off[P] = carry[0];
+    wi_off[P] = carry[1];
+    ctr->num_hits = ray_off[R];
+    ctr->num_work_items = carry[1];
+    ctr->magic = kCountersMagic;
+  }
+}
+
+// ----------------------------------------------------------- fill kernel --
+
+// strict weak order on (t_c, prim) with double-float recomputation of close keys
+__device__ __forceinline__ bool key_less(float ahi, float alo, int ap, float bhi, float blo, int bp,
+                                         const float* center, const float* scale, const float* quat,
+                                         float3 o, float3 d, const msplat_opts& opt) {
+  float diff = (ahi - bhi) + (alo - blo);
+  if (fabsf(diff) > kEpsKey * (1.f + fabsf(ahi))) return diff < 0.f;
+  HitDF a = hit_test_df(center, scale, quat, ap, o, d, opt);
+  HitDF b = hit_test_df(center, scale, quat, bp, o, d, opt);
+  int sg = df_sign(df_sub(a.tc, b.tc));
+  if (sg != 0) return sg < 0;
+  return ap < bp;
+}
+
+__global__ __launch_bounds__(256) void bin_fill_kernel(
+    const float* __restrict__ ray_o, const float* __restrict__ ray_d,
+    const float* __restrict__ center, const float* __restrict__ scale,
+    const float* __restrict__ quat, const float* __restrict__ geo, int64_t R, int P,
+    msplat_opts opt, Workspace ws) {
+  int64_t packet = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = lane_id();
+  int64_t ray = packet * kWave + lane;
+  if (packet * kWave >= R) return;
+  bool valid = ray < R;
+  float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
+  float3 d = valid ? ld3(ray_d, ray) : make_float3(0.f, 0.f, 1.f);
+  Cone cone = packet_cone(valid, o, d);
+  int64_t off = valid ? ws.ray_off[ray] : 0;
+  int n = 0;
+  // pass 1: unsorted hits (primitive order) with their decided K, clip flag, eta
+  for (int base = 0; base < P; base += kWave) {
+    int pl = base + lane;
+    bool cand = false;
+    if (pl < P) {
+      const float* gp = geo + (int64_t)pl * kGeoStride;
+      cand = cone_may_hit(cone, gp[G_MU], gp[G_MU + 1], gp[G_MU + 2], gp[G_RAD]);
+    }
+    uint64_t mask = __ballot(cand);
+    while (mask) {
+      int bit = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      int p = __builtin_amdgcn_readfirstlane(base + bit);
+      const float* gp = geo + (int64_t)p * kGeoStride;
+      if (!valid) continue;
+      int K = 0;
+      HitF h = hit_test_f32(gp, o, d, opt, &K);
+      bool hit = h.hit;
+      bool clipped = h.clipped;
+      float eta = h.eta;
+      if (h.uncertain) {
+        HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
+        hit = hd.hit;
+        K = hd.K;
+        clipped = hd.clipped;
+        eta = hd.eta.hi;
+      }
+      if (hit) {
+        int64_t j = off + n;
+        ws.hit_prim[j] = p;
+        ws.hit_tc_hi[j] = h.tc_hi;
+        ws.hit_tc_lo[j] = h.tc_lo;
+        ws.hit_k[j] = clipped ? -K : K;
+        ws.hit_eta[j] = eta;
+        ++n;
+      }
+    }
+  }
+  if (!valid) return;
+  // pass 2: insertion sort of this ray's segment by (t_c, prim)
+  for (int i = 1; i < n; ++i) {
+    int64_t ji = off + i;
+    int p = ws.hit_prim[ji];
+    float th = ws.hit_tc_hi[ji], tl = ws.hit_tc_lo[ji], et = ws.hit_eta[ji];
+    int kk = ws.hit_k[ji];
+    int j = i - 1;
+    while (j >= 0) {
+      int64_t jj = off + j;
+      int pj = ws.hit_prim[jj];
+      if (!key_less(th, tl, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt))
+        break;
+      ws.hit_prim[jj + 1] = pj;
+      ws.hit_tc_hi[jj + 1] = ws.hit_tc_hi[jj];
+      ws.hit_tc_lo[jj + 1] = ws.hit_tc_lo[jj];
+      ws.hit_eta[jj + 1] = ws.hit_eta[jj];
+      ws.hit_k[jj + 1] = ws.hit_k[jj];
+      --j;
+    }
+    int64_t jd = off + j + 1;
+    ws.hit_prim[jd] = p;
+    ws.hit_tc_hi[jd] = th;
+    ws.hit_tc_lo[jd] = tl;
+    ws.hit_eta[jd] = et;
+    ws.hit_k[jd] = kk;
+  }
+  // pass 3: per-hit local record and grouping by primitive
+  int64_t H = ws.hit_cap;
+  for (int i = 0; i < n; ++i) {
+    int64_t j = off + i;
+    int p = ws.hit_prim[j];
+    const float* gp = geo + (int64_t)p * kGeoStride;
+    const float* Mh = gp + G_M_HI;
+    const float* Ml = gp + G_M_LO;
+    float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j], eta = ws.hit_eta[j];
+    int kk = ws.hit_k[j];
+    bool clipped = kk < 0;
+    int K = clipped ? -kk : kk;
+    // residual delta = (mu - o) - t_c d, accurate to a few ulps of |delta|
+    float dd[3] = {d.x, d.y, d.z};
+    float oo[3] = {o.x, o.y, o.z};
+    float dl[3];
+    for (int k = 0; k < 3; ++k) {
+      df v = two_sum(gp[G_MU + k], -oo[k]);
+      float t = __builtin_fmaf(-tch, dd[k], v.hi);
+      dl[k] = __builtin_fmaf(-tcl, dd[k], t) + v.lo;
+    }
+    for (int r = 0; r < 3; ++r) {
+      float pc = 0.f, e = 0.f;
+      for (int c = 0; c < 3; ++c) {
+        pc = __builtin_fmaf(Mh[3 * r + c], dl[c], pc);
+        pc = __builtin_fmaf(Ml[3 * r + c], dl[c], pc);
+        e = __builtin_fmaf(Mh[3 * r + c], dd[c], e);
+        e = __builtin_fmaf(Ml[3 * r + c], dd[c], e);
+      }
+      ws.hit_pc[r * H + j] = -pc;
+      ws.hit_e[r * H + j] = e;
+    }
+    float sa, dlt;
+    if (clipped) {
+      sa = -(tch + tcl);
+      dlt = ((tch + eta) + tcl) / (float)K;
+    } else {
+      sa = -eta;
+      dlt = 2.f * eta / (float)K;
+    }
+    ws.hit_sa[j] = sa;
+    ws.hit_dlt[j] = dlt;
+    ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
+    ws.hit_ray[j] = (int32_t)ray;
+    int slot = atomicAdd(&ws.prim_cursor[p], 1);
+    ws.phit[slot] = (int32_t)j;
+  }
+}
+
+// ------------------------------------------------------------ compositor --
+
+// optical depth kept as a double-float (compensated) sum
+__device__ __forceinline__ float depth_total(float hi, float lo, float x) { return hi + (lo + x); }
+
+__global__ __launch_bounds__(256) void composite_kernel(Workspace ws, int64_t R, msplat_opts opt,
+                                                        float* __restrict__ rgb,
+                                                        float* __restrict__ trans,
+                                                        float* __restrict__ feat, int cf) {
+  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  int64_t a = ws.ray_off[ray], b = ws.ray_off[ray + 1];
+  int64_t H = ws.hit_cap;
+  float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+  float f[16];
+  for (int k = 0; k < 16; ++k) f[k] = 0.f;
+  float shi = 0.f, slo = 0.f;
+  bool stopped = false;
+  for (int64_t j = a; j < b; ++j) {
+    if (stopped) {
+      ws.hit_nused[j] = 0;
+      continue;
+    }
+    ws.hit_sb_hi[j] = shi;
+    ws.hit_sb_lo[j] = slo;
+    float tau = ws.hit_tau[j];
+    float tb = __expf(-(shi + slo));
+    if (opt.t_stop > 0.f && __expf(-depth_total(shi, slo, tau)) < opt.t_stop) {
+      ws.hit_nused[j] = -1;     // cut inside this hit: resolved per sample by the fixup pass
+      stopped = true;
+      continue;
+    }
+    ws.hit_nused[j] = ws.hit_k[j] & kKMask;
+    c0 = __builtin_fmaf(tb, ws.hit_cloc[0 * H + j], c0);
+    c1 = __builtin_fmaf(tb, ws.hit_cloc[1 * H + j], c1);
+    c2 = __builtin_fmaf(tb, ws.hit_cloc[2 * H + j], c2);
+    for (int k = 0; k < cf; ++k) f[k] = __builtin_fmaf(tb, ws.hit_cloc[(3 + k) * H + j], f[k]);
+    df s = two_sum(shi, tau);
+    slo += s.lo;
+    shi = s.hi;
+  }
+  float t = __expf(-(shi + slo));
+  if (stopped) {
+    // partial sums; the fixup pass adds the cut hit and the background
+    rgb[3 * ray] = c0;
+    rgb[3 * ray + 1] = c1;
+    rgb[3 * ray + 2] = c2;
+    atomicAdd(&ws.counters->num_terminated, 1);
+  } else {
+    rgb[3 * ray] = c0 + t * opt.background[0];
+    rgb[3 * ray + 1] = c1 + t * opt.background[1];
+    rgb[3 * ray + 2] = c2 + t * opt.background[2];
+    trans[ray] = t;
+    ws.ray_tf[ray] = t;
+  }
+  for (int k = 0; k < cf; ++k) feat[ray * cf + k] = f[k];
+}
+
+// per-ray adjoint: transmittance before each hit and g . (what follows it)
+__global__ __launch_bounds__(256) void composite_adjoint_kernel(
+    Workspace ws, int64_t R, msplat_opts opt, const float* __restrict__ grad_rgb,
+    const float* __restrict__ grad_trans, const float* __restrict__ grad_feat, int cf,
+    const float* __restrict__ trans) {
+  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ray >= R) return;
+  int64_t a = ws.ray_off[ray], b = ws.ray_off[ray + 1];
+  int64_t H = ws.hit_cap;
+  float g0 = grad_rgb[3 * ray], g1 = grad_rgb[3 * ray + 1], g2 = grad_rgb[3 * ray + 2];
+  float tf = trans[ray];
+  // d(rgb)/d(tau_k) = T_{k+1} c_k - sum_{j>k} w_j c_j - T_final bg, and
+  // d(T_final)/d(tau_k) = -T_final: the suffix starts with T_final (g.bg + g_T)
+  float gt = grad_trans ? grad_trans[ray] : 0.f;
+  float acc = tf * (g0 * opt.background[0] + g1 * opt.background[1] + g2 * opt.background[2] + gt);
+  for (int64_t j = b - 1; j >= a; --j) {
+    if (ws.hit_nused[j] <= 0) continue;
+    ws.hit_gsa[j] = acc;
+    float tb = __expf(-(ws.hit_sb_hi[j] + ws.hit_sb_lo[j]));
+    float gc = g0 * ws.hit_cloc[0 * H + j] + g1 * ws.hit_cloc[1 * H + j] + g2 * ws.hit_cloc[2 * H + j];
+    if (grad_feat)
+      for (int k = 0; k < cf; ++k) gc += grad_feat[ray * cf + k] * ws.hit_cloc[(3 + k) * H + j];
+    ws.hit_tb[j] = tb;
+    ws.hit_gtot[j] = tb * gc;
+    acc = __builtin_fmaf(tb, gc, acc);
+  }
+}
+
+// dL/dM and dL/dv accumulated per primitive -> dL/d(center, scale, quat)
+__global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* __restrict__ acc,
+                                    int P, float* __restrict__ g_center, float* __restrict__ g_scale,
+                                    float* __restrict__ g_quat) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const float* gp = geo + (int64_t)i * kGeoStride;
+  const float* A = acc + (int64_t)i * 12;
+  float M[9], GM[9], u[3];
+  for (int k = 0; k < 9; ++k) {
+    M[k] = gp[G_M_HI + k] + gp[G_M_LO + k];
+    GM[k] = A[k];
+  }
+  for (int k = 0; k < 3; ++k) u[k] = A[9 + k];
+  // dL/dmu = M^T u
+  for (int c = 0; c < 3; ++c) g_center[3 * i + c] = M[c] * u[0] + M[3 + c] * u[1] + M[6 + c] * u[2];
+  // M[a][b] = R[b][a] / s[a]
+  float G[9];   // dL/dR
+  for (int a2 = 0; a2 < 3; ++a2) {
+    float s = gp[G_S + a2];
+    float ds = 0.f;
+    for (int b2 = 0; b2 < 3; ++b2) {
+      ds += GM[3 * a2 + b2] * M[3 * a2 + b2];
+      G[3 * b2 + a2] = GM[3 * a2 + b2] / s;
+    }
+    g_scale[3 * i + a2] = -ds / s;
+  }
+  float w = gp[G_QN], x = gp[G_QN + 1], y = gp[G_QN + 2], z = gp[G_QN + 3];
+  float dw = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+  float dx = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
+                    2.f * x * G[8]);
+  float dy = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] -
+                    2.f * y * G[8]);
+  float dz = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] + y * G[5] + x * G[6] +
+                    y * G[7]);
+  float dot = w * dw + x * dx + y * dy + z * dz;
+  float inv = gp[G_INVQ];
+  g_quat[4 * i] = (dw - w * dot) * inv;
+  g_quat[4 * i + 1] = (dx - x * dot) * inv;
+  g_quat[4 * i + 2] = (dy - y * dot) * inv;
+  g_quat[4 * i + 3] = (dz - z * dot) * inv;
+}
+
+__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0u;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers --
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const Workspace& ws, const float* center, const float* scale,
+                             const float* quat, int P, hipStream_t s) {
+  hipLaunchKernelGGL(preprocess_kernel, dim3((P + 127) / 128), dim3(128), 0, s, center, scale, quat,
+                     ws.geo, P);
+  return hipGetLastError();
+}
+
+static inline unsigned packet_blocks(int64_t R) {
+  int64_t packets = (R + kWave - 1) / kWave;
+  return (unsigned)((packets + 3) / 4);
+}
+
+hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float* ray_d,
+                             const float* center, const float* scale, const float* quat, int64_t R,
+                             int P, const msplat_opts& o, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_count_kernel, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
+                     scale, quat, (const float*)ws.geo, R, P, o, ws.ray_off, ws.prim_nhit,
+                     ws.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_scans(const Workspace& ws, int64_t R, int P, hipStream_t s) {
+  // ray_off[0] = 0 and ray_off[1..R] hold counts: inclusive scan of [1..R]
+  int64_t n = R;
+  int32_t* data = ws.ray_off + 1;
+  int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb > 0) {
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)nb), dim3(256), 0, s, data, n, ws.scan_tmp);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, s, ws.scan_tmp, nb,
+                       ws.scan_tmp + nb);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(256), 0, s, data, n,
+                       (const int32_t*)ws.scan_tmp);
+  }
+  hipLaunchKernelGGL(prim_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_nhit,
+                     ws.prim_off, ws.prim_cursor, ws.wi_off, P, (const int32_t*)ws.ray_off, R,
+                     ws.counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float* ray_d,
+                           const float* center, const float* scale, const float* quat, int64_t R,
+                           int P, const msplat_opts& o, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(bin_fill_kernel, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
+                     scale, quat, (const float*)ws.geo, R, P, o, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_composite(const Workspace& ws, int64_t R, const msplat_opts& o, float* rgb,
+                            float* trans, float* feat, int cf, hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, ws, R, o,
+                     rgb, trans, feat, cf);
+  return hipGetLastError();
+}
+
+hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat_opts& o,
+                                    const float* grad_rgb, const float* grad_trans,
+                                    const float* grad_feat, int cf, const float* trans,
+                                    hipStream_t s) {
+  if (R <= 0) return hipSuccess;
+  hipLaunchKernelGGL(composite_adjoint_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, ws,
+                     R, o, grad_rgb, grad_trans, grad_feat, cf, trans);
+  return hipGetLastError();
+}
+
+hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
+                               float* g_quat, hipStream_t s) {
+  hipLaunchKernelGGL(geo_finalize_kernel, dim3((P + 127) / 128), dim3(128), 0, s,
+                     (const float*)ws.geo, (const float*)ws.geo_grad, P, g_center, g_scale, g_quat);
+  return hipGetLastError();
+}
+
+}  // namespace msplat

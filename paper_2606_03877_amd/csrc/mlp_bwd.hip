@@ -1,0 +1,590 @@
+// Fused adjoint of the per-primitive MLP, of the hit-local compositing and of
+// the sample geometry (the paper prints no backward; this is the exact
+// derivative of the forward in mlp.hip with the discrete decisions fixed).
+//
+// Work decomposition is the forward's: one workgroup per group of up to
+// kHitsPerItem hits of one primitive, weights (forward and transposed) staged
+// in LDS, each wave walking its share of the samples in 32-column blocks.
+// Per block the wave
+//   1. recomputes the network, keeping every layer's input activations in
+//      registers (nothing is stored to memory between forward and backward);
+//   2. forms dL/d(raw outputs) from the compositing adjoint: with per-hit
+//      transmittance T_b, suffix g.S_after and total g.(hit colour) from the
+//      per-ray adjoint, dtau_k = T_{k+1} g.c_k - sum_{j>k} w_j g.c_j - g.S_after;
+//   3. runs the transposed chain delta_{j-1} = W_j^T delta_j * relu' on the
+//      matrix cores, registers to registers;
+//   4. reduces dL/dp of its samples into per-hit sums and chains them through
+//      the contact point, the chord and the frame M = diag(s)^-1 R^T.
+// Weight gradients are contractions over samples: the waves of a workgroup
+// publish delta_j and the layer inputs of their block to LDS, then each wave
+// accumulates its own 16-row strips of dW_j over all the workgroup's samples
+// in registers.  Those sums are added to global memory once per work item.
+#include "mlp_kernels.h"
+
+namespace msplat {
+
+namespace {
+
+template <class N>
+struct Bwd {
+  static constexpr int NW = N::BF16 ? 4 : 2;        // waves per workgroup
+  static constexpr int XS = 32 * NW;                // samples per exchange round
+  static constexpr int ESZ = N::BF16 ? 2 : 4;       // exchange element bytes
+  static constexpr int XSP = XS + (N::BF16 ? 8 : 4);  // padded row (elements)
+  static constexpr int mx(int a, int b) { return a > b ? a : b; }
+  static constexpr int HROWS = mx(rup(N::IN + 1, 16), rup(N::W, 16));
+  static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
+  static constexpr int XH_OFF = N::total_bytes();
+  static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
+  static constexpr int LDS = XD_OFF + DROWS * XSP * ESZ;
+  // weight-gradient tiles (16 x 16) of layer j
+  static constexpr int inp(int j) { return j == 0 ? N::IN + 1 : N::W; }
+  static constexpr int RT(int j) { return (N::fout(j) + 15) / 16; }
+  static constexpr int CT(int j) { return (inp(j) + 15) / 16; }
+  static constexpr int CTB(int j) { return CT(j) + (j > 0 ? 1 : 0); }
+  static constexpr int OWN(int j) { return (RT(j) + NW - 1) / NW; }
+  static constexpr int TOFF(int j) { return j == 0 ? 0 : TOFF(j - 1) + OWN(j - 1) * CTB(j - 1); }
+  static constexpr int TT = TOFF(N::NL);
+};
+
+template <class N>
+using BT = typename Operands<N>::BT;
+
+// D registers -> B operand (no activation), first NSLOT slots
+template <class N, int NSLOT, int RB>
+__device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB], BT<N> (&B)[rup(rup(NSLOT, N::KSTEP) / N::KSTEP, N::KGRP)]) {
+  constexpr int KS = rup(NSLOT, N::KSTEP) / N::KSTEP;
+  if constexpr (N::BF16) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int t = 8 * s + e;
+        v[e] = (__bf16)acc[t / 16][t % 16];
+      }
+      B[s] = v;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < rup(KS, N::KGRP); ++s) B[s] = s < KS ? acc[s / 16][s % 16] : 0.f;
+  }
+}
+
+// transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j)
+template <class N, int J>
+__device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ lds, int lane,
+                                          const BT<N> (&B)[rup(N::bks(J), N::KGRP)],
+                                          f32x16 (&acc)[N::brb(J)]) {
+  constexpr int RB = N::brb(J);
+  constexpr int NG = N::groups(N::bks(J));
+  const uint8_t* A = lds + N::bwdA_off(J);
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    f32x16 c;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) c[e] = 0.f;
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+      uint4 raw = lds16(A + ((rb * NG + gi) * 64 + lane) * 16);
+      if constexpr (N::BF16) {
+        c = mfma32(as_bf16x8(raw), B[gi], c);
+      } else {
+        f32x4 a4 = as_f32x4(raw);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B[4 * gi + e], c);
+      }
+    }
+    acc[rb] = c;
+  }
+}
+
+template <class N>
+__device__ __forceinline__ float bval(const BT<N>& v, int e) {
+  if constexpr (N::BF16) return (float)v[e]; else return v;
+}
+
+// publish this wave's 32 columns of a layer input (slots -> canonical rows)
+template <class N, int J, int NKS>
+__device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const BT<N> (&a)[NKS], int g,
+                                              int colx, bool valid) {
+  using B = Bwd<N>;
+#pragma unroll
+  for (int s = 0; s < NKS; ++s) {
+#pragma unroll
+    for (int e = 0; e < N::KSTEP; ++e) {
+      int t = N::KSTEP * s + e;
+      if (N::BF16 ? (t >= (J == 0 ? N::ENC_KS * 8 : N::HID_KS * 8)) : (s >= (J == 0 ? N::ENC_KS : N::HID_KS)))
+        continue;
+      int f = N::in_feat(J, g, t);
+      if (f < 0) continue;
+      float v = valid ? bval<N>(a[s], e) : 0.f;
+      if constexpr (N::BF16) {
+        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = (__bf16)v;
+      } else {
+        reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = v;
+      }
+    }
+  }
+}
+
+// publish this wave's 32 columns of delta_j (D layout -> canonical rows)
+template <class N, int J>
+__device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f32x16 (&dz)[N::frb(J)], int g,
+                                              int colx, bool valid) {
+  using B = Bwd<N>;
+#pragma unroll
+  for (int rb = 0; rb < N::frb(J); ++rb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int n = phi_std(g, 16 * rb + r);
+      if (n >= N::fout(J)) continue;
+      float v = valid ? dz[rb][r] : 0.f;
+      if constexpr (N::BF16) {
+        reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = (__bf16)v;
+      } else {
+        reinterpret_cast<float*>(lds + B::XD_OFF)[n * B::XSP + colx] = v;
+      }
+    }
+  }
+}
+
+// accumulate this wave's row strips of dW_J (and db_J) over the round
+template <class N, int J>
+__device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4* __restrict__ dacc, int q,
+                                         int lane) {
+  using B = Bwd<N>;
+  const int r16 = lane % 16, kg = lane / 16;
+#pragma unroll
+  for (int i = 0; i < B::OWN(J); ++i) {
+    int rt = q + i * B::NW;
+    if (rt >= B::RT(J)) continue;
+    f32x4* acc = dacc + B::TOFF(J) + i * B::CTB(J);
+    if constexpr (N::BF16) {
+      const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
+      const __bf16* xh = reinterpret_cast<const __bf16*>(lds + B::XH_OFF);
+      bf16x8 ones;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
+#pragma unroll
+      for (int kk = 0; kk < B::XS / 32; ++kk) {
+        int so = 32 * kk + 8 * kg;
+        bf16x8 a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
+#pragma unroll
+        for (int ct = 0; ct < B::CT(J); ++ct) {
+          bf16x8 b = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
+          acc[ct] = mfma16(a, b, acc[ct]);
+        }
+        if constexpr (J > 0) acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
+      }
+    } else {
+      const float* xd = reinterpret_cast<const float*>(lds + B::XD_OFF);
+      const float* xh = reinterpret_cast<const float*>(lds + B::XH_OFF);
+      float one = r16 == 0 ? 1.f : 0.f;
+#pragma unroll
+      for (int kk = 0; kk < B::XS / 16; ++kk) {
+        int so = 16 * kk + 4 * kg;
+        f32x4 a = *reinterpret_cast<const f32x4*>(xd + (16 * rt + r16) * B::XSP + so);
+#pragma unroll
+        for (int ct = 0; ct < B::CT(J); ++ct) {
+          f32x4 b = *reinterpret_cast<const f32x4*>(xh + (16 * ct + r16) * B::XSP + so);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[ct] = mfma16(a[e], b[e], acc[ct]);
+        }
+        if constexpr (J > 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[B::CT(J)] = mfma16(a[e], one, acc[B::CT(J)]);
+        }
+      }
+    }
+  }
+}
+
+// add this wave's weight-gradient strips of layers J.. to the global gradient
+template <class N, int J>
+__device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dacc, float* __restrict__ gm, int q,
+                                         int lane) {
+  using B = Bwd<N>;
+  const int r16 = lane % 16, rq = lane / 16;
+#pragma unroll
+  for (int i = 0; i < B::OWN(J); ++i) {
+    int rt = q + i * B::NW;
+    if (rt >= B::RT(J)) continue;
+#pragma unroll
+    for (int ct = 0; ct < B::CTB(J); ++ct) {
+      f32x4 v = dacc[B::TOFF(J) + i * B::CTB(J) + ct];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int n = 16 * rt + 4 * rq + r;
+        if (n >= N::fout(J) || v[r] == 0.f) continue;
+        if (ct < B::CT(J)) {
+          int f = 16 * ct + r16;
+          if (f >= B::inp(J)) continue;
+          int idx = (J == 0 && f == N::IN) ? N::off_b(0) + n : N::off_w(J) + n * N::fin(J) + f;
+          atomicAdd(gm + idx, v[r]);
+        } else if (r16 == 0) {
+          atomicAdd(gm + N::off_b(J) + n, v[r]);
+        }
+      }
+    }
+  }
+  if constexpr (J + 1 < N::NL) flush_dw<N, J + 1>(dacc, gm, q, lane);
+}
+
+struct BwdArgs {
+  Workspace ws;
+  msplat_opts opt;
+  int P;
+  int n_params;
+  const float* ray_d;
+  const float* grad_rgb;
+  const float* grad_feat;
+  float* g_mlp;
+};
+
+template <class N>
+struct Keep {
+  float ev[N::ENC_KS * N::KSTEP];
+  BT<N> a0[rup(N::ENC_KS, N::KGRP)];
+  BT<N> ah[N::NL - 1][rup(N::HID_KS, N::KGRP)];
+};
+
+// forward recompute keeping every layer input
+template <class N, int J>
+__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ lds, int lane, Keep<N>& kp,
+                                           f32x16 (&acc)[N::RBH], f32x16& out) {
+  if constexpr (J < N::NL - 1) {
+    relu_to_B<N>(acc, kp.ah[J - 1]);
+    layer_fwd<N, J, N::HID_KS>(lds, lane, kp.ah[J - 1], acc);
+    chain_keep<N, J + 1>(lds, lane, kp, acc, out);
+  } else {
+    relu_to_B<N>(acc, kp.ah[J - 1]);
+    f32x16 o[1];
+    layer_fwd<N, J, N::HID_KS>(lds, lane, kp.ah[J - 1], o);
+    out = o[0];
+  }
+}
+
+template <class N>
+__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, int lane, const float p[3],
+                                               Keep<N>& kp) {
+  int g = lane / 32;
+  encode_slots<N>(p, g, kp.ev);
+  if constexpr (N::BF16) {
+#pragma unroll
+    for (int s = 0; s < N::ENC_KS; ++s) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)kp.ev[8 * s + e];
+      kp.a0[s] = v;
+    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < rup(N::ENC_KS, N::KGRP); ++s) kp.a0[s] = s < N::ENC_KS ? kp.ev[s] : 0.f;
+  }
+  f32x16 acc[N::RBH];
+  layer_fwd<N, 0, N::ENC_KS>(lds, lane, kp.a0, acc);
+  f32x16 out;
+  chain_keep<N, 1>(lds, lane, kp, acc, out);
+  return out;
+}
+
+// backward through layers J..0 with the weight-gradient exchange
+template <class N, int J>
+__device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, int q, int colx, bool valid,
+                                           const Keep<N>& kp, const f32x16 (&dz)[N::frb(J)],
+                                           f32x16 (&da0)[N::RB0], f32x4* __restrict__ dacc) {
+  const int g = lane / 32;
+  publish_delta<N, J>(lds, dz, g, colx, valid);
+  if constexpr (J == 0) publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, kp.a0, g, colx, valid);
+  else publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx, valid);
+  // transposed product for the next delta, overlapping the exchange
+  BT<N> Bd[rup(N::bks(J), N::KGRP)];
+  if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
+  else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
+  f32x16 da[N::brb(J)];
+  layer_bwd<N, J>(lds, lane, Bd, da);
+  __syncthreads();
+  dw_tiles<N, J>(lds, dacc, q, lane);
+  __syncthreads();
+  if constexpr (J > 0) {
+    // relu': the layer input a_J = relu(z_{J-1}) is positive where z_{J-1} is
+    f32x16 dzn[N::RBH];
+#pragma unroll
+    for (int rb = 0; rb < N::RBH; ++rb) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int t = 16 * rb + r;
+        float a = bval<N>(kp.ah[J - 1][t / N::KSTEP], t % N::KSTEP);
+        dzn[rb][r] = a > 0.f ? da[rb][r] : 0.f;
+      }
+    }
+    chain_back<N, J - 1>(lds, lane, q, colx, valid, kp, dzn, da0, dacc);
+  } else {
+#pragma unroll
+    for (int rb = 0; rb < N::RB0; ++rb) da0[rb] = da[rb];
+  }
+}
+
+template <class N>
+__global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
+  using B = Bwd<N>;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ int rounds_s[B::NW];
+  const Workspace& ws = args.ws;
+  const int lane = threadIdx.x % 64;
+  const int q = threadIdx.x / 64;
+  const int col = lane % 32;
+  const int g = lane / 32;
+  const int colx = 32 * q + col;
+  const int wi = blockIdx.x;
+  const int p = find_prim(ws.wi_off, args.P, wi);
+  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * kHitsPerItem;
+  const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
+  const int64_t H = ws.hit_cap;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(ws.wpack + (int64_t)p * ws.wpack_bytes);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < N::total_bytes() / 16; i += blockDim.x) dst[i] = src[i];
+  }
+  const int h0 = (nh * q) / B::NW, h1 = (nh * (q + 1)) / B::NW;
+  const int c = h1 - h0;
+  int my_hit = 0, my_k = 0;
+  if (lane < c) {
+    my_hit = ws.phit[first + h0 + lane];
+    my_k = ws.hit_nused[my_hit] > 0 ? (ws.hit_k[my_hit] & kKMask) : 0;
+  }
+  int incl = wave_incl_scan(my_k);
+  int my_off = incl - my_k;
+  const int ns = __shfl(incl, 63, 64);
+  const int nblk = (ns + 31) / 32;
+  if (lane == 0) rounds_s[q] = nblk;
+  __syncthreads();
+  int rounds = 0;
+  for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
+  const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
+  f32x4 dacc[B::TT];
+#pragma unroll
+  for (int i = 0; i < B::TT; ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float gsum[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) gsum[i] = 0.f;
+  // carries of the hit-local scans from block to block
+  float cr_tau = 0.f, cr_P = 0.f, cr_geo[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) cr_geo[i] = 0.f;
+
+  for (int b = 0; b < rounds; ++b) {
+    const int x = 32 * b + col;
+    const bool valid = x < ns;
+    int slot = 0;
+    for (int l = 1; l < c; ++l)
+      if (__shfl(my_off, l, 64) <= x) slot = l;
+    const int hit = __shfl(my_hit, slot, 64);
+    const int K = __shfl(my_k, slot, 64);
+    const int k = valid ? x - __shfl(my_off, slot, 64) : 0;
+    const int ray = ws.hit_ray[hit];
+    float u = 0.5f;
+    if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
+    const float dlt = ws.hit_dlt[hit];
+    const float sk = __builtin_fmaf((float)k + u, dlt, ws.hit_sa[hit]);
+    float pc[3], ee[3], pl[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = ws.hit_pc[a * H + hit];
+      ee[a] = ws.hit_e[a * H + hit];
+      pl[a] = __builtin_fmaf(sk, ee[a], pc[a]);
+    }
+    Keep<N> kp;
+    f32x16 o = forward_keep<N>(lds, lane, pl, kp);
+
+    // ---- compositing adjoint of the column ----
+    const int nused = valid ? ws.hit_nused[hit] : 0;
+    const bool used = valid && k < nused;
+    const float tb = valid ? ws.hit_tb[hit] : 0.f;
+    const float gtot = valid ? ws.hit_gtot[hit] : 0.f;
+    const float gsa = valid ? ws.hit_gsa[hit] : 0.f;
+    float gr[3] = {0.f, 0.f, 0.f};
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) gr[r] = args.grad_rgb[3 * ray + r];
+    }
+    float cc[3], sig = 0.f, sgm = 0.f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) cc[r] = sigmoidf_(o[r]);
+    if (g == 0) {
+      sig = softplusf_(o[3]);
+      sgm = sigmoidf_(o[3]);
+    }
+    float tau0 = valid ? sig * dlt : 0.f;
+    const float tau = __shfl(tau0, col, 64);
+    // g . (colour, features) of the sample: half 0 holds RGB, both halves features
+    float gcf = g == 0 ? gr[0] * cc[0] + gr[1] * cc[1] + gr[2] * cc[2] : 0.f;
+    float gfv[N::OUT_SLOTS];
+#pragma unroll
+    for (int r = 0; r < N::OUT_SLOTS; ++r) {
+      gfv[r] = 0.f;
+      if constexpr (N::CF > 0) {
+        int f = phi_std(g, r) - 4;
+        if (valid && f >= 0 && f < N::CF) {
+          gfv[r] = args.grad_feat ? args.grad_feat[(int64_t)ray * N::CF + f] : 0.f;
+          gcf += gfv[r] * o[r];
+        }
+      }
+    }
+    const float gc = gcf + __shfl_xor(gcf, 32, 64);
+    const bool head = (k == 0);
+    SegScan sc(head, col);
+    float tincl = sc.incl(tau);
+    if (!sc.seen_head) tincl += cr_tau;
+    float texcl = __shfl_up(tincl, 1, 32);
+    if (head) texcl = 0.f;
+    else if (col == 0) texcl = cr_tau;
+    const float alpha = -expm1f(-tau);
+    const float w = used ? tb * __expf(-texcl) * alpha : 0.f;
+    float P = sc.incl(w * gc);
+    if (!sc.seen_head) P += cr_P;
+    const float dtau = used ? (tb * __expf(-tincl) * gc - (gtot - P) - gsa) : 0.f;
+    // dL/d(raw outputs) in D layout (row block 0)
+    f32x16 dz[1];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dz[0][r] = 0.f;
+    if (g == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) dz[0][r] = w * gr[r] * cc[r] * (1.f - cc[r]);
+      dz[0][3] = dtau * dlt * sgm;
+    }
+#pragma unroll
+    for (int r = 0; r < N::OUT_SLOTS; ++r)
+      if constexpr (N::CF > 0) {
+        int f = phi_std(g, r) - 4;
+        if (f >= 0 && f < N::CF) dz[0][r] = w * gfv[r];
+      }
+    const float dts = dtau * sig;   // half 0: dtau * sigma (for dL/dDelta)
+
+    // ---- network adjoint and weight gradients ----
+    f32x16 da0[N::RB0];
+    chain_back<N, N::NL - 1>(lds, lane, q, colx, valid, kp, dz, da0, dacc);
+
+    // ---- dL/dp of the sample from the input-feature gradient ----
+    float dp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < N::ENC_SLOTS; ++t) {
+      float gf = da0[t / 16][t % 16];
+      if (t < 3 * N::L) {
+        int pr = t / 6, j = t % 6, a = j % 3;
+        float mul = (float)(1 << (2 * pr)) * (g ? 2.f : 1.f) * 3.14159265358979f;
+        // d sin(m p)/dp = m cos(m p); d cos(m p)/dp = -m sin(m p)
+        float dv = j < 3 ? mul * kp.ev[6 * pr + 3 + a] : -mul * kp.ev[6 * pr + a];
+        dp[a] += gf * dv;
+      } else {
+        int a = t - 3 * N::L;
+        if (g == 0) dp[a] += gf;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dp[a] += __shfl_xor(dp[a], 32, 64);
+    if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
+
+    // ---- per-hit geometry sums ----
+    const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
+    const float om = ((float)k + u) / (float)K;
+    float gv[9] = {dp[0], dp[1], dp[2], sk * dp[0], sk * dp[1], sk * dp[2], dtk, om * dtk,
+                   __shfl(dts, col, 64)};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      gv[i] = sc.incl(gv[i]);
+      if (!sc.seen_head) gv[i] += cr_geo[i];
+    }
+    if (valid && g == 0 && k == K - 1) {
+      const float* gp = ws.geo + (int64_t)p * kGeoStride;
+      const int kraw = ws.hit_k[hit];
+      const bool clipped = (kraw & kClippedBit) != 0;
+      const float eta = ws.hit_eta[hit];
+      const float Kf = (float)K;
+      float dtb = gv[7] + gv[8] / Kf;
+      float dta = gv[6] - gv[7] - gv[8] / Kf;
+      float lam = clipped ? dtb : dtb + dta;
+      float zet = clipped ? dtb : dtb - dta;
+      float a2 = ee[0] * ee[0] + ee[1] * ee[1] + ee[2] * ee[2];
+      float kap = eta > 0.f ? zet / (eta * a2) : 0.f;
+      float dd[3] = {args.ray_d[3 * ray], args.ray_d[3 * ray + 1], args.ray_d[3 * ray + 2]};
+      // delta_c = mu - o - t_c d = -R diag(s) p_c
+      float dc[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        dc[r] = 0.f;
+#pragma unroll
+        for (int cidx = 0; cidx < 3; ++cidx) dc[r] -= gp[G_R + 3 * r + cidx] * gp[G_S + cidx] * pc[cidx];
+      }
+      float c1[3], c2[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        float gm = lam * ee[r] / a2 + kap * pc[r];
+        c1[r] = gm - gv[r];
+        c2[r] = gv[3 + r] - (lam * pc[r] + zet * eta * ee[r]) / a2;
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int cidx = 0; cidx < 3; ++cidx) gsum[3 * r + cidx] += c1[r] * dc[cidx] + c2[r] * dd[cidx];
+        gsum[9 + r] += c1[r];
+      }
+    }
+    // carries
+    cr_tau = __shfl(tincl, 31, 32);
+    cr_P = __shfl(P, 31, 32);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cr_geo[i] = __shfl(gv[i], 31, 32);
+  }
+
+  // ---- flush the weight-gradient strips ----
+  flush_dw<N, 0>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
+  // ---- flush the geometry sums ----
+#pragma unroll
+  for (int i = 0; i < 12; ++i) gsum[i] = wave_sum(gsum[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      if (gsum[i] != 0.f) atomicAdd(ws.geo_grad + (int64_t)p * 12 + i, gsum[i]);
+  }
+}
+
+}  // namespace
+
+template <class N>
+static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items, int P, int n_params,
+                           const float* ray_d, const float* grad_rgb, const float* grad_feat,
+                           float* g_mlp, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  BwdArgs a{ws, o, P, n_params, ray_d, grad_rgb, grad_feat, g_mlp};
+  size_t lds = Bwd<N>::LDS;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)mlp_backward_kernel<N>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(mlp_backward_kernel<N>, dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
+                                    const float* ray_d, const float* grad_rgb, const float* grad_feat,
+                                    float* g_mlp, hipStream_t s) {
+#define X(L_, W_, D_, O_, B_)                                                                              \
+  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && (n.prec == MSPLAT_BF16) == B_)              \
+    return bwd_impl<Net<L_, W_, D_, O_, B_>>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, grad_feat, \
+                                             g_mlp, s);
+  X(4, 32, 2, 4, false)
+  X(4, 32, 2, 4, true)
+  X(6, 64, 3, 4, false)
+  X(6, 64, 3, 4, true)
+  X(6, 64, 3, 20, false)
+  X(6, 64, 3, 20, true)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace msplat

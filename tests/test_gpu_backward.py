@@ -1,0 +1,87 @@
+"""GPU parity of the backward pass (through the C ABI and the autograd
+Function) against the oracle's analytic gradient."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_cases import (gpu_render, opts_of, oracle_model, oracle_opts, scene, spec_of, to_dev,
+                       view_rays)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(0, 40, 36), (1, 64, 50), (4, 44, 40)]
+KEYS = ("center", "scale", "quat", "mlp")
+
+
+def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, w, h)
+    opts = opts_of(cfg, t_stop=t_stop)
+    R = len(o)
+    rng = np.random.default_rng(1000 * ci + 4)
+    g_rgb = (rng.standard_normal((R, 3)) / R).astype(np.float32)
+    g_tr = (rng.standard_normal(R) / R).astype(np.float32) if with_trans else None
+    _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
+                                            oracle_model(cfg), oracle_opts(opts), grad_rgb=g_rgb,
+                                            grad_trans=g_tr)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    t, to, td = g["dev"]
+    gt = None if g_tr is None else torch.from_numpy(g_tr).cuda()
+    gc, gs, gq, gm = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                            torch.from_numpy(g_rgb).cuda(), gt)
+    got = {"center": gc.cpu().numpy(), "scale": gs.cpu().numpy(), "quat": gq.cpu().numpy(),
+           "mlp": gm.cpu().numpy()}
+    return got, ref, sc
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("ci,w,h", CASES)
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
+def test_gradients_match_oracle(ci, w, h, precision, tol):
+    got, ref, sc = _grads(ci, precision, w, h)
+    errs = {k: _rel(got[k], ref[k]) for k in KEYS}
+    print(f"config {ci} {precision} rel errors {errs}")
+    for k in KEYS:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+def test_transmittance_gradient_and_quaternion_orthogonality():
+    got, ref, sc = _grads(1, "fp32", 48, 40, with_trans=True)
+    for k in KEYS:
+        assert _rel(got[k], ref[k]) <= 1e-5, k
+    dots = np.abs((got["quat"] * sc["quat"]).sum(1))
+    assert dots.max() <= 1e-5 * np.abs(got["quat"]).max()
+
+
+def test_autograd_function_mse_matches_direct_backward():
+    from paper_2606_03877_amd import Renderer, render
+    ci = 1
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 48, 40)
+    opts = opts_of(cfg)
+    r = Renderer(spec_of(cfg, "fp32"), opts)
+    t, to, td = to_dev(sc, o, d)
+    params = {k: t[k].clone().requires_grad_(True) for k in KEYS}
+    target = torch.rand((len(o), 3), device="cuda")
+    rgb, trans, feat = render(r, params["center"], params["scale"], params["quat"], params["mlp"], to, td)
+    loss = ((rgb - target) ** 2).mean()
+    loss.backward()
+    g_rgb = (2.0 / rgb.numel()) * (rgb.detach() - target)
+    _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    direct = r.backward(ws, t["center"], t["scale"], t["quat"], t["mlp"], to, td, g_rgb)
+    for k, dv in zip(KEYS, direct):
+        np.testing.assert_allclose(params[k].grad.cpu().numpy(), dv.cpu().numpy(), rtol=1e-4,
+                                   atol=1e-6 * float(dv.abs().max()))
+    # and against the oracle's MSE gradient
+    _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
+                                            oracle_model(cfg), oracle_opts(opts),
+                                            target_rgb=target.cpu().numpy().astype(np.float64))
+    for k in KEYS:
+        assert _rel(params[k].grad.cpu().numpy(), ref[k]) <= 1e-5, k

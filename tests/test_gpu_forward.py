@@ -1,0 +1,114 @@
+"""GPU parity of the forward render through the C ABI against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_cases import (compare_rgb, gpu_render, opts_of, oracle_render, scene, spec_of, to_dev,
+                       view_rays)
+
+pytestmark = pytest.mark.gpu
+
+# (config, width, height): small frames that span several 8x8 tiles and a
+# ragged tail of rays (counts not a multiple of 64)
+CASES = [(0, 64, 64), (1, 100, 75), (4, 90, 70)]
+
+
+def _case(ci, w, h, t_stop=None):
+    sc = scene(ci)
+    o, d = view_rays(ci, w, h)
+    opts = opts_of(synth.CONFIGS[ci], t_stop=t_stop)
+    return sc, o, d, opts
+
+
+@pytest.mark.parametrize("ci,w,h", CASES)
+def test_hit_lists_are_bit_exact(ci, w, h):
+    sc, o, d, opts = _case(ci, w, h)
+    ref = oracle_render(ci, sc, o, d, opts)
+    g = gpu_render(ci, "fp32", sc, o, d, opts)
+    print(f"config {ci} {w}x{h}: hits {len(g['prim'])} fallbacks {g['stats']['num_fallbacks']} "
+          f"min|g| {g['stats']['min_abs_g']:.3g}")
+    np.testing.assert_array_equal(g["ray_off"], ref["ray_off"])
+    np.testing.assert_array_equal(g["prim"], ref["prim"])
+
+
+@pytest.mark.parametrize("ci,w,h", CASES)
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
+def test_forward_matches_oracle(ci, w, h, precision, tol):
+    sc, o, d, opts = _case(ci, w, h)
+    ref = oracle_render(ci, sc, o, d, opts)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    c = compare_rgb(g, ref, tol, opts.t_stop)
+    print(f"config {ci} {precision}: {c}")
+    assert c["max_err"] <= tol
+    assert c["max_terr"] <= max(tol, 1e-5) * 4
+    # a cut that falls on a neighbouring sample changes the pixel by < T_stop
+    assert c["cut_mismatch_err"] <= opts.t_stop + tol
+    assert c["n_cut_mismatch"] <= max(1, len(o) // 1000)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
+def test_full_frame_800_sampled_rays(precision, tol):
+    """Config 1 at its full 800x800 size, checked on 1024 seeded pixels."""
+    ci = 1
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d, _ = synth.make_rays(cfg)
+    opts = opts_of(cfg)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    idx = np.sort(np.random.default_rng(77).choice(len(o), 1024, replace=False))
+    # make sure sampled rays include hits
+    ref = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx)
+    c = compare_rgb(g, ref, tol, opts.t_stop, idx=idx)
+    print(f"800x800 {precision}: {c} stats {g['stats']}")
+    assert c["max_err"] <= tol
+
+
+def test_forward_is_deterministic_and_label_invariant():
+    ci, w, h = 1, 100, 75
+    sc, o, d, opts = _case(ci, w, h)
+    a = gpu_render(ci, "fp32", sc, o, d, opts)
+    b = gpu_render(ci, "fp32", sc, o, d, opts)
+    np.testing.assert_array_equal(a["rgb"], b["rgb"])
+    perm = np.random.default_rng(3).permutation(synth.CONFIGS[ci].num_prims)
+    sc2 = {k: np.ascontiguousarray(v[perm]) for k, v in sc.items()}
+    c = gpu_render(ci, "fp32", sc2, o, d, opts)
+    np.testing.assert_array_equal(a["rgb"], c["rgb"])
+    np.testing.assert_array_equal(perm[c["prim"]], a["prim"])
+
+
+def test_rays_that_miss_and_empty_batch():
+    ci = 0
+    sc = scene(ci)
+    o = np.tile(np.array([[0.0, 0.0, 5.0]], np.float32), (100, 1))
+    d = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (100, 1))
+    opts = opts_of(synth.CONFIGS[ci])
+    g = gpu_render(ci, "fp32", sc, o, d, opts)
+    assert len(g["prim"]) == 0
+    np.testing.assert_array_equal(g["rgb"], 0.0)
+    np.testing.assert_array_equal(g["trans"], 1.0)
+    from paper_2606_03877_amd import Renderer
+    r = Renderer(spec_of(synth.CONFIGS[ci], "fp32"), opts)
+    t, to, td = to_dev(sc, o[:0], d[:0])
+    rgb, trans, feat, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    assert rgb.shape == (0, 3)
+
+
+def test_small_workspace_reports_capacity_then_succeeds():
+    from paper_2606_03877_amd import Renderer, msplat_render_forward
+    from paper_2606_03877_amd import _lib
+    ci, w, h = 1, 100, 75
+    sc, o, d, opts = _case(ci, w, h)
+    r = Renderer(spec_of(synth.CONFIGS[ci], "fp32"), opts)
+    t, to, td = to_dev(sc, o, d)
+    ws = r.new_workspace(len(o), hits=10)
+    R = len(o)
+    rgb = torch.empty((R, 3), device="cuda")
+    trans = torch.empty((R,), device="cuda")
+    st, need = msplat_render_forward(r.ctx, r.spec, r.opts, t["center"], t["scale"], t["quat"], t["mlp"],
+                                     to, td, rgb, trans, None, ws)
+    assert st == _lib.MSPLAT_E_CAPACITY and need > ws.numel()
+    ws2 = torch.empty(need, dtype=torch.uint8, device="cuda")
+    st, _ = msplat_render_forward(r.ctx, r.spec, r.opts, t["center"], t["scale"], t["quat"], t["mlp"],
+                                  to, td, rgb, trans, None, ws2)
+    assert st == _lib.MSPLAT_OK
