@@ -43,7 +43,10 @@ typedef enum msplat_status {
 
 typedef enum msplat_precision {
   MSPLAT_FP32 = 0, /* MLP products and sums in float32 (matrix cores, f32 operands) */
-  MSPLAT_BF16 = 1  /* MLP operands in bfloat16 on the matrix cores, float32 accumulation */
+  MSPLAT_BF16 = 1, /* MLP operands in bfloat16 on the matrix cores, float32 accumulation */
+  MSPLAT_BF16X3 = 2 /* weights and activations as hi + lo bfloat16 pairs, products
+                       hi*hi + hi*lo + lo*hi on the matrix cores, float32 accumulation
+                       (about 16 significant bits; three times the matrix work) */
 } msplat_precision;
 
 /*

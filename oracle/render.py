@@ -36,7 +36,7 @@ import torch
 from .pcg import sample_offsets
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
-           "encode", "mlp_apply", "render"]
+           "encode", "mlp_apply", "relu_margin", "render"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -151,6 +151,37 @@ def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model) -> torch.Tenso
         if li < len(dims) - 1:
             h = _where(h.real > 0, h, torch.zeros_like(h))
     return h
+
+
+def relu_margin(theta, x, model: Model) -> np.ndarray:
+    """Relative distance of every ReLU gate from its switching point.
+
+    For each row of ``x`` (encoded samples) and each hidden unit j of each
+    hidden layer, with layer input h, z_j = W_j . h + b_j; the margin of the
+    unit is |z_j| / (sum_i |W_ji h_i| + |b_j|), and the row's margin is the
+    smallest over all hidden units.  Perturbing every weight, bias and input
+    of a layer by a relative amount below the margin cannot change the sign of
+    any z_j of that layer, so a gate whose margin is below the rounding level
+    of an implementation is a decision that implementation may take either
+    way (the gradient is discontinuous there).  Float64, no autograd.
+    """
+    th = np.asarray(theta.detach().real if torch.is_tensor(theta) else theta, np.float64)
+    h = np.asarray(x.detach().real if torch.is_tensor(x) else x, np.float64)
+    m = np.full(h.shape[0], np.inf)
+    off = 0
+    dims = model.layer_dims()
+    for fi, fo in dims[:-1]:
+        w = th[off:off + fi * fo].reshape(fo, fi)
+        off += fi * fo
+        b = th[off:off + fo]
+        off += fo
+        z = h @ w.T + b
+        scale = np.abs(h) @ np.abs(w).T + np.abs(b)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(scale > 0, np.abs(z) / scale, np.inf)
+        m = np.minimum(m, r.min(1))
+        h = np.maximum(z, 0.0)
+    return m
 
 
 def _softplus(o):
@@ -270,8 +301,12 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     n_used = used.sum(1).numpy()
     samples = None
     if keep_samples:
+        margin = np.full(len(hs), np.inf)
+        for p in np.unique(sprim):
+            idx = np.nonzero(sprim == p)[0]
+            margin[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model)
         samples = {"hit": hs, "k": kk, "u": u, "t": tk, "p": pk, "c": col, "sigma": sig,
-                   "f": feat, "tau": tau, "ray": sray}
+                   "f": feat, "tau": tau, "ray": sray, "relu_margin": margin}
     return _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples)
 
 

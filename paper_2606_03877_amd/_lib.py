@@ -20,6 +20,7 @@ MSPLAT_E_STATE = 5
 
 MSPLAT_FP32 = 0
 MSPLAT_BF16 = 1
+MSPLAT_BF16X3 = 2
 
 c_f32p = ctypes.POINTER(ctypes.c_float)
 c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -62,7 +63,7 @@ EXPORTS = {
         ctypes.c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts),
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
-        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "msplat_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "msplat_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,

@@ -54,7 +54,7 @@ bool shape_of(const msplat_model* m, NetShape* n) {
   n->NOUT = m->out_dim;
   n->prec = m->precision;
   if (n->P < 1 || n->L < 1 || n->W < 1 || n->D < 1 || n->NOUT < 4 || n->NOUT > 20) return false;
-  if (n->prec != MSPLAT_FP32 && n->prec != MSPLAT_BF16) return false;
+  if (n->prec != MSPLAT_FP32 && n->prec != MSPLAT_BF16 && n->prec != MSPLAT_BF16X3) return false;
   int64_t in = 3 + 6 * n->L, np = 0, prev = in;
   for (int j = 0; j < n->D; ++j) {
     np += prev * n->W + n->W;
@@ -99,9 +99,13 @@ uint64_t layout(const NetShape& n, int64_t R, int64_t hcap, uint8_t* base, Works
   ws.hit_tc_lo = (float*)take(H * 4);
   ws.hit_eta = (float*)take(H * 4);
   ws.hit_sa = (float*)take(H * 4);
+  ws.hit_sa_lo = (float*)take(H * 4);
   ws.hit_dlt = (float*)take(H * 4);
+  ws.hit_dlt_lo = (float*)take(H * 4);
   ws.hit_pc = (float*)take(H * 12);
+  ws.hit_pc_lo = (float*)take(H * 12);
   ws.hit_e = (float*)take(H * 12);
+  ws.hit_e_lo = (float*)take(H * 12);
   ws.hit_tau = (float*)take(H * 4);
   ws.hit_cloc = (float*)take(H * 4 * nc);
   ws.hit_sb_hi = (float*)take(H * 4);
@@ -468,10 +472,23 @@ int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const mspl
                               const double* mlp, const double* ray_o, const double* ray_d,
                               int64_t R, double* rgb, double* trans, double* feat, void* wsp,
                               uint64_t ws_bytes, uint64_t* need_bytes, void* stream) {
-  (void)ctx; (void)m; (void)o; (void)center; (void)scale; (void)quat; (void)mlp; (void)ray_o;
-  (void)ray_d; (void)R; (void)rgb; (void)trans; (void)feat; (void)wsp; (void)ws_bytes;
-  (void)need_bytes; (void)stream;
-  return MSPLAT_E_UNSUPPORTED;
+  NetShape n;
+  if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
+  if (R > 0 && (!ray_o || !ray_d || !rgb || !trans)) return MSPLAT_E_INVALID;
+  if (n.NOUT > 4 && R > 0 && !feat) return MSPLAT_E_INVALID;
+  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  if (need_bytes) *need_bytes = 256;
+  if (ws_bytes < 256) return MSPLAT_E_CAPACITY;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  HIPCHK(launch_forward_f64(n, *o, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, wsp,
+                            ws_bytes, 0, s));
+  HIPCHK(hipMemcpyAsync(ctx->host_ctr, wsp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // more hits on one ray than the float64 checker keeps: refuse rather than truncate
+  if (*reinterpret_cast<int32_t*>(ctx->host_ctr) != 0) return MSPLAT_E_CAPACITY;
+  return MSPLAT_OK;
 }
 
 }  // extern "C"

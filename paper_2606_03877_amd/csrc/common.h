@@ -63,10 +63,16 @@ struct Workspace {
   float* hit_tc_hi;
   float* hit_tc_lo;
   float* hit_eta;
+  // sample geometry of a hit as double-float pairs (hi in the first array,
+  // lo in the second): sample k sits at p_c + s_k e with s_k = s_a + (k+u) Delta
   float* hit_sa;         // t_a - t_c
+  float* hit_sa_lo;
   float* hit_dlt;        // bin width Delta = (t_b - t_a) / K
+  float* hit_dlt_lo;
   float* hit_pc;         // [3][H] contact point in the local frame (SoA)
+  float* hit_pc_lo;      // [3][H]
   float* hit_e;          // [3][H] M d (SoA)
+  float* hit_e_lo;       // [3][H]
   float* hit_tau;        // optical depth of the whole hit (or of its used part)
   float* hit_cloc;       // [NC][H] hit-local colour (and feature) sums
   float* hit_sb_hi;      // optical depth before the hit (double-float)

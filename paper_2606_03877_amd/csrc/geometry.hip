@@ -549,40 +549,55 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
     const float* gp = geo + (int64_t)p * kGeoStride;
     const float* Mh = gp + G_M_HI;
     const float* Ml = gp + G_M_LO;
-    float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j], eta = ws.hit_eta[j];
+    float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j];
     int kk = ws.hit_k[j];
     bool clipped = kk < 0;
     int K = clipped ? -kk : kk;
-    // residual delta = (mu - o) - t_c d, accurate to a few ulps of |delta|
-    float dd[3] = {d.x, d.y, d.z};
-    float oo[3] = {o.x, o.y, o.z};
-    float dl[3];
-    for (int k = 0; k < 3; ++k) {
-      df v = two_sum(gp[G_MU + k], -oo[k]);
-      float t = __builtin_fmaf(-tch, dd[k], v.hi);
-      dl[k] = __builtin_fmaf(-tcl, dd[k], t) + v.lo;
-    }
+    // residual delta = (mu - o) - t_c d and the local contact point
+    // p_c = -M delta and direction e = M d, all as double-floats: sample
+    // positions feed an encoding of frequency up to 2^(L-1) pi, so their
+    // float32 rounding would be amplified into the gradients
+    const float dd[3] = {d.x, d.y, d.z};
+    const float oo[3] = {o.x, o.y, o.z};
+    const df tc = {tch, tcl};
+    df dl[3];
+    for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
+    df pcv[3], ev[3];
     for (int r = 0; r < 3; ++r) {
-      float pc = 0.f, e = 0.f;
+      df pc = {0.f, 0.f}, e = {0.f, 0.f};
       for (int c = 0; c < 3; ++c) {
-        pc = __builtin_fmaf(Mh[3 * r + c], dl[c], pc);
-        pc = __builtin_fmaf(Ml[3 * r + c], dl[c], pc);
-        e = __builtin_fmaf(Mh[3 * r + c], dd[c], e);
-        e = __builtin_fmaf(Ml[3 * r + c], dd[c], e);
+        const df m = {Mh[3 * r + c], Ml[3 * r + c]};
+        pc = df_add(pc, df_mul(m, dl[c]));
+        e = df_add(e, df_mulf(m, dd[c]));
       }
-      ws.hit_pc[r * H + j] = -pc;
-      ws.hit_e[r * H + j] = e;
+      pcv[r] = df_neg(pc);
+      ev[r] = e;
+      ws.hit_pc[r * H + j] = pcv[r].hi;
+      ws.hit_pc_lo[r * H + j] = pcv[r].lo;
+      ws.hit_e[r * H + j] = e.hi;
+      ws.hit_e_lo[r * H + j] = e.lo;
     }
-    float sa, dlt;
+    // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the same contact point
+    df gg = {1.f, 0.f}, aa = {0.f, 0.f};
+    for (int r = 0; r < 3; ++r) {
+      gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
+      aa = df_add(aa, df_mul(ev[r], ev[r]));
+    }
+    const df etad = df_sqrt(df_div(gg, aa));
+    ws.hit_eta[j] = etad.hi;
+    df sa, dlt;
+    const df Kd = {(float)K, 0.f};
     if (clipped) {
-      sa = -(tch + tcl);
-      dlt = ((tch + eta) + tcl) / (float)K;
+      sa = df_neg(tc);
+      dlt = df_div(df_add(tc, etad), Kd);
     } else {
-      sa = -eta;
-      dlt = 2.f * eta / (float)K;
+      sa = df_neg(etad);
+      dlt = df_div(df_mulf(etad, 2.f), Kd);
     }
-    ws.hit_sa[j] = sa;
-    ws.hit_dlt[j] = dlt;
+    ws.hit_sa[j] = sa.hi;
+    ws.hit_sa_lo[j] = sa.lo;
+    ws.hit_dlt[j] = dlt.hi;
+    ws.hit_dlt_lo[j] = dlt.lo;
     ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
     ws.hit_ray[j] = (int32_t)ray;
     int slot = atomicAdd(&ws.prim_cursor[p], 1);

@@ -27,126 +27,99 @@ __global__ void pack_weights_kernel(const float* __restrict__ mlp, uint8_t* __re
   int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (int64_t)P * NG16) return;
   int p = (int)(gid / NG16);
-  int grp = (int)(gid % NG16);
-  int byte = grp * 16;
+  int byte = (int)(gid % NG16) * 16;
   const float* th = mlp + (int64_t)p * N::n_params();
   uint8_t* dst = wpack + (int64_t)p * wpack_bytes + byte;
-  float vals[8];
-  int nv = 4;
-  bool bf = false;
-  // locate the section
-  bool done = false;
+  float vals[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  bool is_bias = false;
+  int part = 0;   // 0: value (or hi part), 1: lo part of a split operand
 #pragma unroll
   for (int j = 0; j < N::NL; ++j) {
-    if (!done && byte >= N::fwdA_off(j) && byte < N::fwdA_off(j) + N::fwdA_bytes(j)) {
-      int q = (byte - N::fwdA_off(j)) / 16;          // [rb][grp][lane]
-      int lane = q % 64;
-      int gi = (q / 64) % N::groups(N::fks(j));
-      int rb = q / 64 / N::groups(N::fks(j));
-      int n = 32 * rb + lane % 32;
-      int g = lane / 32;
-      if (N::BF16) {
-        bf = true;
-        nv = 8;
-        for (int e = 0; e < 8; ++e) vals[e] = net_weight<N>(th, j, n, N::in_feat(j, g, 8 * gi + e));
-      } else {
-        for (int e = 0; e < 4; ++e) {
-          int s = 4 * gi + e;
-          vals[e] = s < N::fks(j) ? net_weight<N>(th, j, n, N::in_feat(j, g, s)) : 0.f;
+    const bool in_f = byte >= N::fwdA_off(j) && byte < N::fwdA_off(j) + N::fwdA_bytes(j);
+    const bool in_b = byte >= N::bwdA_off(j) && byte < N::bwdA_off(j) + N::bwdA_bytes(j);
+    if (in_f || in_b) {
+      const int single = in_f ? N::fwdA_single(j) : N::bwdA_single(j);
+      const int rel = byte - (in_f ? N::fwdA_off(j) : N::bwdA_off(j));
+      part = rel / single;
+      const int q = (rel % single) / 16;          // [rb][group][lane]
+      const int ng = N::groups(in_f ? N::fks(j) : N::bks(j));
+      const int nk = in_f ? N::fks(j) : N::bks(j);
+      const int lane = q % 64, gi = (q / 64) % ng, rb = q / 64 / ng;
+      const int g = lane / 32;
+      int f_row = -1;
+      if (in_b) {                                  // transposed: rows are input features
+        int rho = 32 * rb + lane % 32;
+        if (j == 0) {
+          int gr, tr;
+          phi_std_inv(rho, gr, tr);
+          f_row = N::in_feat(0, gr, tr);
+          if (f_row == N::IN) f_row = -1;          // no gradient for the constant
+        } else {
+          f_row = rho < N::W ? rho : -1;
         }
       }
-      done = true;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (!N::BF16 && e >= 4) break;
+        const int t = N::BF16 ? 8 * gi + e : 4 * gi + e;       // slot of lane half g
+        const int s = N::BF16 ? gi : t;                        // k-step
+        if (s >= nk) continue;
+        vals[e] = in_f ? net_weight<N>(th, j, 32 * rb + lane % 32, N::in_feat(j, g, t))
+                       : net_weight<N>(th, j, phi_std(g, t), f_row);
+      }
     }
-    if (!done && j > 0 && byte >= N::bias_off(j) && byte < N::bias_off(j) + N::bias_bytes(j)) {
-      int fidx = (byte - N::bias_off(j)) / 4;        // [rb][g][16]
+    if (j > 0 && byte >= N::bias_off(j) && byte < N::bias_off(j) + N::bias_bytes(j)) {
+      is_bias = true;
+      const int fidx = (byte - N::bias_off(j)) / 4;            // [rb][g][16]
       for (int e = 0; e < 4; ++e) {
         int ff = fidx + e;
         int r = ff % 16, g = (ff / 16) % 2, rb = ff / 32;
         int n = phi_std(g, 16 * rb + r);
         vals[e] = n < N::fout(j) ? th[N::off_b(j) + n] : 0.f;
       }
-      done = true;
-    }
-    if (!done && byte >= N::bwdA_off(j) && byte < N::bwdA_off(j) + N::bwdA_bytes(j)) {
-      int q = (byte - N::bwdA_off(j)) / 16;
-      int lane = q % 64;
-      int gi = (q / 64) % N::groups(N::bks(j));
-      int rb = q / 64 / N::groups(N::bks(j));
-      int rho = 32 * rb + lane % 32;                  // input row in D layout
-      int f;
-      if (j == 0) {
-        int gr, tr;
-        phi_std_inv(rho, gr, tr);
-        f = N::in_feat(0, gr, tr);
-        if (f == N::IN) f = -1;                       // no gradient for the constant
-      } else {
-        f = rho < N::W ? rho : -1;
-      }
-      int g = lane / 32;
-      if (N::BF16) {
-        bf = true;
-        nv = 8;
-        for (int e = 0; e < 8; ++e) {
-          int n = phi_std(g, 8 * gi + e);
-          vals[e] = net_weight<N>(th, j, n, f);
-        }
-      } else {
-        for (int e = 0; e < 4; ++e) {
-          int s = 4 * gi + e;
-          int n = phi_std(g, s);
-          vals[e] = s < N::bks(j) ? net_weight<N>(th, j, n, f) : 0.f;
-        }
-      }
-      done = true;
     }
   }
-  if (bf) {
+  if (N::BF16 && !is_bias) {
     bf16x8 v;
-    for (int e = 0; e < 8; ++e) v[e] = (__bf16)vals[e];
+    for (int e = 0; e < 8; ++e) {
+      __bf16 h = (__bf16)vals[e];
+      v[e] = part == 0 ? h : (__bf16)(vals[e] - (float)h);
+    }
     *reinterpret_cast<bf16x8*>(dst) = v;
   } else {
     f32x4 v;
     for (int e = 0; e < 4; ++e) v[e] = vals[e];
     *reinterpret_cast<f32x4*>(dst) = v;
   }
-  (void)nv;
 }
 
 // full network of one 32-sample block; returns the output layer's D registers
+template <class N, int J>
+__device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ lds, int lane,
+                                               f32x16 (&acc)[N::RBH]) {
+  Act<N, rup(N::HID_KS, N::KGRP)> Bh;
+  relu_to_B<N>(acc, Bh);
+  if constexpr (J < N::NL - 1) {
+    layer_fwd<N, J, N::HID_KS>(lds, lane, Bh, acc);
+    return hidden_chain<N, J + 1>(lds, lane, acc);
+  } else {
+    f32x16 out[1];
+    layer_fwd<N, J, N::HID_KS>(lds, lane, Bh, out);
+    return out[0];
+  }
+}
+
 template <class N>
-__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ lds, int lane, const float p[3]) {
-  using BT = typename Operands<N>::BT;
+__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ lds, int lane, const float ph[3],
+                                                const float pl[3]) {
   int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
-  encode_slots<N>(p, g, ev);
-  BT B0[rup(N::ENC_KS, N::KGRP)];
-  if constexpr (N::BF16) {
-#pragma unroll
-    for (int s = 0; s < N::ENC_KS; ++s) {
-      bf16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (__bf16)ev[8 * s + e];
-      B0[s] = v;
-    }
-  } else {
-#pragma unroll
-    for (int s = 0; s < rup(N::ENC_KS, N::KGRP); ++s) B0[s] = s < N::ENC_KS ? ev[s] : 0.f;
-  }
+  encode_slots<N>(ph, pl, g, ev);
+  Act<N, rup(N::ENC_KS, N::KGRP)> B0;
+  enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
   layer_fwd<N, 0, N::ENC_KS>(lds, lane, B0, acc);
-  BT Bh[rup(N::HID_KS, N::KGRP)];
-#pragma unroll
-  for (int j = 1; j < N::NL - 1; ++j) {
-    relu_to_B<N>(acc, Bh);
-    // J must be a compile-time constant: dispatch on j
-    if (j == 1) layer_fwd<N, 1, N::HID_KS>(lds, lane, Bh, acc);
-    if constexpr (N::NL - 1 > 2) if (j == 2) layer_fwd<N, (N::NL - 1 > 2 ? 2 : 1), N::HID_KS>(lds, lane, Bh, acc);
-    if constexpr (N::NL - 1 > 3) if (j == 3) layer_fwd<N, (N::NL - 1 > 3 ? 3 : 1), N::HID_KS>(lds, lane, Bh, acc);
-  }
-  relu_to_B<N>(acc, Bh);
-  f32x16 out[1];
-  layer_fwd<N, N::NL - 1, N::HID_KS>(lds, lane, Bh, out);
-  return out[0];
+  return hidden_chain<N, 1>(lds, lane, acc);
 }
 
 // ------------------------------------------------------------- forward --
@@ -213,19 +186,20 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
     int slot = 0;
     for (int l = 1; l < c; ++l)
       if (__shfl(my_off, l, 64) <= x) slot = l;
+    // cross-lane reads run on every lane: a lane that is switched off by a
+    // branch does not serve its value to the others
     const int hit = __shfl(my_hit, slot, 64);
     const int K = __shfl(my_k, slot, 64);
-    const int k = valid ? x - __shfl(my_off, slot, 64) : 0;
+    const int hoff = __shfl(my_off, slot, 64);
+    const int k = valid ? x - hoff : 0;
     // sample position in the primitive's frame: p = p_c + (t_k - t_c) e
     const int ray = ws.hit_ray[hit];
     float u = 0.5f;
     if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
-    const float sk = __builtin_fmaf((float)k + u, dlt, ws.hit_sa[hit]);
-    float pl[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) pl[a] = __builtin_fmaf(sk, ws.hit_e[a * H + hit], ws.hit_pc[a * H + hit]);
-    f32x16 o = forward_block<N>(lds, lane, pl);
+    float ph[3], pl[3];
+    sample_position(ws, hit, k, u, ph, pl);
+    f32x16 o = forward_block<N>(lds, lane, ph, pl);
     // density of the column (held by half 0), shared with half 1
     float tau0 = valid ? softplusf_(o[3]) * dlt : 0.f;
     const float tau = __shfl(tau0, col, 64);
@@ -343,33 +317,22 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
   return hipGetLastError();
 }
 
-#define MSPLAT_NETS(X)                 \
-  X(4, 32, 2, 4, false)                \
-  X(4, 32, 2, 4, true)                 \
-  X(6, 64, 3, 4, false)                \
-  X(6, 64, 3, 4, true)                 \
-  X(6, 64, 3, 20, false)               \
-  X(6, 64, 3, 20, true)
-
-#define MSPLAT_MATCH(L_, W_, D_, O_, B_) \
-  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && (n.prec == MSPLAT_BF16) == B_)
-
 bool mlp_supported(const NetShape& n) {
-#define X(L_, W_, D_, O_, B_) MSPLAT_MATCH(L_, W_, D_, O_, B_) return true;
+#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return true;
   MSPLAT_NETS(X)
 #undef X
   return false;
 }
 
 int64_t mlp_wpack_bytes(const NetShape& n) {
-#define X(L_, W_, D_, O_, B_) MSPLAT_MATCH(L_, W_, D_, O_, B_) return Net<L_, W_, D_, O_, B_>::total_bytes();
+#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return MSPLAT_NET(L_, W_, D_, O_, P_)::total_bytes();
   MSPLAT_NETS(X)
 #undef X
   return 0;
 }
 
 hipError_t launch_pack_weights(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s) {
-#define X(L_, W_, D_, O_, B_) MSPLAT_MATCH(L_, W_, D_, O_, B_) return pack_impl<Net<L_, W_, D_, O_, B_>>(ws, mlp, n.P, s);
+#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return pack_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, mlp, n.P, s);
   MSPLAT_NETS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -377,8 +340,8 @@ hipError_t launch_pack_weights(const NetShape& n, const Workspace& ws, const flo
 
 hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
                               int mode, float* rgb, float* trans, float* feat, hipStream_t s) {
-#define X(L_, W_, D_, O_, B_) \
-  MSPLAT_MATCH(L_, W_, D_, O_, B_) return fwd_impl<Net<L_, W_, D_, O_, B_>>(ws, o, items, mode, n.P, rgb, trans, feat, s);
+#define X(L_, W_, D_, O_, P_) \
+  MSPLAT_MATCH(L_, W_, D_, O_, P_) return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, mode, n.P, rgb, trans, feat, s);
   MSPLAT_NETS(X)
 #undef X
   return hipErrorInvalidValue;

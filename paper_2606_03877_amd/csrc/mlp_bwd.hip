@@ -27,16 +27,21 @@ namespace {
 
 template <class N>
 struct Bwd {
-  static constexpr int NW = N::BF16 ? 4 : 2;        // waves per workgroup
+  // waves per workgroup (the split form's four exchange planes need the
+  // smaller round to fit the 160 KiB of LDS next to the weights)
+  static constexpr int NW = (N::BF16 && !N::SPLIT) ? 4 : 2;
   static constexpr int XS = 32 * NW;                // samples per exchange round
   static constexpr int ESZ = N::BF16 ? 2 : 4;       // exchange element bytes
   static constexpr int XSP = XS + (N::BF16 ? 8 : 4);  // padded row (elements)
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int HROWS = mx(rup(N::IN + 1, 16), rup(N::W, 16));
   static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
-  static constexpr int XH_OFF = N::total_bytes();
-  static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
-  static constexpr int LDS = XD_OFF + DROWS * XSP * ESZ;
+  static constexpr int XH_OFF = N::total_bytes();                 // layer inputs (hi parts)
+  static constexpr int XL_OFF = XH_OFF + HROWS * XSP * ESZ;        // lo parts (split form)
+  static constexpr int XD_OFF = XL_OFF + (N::SPLIT ? HROWS * XSP * ESZ : 0);  // deltas (hi)
+  static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
+  static constexpr int LDS = XDL_OFF + (N::SPLIT ? DROWS * XSP * ESZ : 0);
+  static_assert(LDS <= 160 * 1024, "LDS budget of one workgroup");
   // weight-gradient tiles (16 x 16) of layer j
   static constexpr int inp(int j) { return j == 0 ? N::IN + 1 : N::W; }
   static constexpr int RT(int j) { return (N::fout(j) + 15) / 16; }
@@ -52,29 +57,23 @@ using BT = typename Operands<N>::BT;
 
 // D registers -> B operand (no activation), first NSLOT slots
 template <class N, int NSLOT, int RB>
-__device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB], BT<N> (&B)[rup(rup(NSLOT, N::KSTEP) / N::KSTEP, N::KGRP)]) {
+__device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB],
+                                       Act<N, rup(rup(NSLOT, N::KSTEP) / N::KSTEP, N::KGRP)>& B) {
   constexpr int KS = rup(NSLOT, N::KSTEP) / N::KSTEP;
-  if constexpr (N::BF16) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      bf16x8 v;
+  for (int s = 0; s < rup(KS, N::KGRP); ++s) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        int t = 8 * s + e;
-        v[e] = (__bf16)acc[t / 16][t % 16];
-      }
-      B[s] = v;
+    for (int e = 0; e < N::KSTEP; ++e) {
+      int t = N::KSTEP * s + e;
+      act_set<N>(B, s, e, t < NSLOT ? acc[t / 16][t % 16] : 0.f);
     }
-  } else {
-#pragma unroll
-    for (int s = 0; s < rup(KS, N::KGRP); ++s) B[s] = s < KS ? acc[s / 16][s % 16] : 0.f;
   }
 }
 
 // transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j)
 template <class N, int J>
 __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ lds, int lane,
-                                          const BT<N> (&B)[rup(N::bks(J), N::KGRP)],
+                                          const Act<N, rup(N::bks(J), N::KGRP)>& B,
                                           f32x16 (&acc)[N::brb(J)]) {
   constexpr int RB = N::brb(J);
   constexpr int NG = N::groups(N::bks(J));
@@ -86,13 +85,18 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ lds, int l
     for (int e = 0; e < 16; ++e) c[e] = 0.f;
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
-      uint4 raw = lds16(A + ((rb * NG + gi) * 64 + lane) * 16);
+      const int idx = ((rb * NG + gi) * 64 + lane) * 16;
+      uint4 raw = lds16(A + idx);
       if constexpr (N::BF16) {
-        c = mfma32(as_bf16x8(raw), B[gi], c);
+        c = mfma32(as_bf16x8(raw), B.hi[gi], c);
+        if constexpr (N::SPLIT) {
+          c = mfma32(as_bf16x8(raw), B.lo[gi], c);
+          c = mfma32(as_bf16x8(lds16(A + N::bwdA_single(J) + idx)), B.hi[gi], c);
+        }
       } else {
         f32x4 a4 = as_f32x4(raw);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B[4 * gi + e], c);
+        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B.hi[4 * gi + e], c);
       }
     }
     acc[rb] = c;
@@ -106,7 +110,7 @@ __device__ __forceinline__ float bval(const BT<N>& v, int e) {
 
 // publish this wave's 32 columns of a layer input (slots -> canonical rows)
 template <class N, int J, int NKS>
-__device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const BT<N> (&a)[NKS], int g,
+__device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const Act<N, NKS>& a, int g,
                                               int colx, bool valid) {
   using B = Bwd<N>;
 #pragma unroll
@@ -118,11 +122,13 @@ __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const B
         continue;
       int f = N::in_feat(J, g, t);
       if (f < 0) continue;
-      float v = valid ? bval<N>(a[s], e) : 0.f;
       if constexpr (N::BF16) {
-        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = (__bf16)v;
+        __bf16 z = (__bf16)0.f;
+        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s][e] : z;
+        if constexpr (N::SPLIT)
+          reinterpret_cast<__bf16*>(lds + B::XL_OFF)[f * B::XSP + colx] = valid ? a.lo[s][e] : z;
       } else {
-        reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = v;
+        reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s] : 0.f;
       }
     }
   }
@@ -141,7 +147,10 @@ __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f
       if (n >= N::fout(J)) continue;
       float v = valid ? dz[rb][r] : 0.f;
       if constexpr (N::BF16) {
-        reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = (__bf16)v;
+        __bf16 h = (__bf16)v;
+        reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = h;
+        if constexpr (N::SPLIT)
+          reinterpret_cast<__bf16*>(lds + B::XDL_OFF)[n * B::XSP + colx] = (__bf16)(v - (float)h);
       } else {
         reinterpret_cast<float*>(lds + B::XD_OFF)[n * B::XSP + colx] = v;
       }
@@ -170,12 +179,25 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
       for (int kk = 0; kk < B::XS / 32; ++kk) {
         int so = 32 * kk + 8 * kg;
         bf16x8 a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
+        bf16x8 al;
+        if constexpr (N::SPLIT)
+          al = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(lds + B::XDL_OFF) +
+                                                 (16 * rt + r16) * B::XSP + so);
 #pragma unroll
         for (int ct = 0; ct < B::CT(J); ++ct) {
           bf16x8 b = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
           acc[ct] = mfma16(a, b, acc[ct]);
+          if constexpr (N::SPLIT) {
+            const __bf16* xl = reinterpret_cast<const __bf16*>(lds + B::XL_OFF);
+            bf16x8 bl = *reinterpret_cast<const bf16x8*>(xl + (16 * ct + r16) * B::XSP + so);
+            acc[ct] = mfma16(a, bl, acc[ct]);
+            acc[ct] = mfma16(al, b, acc[ct]);
+          }
         }
-        if constexpr (J > 0) acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
+        if constexpr (J > 0) {
+          acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
+          if constexpr (N::SPLIT) acc[B::CT(J)] = mfma16(al, ones, acc[B::CT(J)]);
+        }
       }
     } else {
       const float* xd = reinterpret_cast<const float*>(lds + B::XD_OFF);
@@ -245,8 +267,8 @@ struct BwdArgs {
 template <class N>
 struct Keep {
   float ev[N::ENC_KS * N::KSTEP];
-  BT<N> a0[rup(N::ENC_KS, N::KGRP)];
-  BT<N> ah[N::NL - 1][rup(N::HID_KS, N::KGRP)];
+  Act<N, rup(N::ENC_KS, N::KGRP)> a0;
+  Act<N, rup(N::HID_KS, N::KGRP)> ah[N::NL - 1];
 };
 
 // forward recompute keeping every layer input
@@ -266,22 +288,11 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ lds, int 
 }
 
 template <class N>
-__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, int lane, const float p[3],
-                                               Keep<N>& kp) {
+__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, int lane, const float ph[3],
+                                               const float pl[3], Keep<N>& kp) {
   int g = lane / 32;
-  encode_slots<N>(p, g, kp.ev);
-  if constexpr (N::BF16) {
-#pragma unroll
-    for (int s = 0; s < N::ENC_KS; ++s) {
-      bf16x8 v;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (__bf16)kp.ev[8 * s + e];
-      kp.a0[s] = v;
-    }
-  } else {
-#pragma unroll
-    for (int s = 0; s < rup(N::ENC_KS, N::KGRP); ++s) kp.a0[s] = s < N::ENC_KS ? kp.ev[s] : 0.f;
-  }
+  encode_slots<N>(ph, pl, g, kp.ev);
+  enc_to_B<N>(kp.ev, kp.a0);
   f32x16 acc[N::RBH];
   layer_fwd<N, 0, N::ENC_KS>(lds, lane, kp.a0, acc);
   f32x16 out;
@@ -299,7 +310,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, 
   if constexpr (J == 0) publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, kp.a0, g, colx, valid);
   else publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx, valid);
   // transposed product for the next delta, overlapping the exchange
-  BT<N> Bd[rup(N::bks(J), N::KGRP)];
+  Act<N, rup(N::bks(J), N::KGRP)> Bd;
   if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
   else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
   f32x16 da[N::brb(J)];
@@ -315,7 +326,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         int t = 16 * rb + r;
-        float a = bval<N>(kp.ah[J - 1][t / N::KSTEP], t % N::KSTEP);
+        float a = bval<N>(kp.ah[J - 1].hi[t / N::KSTEP], t % N::KSTEP);
         dzn[rb][r] = a > 0.f ? da[rb][r] : 0.f;
       }
     }
@@ -380,23 +391,25 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     int slot = 0;
     for (int l = 1; l < c; ++l)
       if (__shfl(my_off, l, 64) <= x) slot = l;
+    // cross-lane reads run on every lane (an inactive source lane serves garbage)
     const int hit = __shfl(my_hit, slot, 64);
     const int K = __shfl(my_k, slot, 64);
-    const int k = valid ? x - __shfl(my_off, slot, 64) : 0;
+    const int hoff = __shfl(my_off, slot, 64);
+    const int k = valid ? x - hoff : 0;
     const int ray = ws.hit_ray[hit];
     float u = 0.5f;
     if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
-    const float sk = __builtin_fmaf((float)k + u, dlt, ws.hit_sa[hit]);
-    float pc[3], ee[3], pl[3];
+    float ph[3], pl[3];
+    const float sk = sample_position(ws, hit, k, u, ph, pl);
+    float pc[3], ee[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       pc[a] = ws.hit_pc[a * H + hit];
       ee[a] = ws.hit_e[a * H + hit];
-      pl[a] = __builtin_fmaf(sk, ee[a], pc[a]);
     }
     Keep<N> kp;
-    f32x16 o = forward_keep<N>(lds, lane, pl, kp);
+    f32x16 o = forward_keep<N>(lds, lane, ph, pl, kp);
 
     // ---- compositing adjoint of the column ----
     const int nused = valid ? ws.hit_nused[hit] : 0;
@@ -573,16 +586,11 @@ static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items,
 hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
                                     const float* ray_d, const float* grad_rgb, const float* grad_feat,
                                     float* g_mlp, hipStream_t s) {
-#define X(L_, W_, D_, O_, B_)                                                                              \
-  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && (n.prec == MSPLAT_BF16) == B_)              \
-    return bwd_impl<Net<L_, W_, D_, O_, B_>>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, grad_feat, \
-                                             g_mlp, s);
-  X(4, 32, 2, 4, false)
-  X(4, 32, 2, 4, true)
-  X(6, 64, 3, 4, false)
-  X(6, 64, 3, 4, true)
-  X(6, 64, 3, 20, false)
-  X(6, 64, 3, 20, true)
+#define X(L_, W_, D_, O_, P_)                                                                   \
+  MSPLAT_MATCH(L_, W_, D_, O_, P_)                                                              \
+  return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, \
+                                                  grad_feat, g_mlp, s);
+  MSPLAT_NETS(X)
 #undef X
   return hipErrorInvalidValue;
 }

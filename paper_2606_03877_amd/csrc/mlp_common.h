@@ -43,10 +43,16 @@ __host__ __device__ constexpr int phi_enc(int L, int g, int t) {
 
 __host__ __device__ constexpr int rup(int a, int b) { return (a + b - 1) / b * b; }
 
-template <int L_, int W_, int D_, int NOUT_, bool BF16_>
+// SPLIT_: bfloat16 operands carried as a sum of two bfloat16 values (hi, lo);
+// a product of two such operands is taken as hi*hi + hi*lo + lo*hi on the
+// matrix cores with float32 accumulation (about 16 significant bits).
+template <int L_, int W_, int D_, int NOUT_, bool BF16_, bool SPLIT_ = false>
 struct Net {
   static constexpr int L = L_, W = W_, D = D_, NOUT = NOUT_;
   static constexpr bool BF16 = BF16_;
+  static constexpr bool SPLIT = SPLIT_;
+  static_assert(BF16 || !SPLIT, "split operands are a bfloat16 form");
+  static constexpr int NSPLIT = SPLIT ? 2 : 1;
   static constexpr int IN = 3 + 6 * L;
   static constexpr int NL = D + 1;
   static constexpr int CF = NOUT - 4;
@@ -75,10 +81,13 @@ struct Net {
   __host__ __device__ static constexpr int bks(int j) { return j == NL - 1 ? OUT_KS : HID_KS; }
   __host__ __device__ static constexpr int groups(int ks) { return rup(ks, KGRP) / KGRP; }
 
-  // byte sizes of the packed sections
-  __host__ __device__ static constexpr int fwdA_bytes(int j) { return frb(j) * groups(fks(j)) * 64 * 16; }
+  // byte sizes of the packed sections (a split section holds all hi parts,
+  // then all lo parts)
+  __host__ __device__ static constexpr int fwdA_single(int j) { return frb(j) * groups(fks(j)) * 64 * 16; }
+  __host__ __device__ static constexpr int bwdA_single(int j) { return brb(j) * groups(bks(j)) * 64 * 16; }
+  __host__ __device__ static constexpr int fwdA_bytes(int j) { return NSPLIT * fwdA_single(j); }
   __host__ __device__ static constexpr int bias_bytes(int j) { return j == 0 ? 0 : frb(j) * 2 * 16 * 4; }
-  __host__ __device__ static constexpr int bwdA_bytes(int j) { return brb(j) * groups(bks(j)) * 64 * 16; }
+  __host__ __device__ static constexpr int bwdA_bytes(int j) { return NSPLIT * bwdA_single(j); }
   __host__ __device__ static constexpr int fwdA_off(int j) {
     return j == 0 ? 0 : fwdA_off(j - 1) + fwdA_bytes(j - 1);
   }
@@ -114,6 +123,15 @@ __device__ __forceinline__ float net_weight(const float* th, int j, int n, int f
   return th[N::off_w(j) + n * N::fin(j) + f];
 }
 
+// Compiled networks: (pe_freqs, hidden width, hidden layers, outputs, precision).
+#define MSPLAT_NETS(X)                                                              \
+  X(4, 32, 2, 4, MSPLAT_FP32) X(4, 32, 2, 4, MSPLAT_BF16) X(4, 32, 2, 4, MSPLAT_BF16X3) \
+  X(6, 64, 3, 4, MSPLAT_FP32) X(6, 64, 3, 4, MSPLAT_BF16) X(6, 64, 3, 4, MSPLAT_BF16X3) \
+  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3)
+#define MSPLAT_NET(L_, W_, D_, O_, P_) Net<L_, W_, D_, O_, (P_) != MSPLAT_FP32, (P_) == MSPLAT_BF16X3>
+#define MSPLAT_MATCH(L_, W_, D_, O_, P_) \
+  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && n.prec == (P_))
+
 __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
@@ -134,21 +152,6 @@ __device__ __forceinline__ f32x4 as_f32x4(uint4 v) { return __builtin_bit_cast(f
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
 __device__ __forceinline__ float softplusf_(float x) {
   return fmaxf(x, 0.f) + log1pf(__expf(-fabsf(x)));
-}
-
-// sin(pi x), cos(pi x): accurate library form for float32, hardware sine
-// (argument in turns after exact reduction to [-1/2, 1/2]) for bfloat16.
-template <bool FAST>
-__device__ __forceinline__ void sincospi_(float x, float& s, float& c) {
-  if constexpr (FAST) {
-    float h = 0.5f * x;
-    float r = h - rintf(h);
-    s = __builtin_amdgcn_sinf(r);
-    c = __builtin_amdgcn_cosf(r);
-  } else {
-    s = sinpif(x);
-    c = cospif(x);
-  }
 }
 
 }  // namespace msplat

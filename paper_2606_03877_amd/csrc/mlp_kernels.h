@@ -12,9 +12,47 @@ namespace msplat {
 
 // ---------------------------------------------------------- forward chain --
 
+// sample position p = p_c + s e with s = s_a + (k + u) Delta, evaluated in
+// double-float arithmetic from the hit's double-float record; returns s (float)
+__device__ __forceinline__ float sample_position(const Workspace& ws, int hit, int k, float u, float ph[3],
+                                                 float pl[3]) {
+  const int64_t H = ws.hit_cap;
+  const df ku = two_sum((float)k, u);
+  const df dlt = {ws.hit_dlt[hit], ws.hit_dlt_lo[hit]};
+  const df s = df_add(df{ws.hit_sa[hit], ws.hit_sa_lo[hit]}, df_mul(ku, dlt));
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const df e = {ws.hit_e[a * H + hit], ws.hit_e_lo[a * H + hit]};
+    const df p = df_add(df{ws.hit_pc[a * H + hit], ws.hit_pc_lo[a * H + hit]}, df_mul(s, e));
+    ph[a] = p.hi;
+    pl[a] = p.lo;
+  }
+  return s.hi;
+}
+
+// sin(pi x), cos(pi x) of x = m (hi + lo) for a power of two m: m hi is exact,
+// its reduction modulo 2 is exact, and m lo is added to the reduced argument,
+// so the result is accurate to float32 rounding of the reduced argument
+template <bool FAST>
+__device__ __forceinline__ void sincospi_df(float hi, float lo, float m, float& s, float& c) {
+  const float xh = hi * m, xl = lo * m;
+  if constexpr (FAST) {
+    // hardware sine takes turns: x pi = 2 pi (x / 2)
+    float h = 0.5f * xh;
+    float r = (h - rintf(h)) + 0.5f * xl;
+    s = __builtin_amdgcn_sinf(r);
+    c = __builtin_amdgcn_cosf(r);
+  } else {
+    float r = (xh - 2.f * rintf(0.5f * xh)) + xl;
+    s = sinpif(r);
+    c = cospif(r);
+  }
+}
+
 // positional encoding of one sample into the lane half's input slots
 template <class N>
-__device__ __forceinline__ void encode_slots(const float p[3], int g, float (&v)[N::ENC_KS * N::KSTEP]) {
+__device__ __forceinline__ void encode_slots(const float ph[3], const float pl[3], int g,
+                                             float (&v)[N::ENC_KS * N::KSTEP]) {
 #pragma unroll
   for (int t = 0; t < N::ENC_KS * N::KSTEP; ++t) v[t] = 0.f;
 #pragma unroll
@@ -24,13 +62,13 @@ __device__ __forceinline__ void encode_slots(const float p[3], int g, float (&v)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       float s, c;
-      sincospi_<N::BF16>(p[a] * mul, s, c);
+      sincospi_df<N::BF16>(ph[a], pl[a], mul, s, c);
       v[6 * pr + a] = s;
       v[6 * pr + 3 + a] = c;
     }
   }
 #pragma unroll
-  for (int a = 0; a < 3; ++a) v[3 * N::L + a] = g == 0 ? p[a] : (a == 0 ? 1.f : 0.f);
+  for (int a = 0; a < 3; ++a) v[3 * N::L + a] = g == 0 ? ph[a] : (a == 0 ? 1.f : 0.f);
 }
 
 template <class N>
@@ -39,10 +77,29 @@ struct Operands {
   using BT = typename std::conditional<N::BF16, bf16x8, float>::type;
 };
 
+// B operands of one layer input: hi parts, and lo parts in the split form
+template <class N, int NK>
+struct Act {
+  typename Operands<N>::BT hi[NK];
+  typename Operands<N>::BT lo[N::SPLIT ? NK : 1];
+};
+
+// store x into slot e of k-step entry s (hi, and the residual as lo)
+template <class N, int NK>
+__device__ __forceinline__ void act_set(Act<N, NK>& a, int s, int e, float x) {
+  if constexpr (N::BF16) {
+    __bf16 h = (__bf16)x;
+    a.hi[s][e] = h;
+    if constexpr (N::SPLIT) a.lo[s][e] = (__bf16)(x - (float)h);
+  } else {
+    a.hi[s] = x;
+  }
+}
+
 // one dense layer on the matrix cores: acc[rb] = bias + W_j x
 template <class N, int J, int KS>
 __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ lds, int lane,
-                                          const typename Operands<N>::BT (&B)[rup(KS, N::KGRP)],
+                                          const Act<N, rup(KS, N::KGRP)>& B,
                                           f32x16 (&acc)[N::frb(J)]) {
   constexpr int RB = N::frb(J);
   constexpr int NG = N::groups(KS);
@@ -68,13 +125,19 @@ __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ lds, int l
     }
 #pragma unroll
     for (int gi = 0; gi < NG; ++gi) {
-      uint4 raw = lds16(A + ((rb * NG + gi) * 64 + lane) * 16);
+      const int idx = ((rb * NG + gi) * 64 + lane) * 16;
+      uint4 raw = lds16(A + idx);
       if constexpr (N::BF16) {
-        c = mfma32(as_bf16x8(raw), B[gi], c);
+        c = mfma32(as_bf16x8(raw), B.hi[gi], c);
+        if constexpr (N::SPLIT) {
+          bf16x8 alo = as_bf16x8(lds16(A + N::fwdA_single(J) + idx));
+          c = mfma32(as_bf16x8(raw), B.lo[gi], c);
+          c = mfma32(alo, B.hi[gi], c);
+        }
       } else {
         f32x4 a4 = as_f32x4(raw);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B[4 * gi + e], c);
+        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B.hi[4 * gi + e], c);
       }
     }
     acc[rb] = c;
@@ -84,20 +147,27 @@ __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ lds, int l
 // ReLU and conversion of a hidden layer's D registers into the next B operand
 template <class N>
 __device__ __forceinline__ void relu_to_B(const f32x16 (&acc)[N::RBH],
-                                          typename Operands<N>::BT (&B)[rup(N::HID_KS, N::KGRP)]) {
+                                          Act<N, rup(N::HID_KS, N::KGRP)>& B) {
 #pragma unroll
   for (int rb = 0; rb < N::RBH; ++rb) {
-    if constexpr (N::BF16) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        bf16x8 v;
+    for (int r = 0; r < 16; ++r) {
+      int t = 16 * rb + r;
+      act_set<N>(B, t / N::KSTEP, t % N::KSTEP, fmaxf(acc[rb][r], 0.f));
+    }
+  }
+}
+
+// encoding slots of one sample into the first layer's B operand
+template <class N>
+__device__ __forceinline__ void enc_to_B(const float (&ev)[N::ENC_KS * N::KSTEP],
+                                         Act<N, rup(N::ENC_KS, N::KGRP)>& B) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (__bf16)fmaxf(acc[rb][8 * h + e], 0.f);
-        B[2 * rb + h] = v;
-      }
-    } else {
+  for (int s = 0; s < rup(N::ENC_KS, N::KGRP); ++s) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) B[16 * rb + r] = fmaxf(acc[rb][r], 0.f);
+    for (int e = 0; e < N::KSTEP; ++e) {
+      int t = N::KSTEP * s + e;
+      act_set<N>(B, s, e, t < N::ENC_KS * N::KSTEP ? ev[t] : 0.f);
     }
   }
 }

@@ -31,10 +31,11 @@ class NetSpec:
     hidden_width: int
     hidden_layers: int
     out_dim: int
-    precision: str = "fp32"          # "fp32" | "bf16"
+    precision: str = "fp32"          # "fp32" | "bf16" | "bf16x3"
 
     def c(self) -> _lib.Model:
-        prec = {"fp32": _lib.MSPLAT_FP32, "bf16": _lib.MSPLAT_BF16}[self.precision]
+        prec = {"fp32": _lib.MSPLAT_FP32, "bf16": _lib.MSPLAT_BF16,
+                "bf16x3": _lib.MSPLAT_BF16X3}[self.precision]
         return _lib.Model(self.num_prims, self.pe_freqs, self.hidden_width, self.hidden_layers,
                           self.out_dim, prec)
 

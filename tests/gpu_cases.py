@@ -63,27 +63,47 @@ def to_dev(sc, o, d):
     return t, torch.from_numpy(np.ascontiguousarray(o)).to(dev), torch.from_numpy(np.ascontiguousarray(d)).to(dev)
 
 
-def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096):
+# Relative ReLU margin (oracle.relu_margin) below which an implementation
+# computing in the given arithmetic may take a gate either way: about eight
+# times the typical relative error of a pre-activation there (float32: a
+# 64-term dot product, ~sqrt(64) 2^-24 per layer over three layers; bfloat16
+# hi+lo pairs: ~2^-16 per product; plain bfloat16: ~2^-8).
+RELU_AMBIGUOUS = {"fp32": 1e-5, "bf16x3": 3e-5, "bf16": 2e-2}
+
+
+def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096, margins=False):
+    """Oracle forward in chunks; with ``margins`` also the smallest ReLU
+    margin over each ray's samples (``relu_margin``, inf for rays without
+    samples)."""
     cfg = synth.CONFIGS[ci]
     p = oracle.to_tensors(sc)
     oo = oracle_opts(opts)
-    rgbs, trs, fts, nus, offs, prims = [], [], [], [], [0], []
+    rgbs, trs, fts, nus, offs, prims, mrg = [], [], [], [], [0], [], []
     for s in range(0, len(o), chunk):
         e = min(len(o), s + chunk)
         ids = None if ray_ids is None else ray_ids[s:e]
         out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"],
                             torch.from_numpy(o[s:e].astype(np.float64)),
                             torch.from_numpy(d[s:e].astype(np.float64)), oracle_model(cfg), oo,
-                            ray_index_base=s, ray_ids=ids)
+                            ray_index_base=s, ray_ids=ids, keep_samples=margins)
+        if margins:
+            m = np.full(e - s, np.inf)
+            smp = out["samples"]
+            if smp is not None:
+                np.minimum.at(m, smp["ray"], smp["relu_margin"])
+            mrg.append(m)
         rgbs.append(out["rgb"].numpy())
         trs.append(out["trans"].numpy())
         fts.append(out["feat"].numpy())
         nus.append(out["n_used"])
         offs.extend((out["ray_off"][1:] + offs[-1]).tolist())
         prims.append(out["prim"])
-    return {"rgb": np.concatenate(rgbs), "trans": np.concatenate(trs), "feat": np.concatenate(fts),
-            "n_used": np.concatenate(nus), "ray_off": np.array(offs, np.int64),
-            "prim": np.concatenate(prims)}
+    res = {"rgb": np.concatenate(rgbs), "trans": np.concatenate(trs), "feat": np.concatenate(fts),
+           "n_used": np.concatenate(nus), "ray_off": np.array(offs, np.int64),
+           "prim": np.concatenate(prims)}
+    if margins:
+        res["relu_margin"] = np.concatenate(mrg)
+    return res
 
 
 def gpu_render(ci, precision, sc, o, d, opts):

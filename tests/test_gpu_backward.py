@@ -6,8 +6,8 @@ import torch
 
 import oracle
 import synth
-from gpu_cases import (gpu_render, opts_of, oracle_model, oracle_opts, scene, spec_of, to_dev,
-                       view_rays)
+from gpu_cases import (RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle_opts, oracle_render,
+                       ray_nused, scene, spec_of, to_dev, view_rays)
 
 pytestmark = pytest.mark.gpu
 
@@ -24,10 +24,24 @@ def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
     rng = np.random.default_rng(1000 * ci + 4)
     g_rgb = (rng.standard_normal((R, 3)) / R).astype(np.float32)
     g_tr = (rng.standard_normal(R) / R).astype(np.float32) if with_trans else None
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    # a termination cut on a neighbouring sample (threshold crossing within
+    # rounding) and a ReLU gate within rounding of its switching point are
+    # discrete decisions either side may take the other way: such rays carry
+    # no upstream gradient on either side
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True)
+    same = ray_nused(g) == ref_fwd["n_used"]
+    clear = ref_fwd["relu_margin"] >= RELU_AMBIGUOUS[precision]
+    print(f"rays with a different cut sample: {int((~same).sum())} of {R}; "
+          f"with a ReLU gate within rounding: {int((~clear).sum())}")
+    keep = same & clear
+    assert keep.sum() >= R // 2
+    g_rgb[~keep] = 0.0
+    if g_tr is not None:
+        g_tr[~keep] = 0.0
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
                                             oracle_model(cfg), oracle_opts(opts), grad_rgb=g_rgb,
                                             grad_trans=g_tr)
-    g = gpu_render(ci, precision, sc, o, d, opts)
     t, to, td = g["dev"]
     gt = None if g_tr is None else torch.from_numpy(g_tr).cuda()
     gc, gs, gq, gm = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
@@ -42,9 +56,19 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("ci,w,h", CASES)
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 2e-3)])
 def test_gradients_match_oracle(ci, w, h, precision, tol):
     got, ref, sc = _grads(ci, precision, w, h)
+    errs = {k: _rel(got[k], ref[k]) for k in KEYS}
+    print(f"config {ci} {precision} rel errors {errs}")
+    for k in KEYS:
+        assert errs[k] <= tol, (k, errs[k])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 2e-3)])
+def test_gradients_match_oracle_without_cut(precision, tol):
+    ci = 4
+    got, ref, sc = _grads(ci, precision, 40, 36, t_stop=0.0)
     errs = {k: _rel(got[k], ref[k]) for k in KEYS}
     print(f"config {ci} {precision} rel errors {errs}")
     for k in KEYS:
@@ -65,23 +89,33 @@ def test_autograd_function_mse_matches_direct_backward():
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
     o, d = view_rays(ci, 48, 40)
+    R = len(o)
     opts = opts_of(cfg)
     r = Renderer(spec_of(cfg, "fp32"), opts)
     t, to, td = to_dev(sc, o, d)
+    target = torch.rand((R, 3), device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    # rays whose cut or ReLU gates are decided within rounding are masked out of the loss
+    _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    off, _, _, nused = r.hits(ws, R)
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True)
+    keep = ((ray_nused({"ray_off": off, "hit_nused": nused}) == ref_fwd["n_used"])
+            & (ref_fwd["relu_margin"] >= RELU_AMBIGUOUS["fp32"]))
+    assert keep.sum() >= R // 2
+    mask = torch.from_numpy(keep.astype(np.float32)).cuda()[:, None]
     params = {k: t[k].clone().requires_grad_(True) for k in KEYS}
-    target = torch.rand((len(o), 3), device="cuda")
     rgb, trans, feat = render(r, params["center"], params["scale"], params["quat"], params["mlp"], to, td)
-    loss = ((rgb - target) ** 2).mean()
+    loss = (((rgb - target) ** 2) * mask).sum() / (3 * R)
     loss.backward()
-    g_rgb = (2.0 / rgb.numel()) * (rgb.detach() - target)
+    g_rgb = (2.0 / (3 * R)) * (rgb.detach() - target) * mask
     _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
     direct = r.backward(ws, t["center"], t["scale"], t["quat"], t["mlp"], to, td, g_rgb)
     for k, dv in zip(KEYS, direct):
         np.testing.assert_allclose(params[k].grad.cpu().numpy(), dv.cpu().numpy(), rtol=1e-4,
                                    atol=1e-6 * float(dv.abs().max()))
-    # and against the oracle's MSE gradient
+    # and against the oracle's gradient of the same masked mean-squared error
+    tg = target.cpu().numpy().astype(np.float64)
+    g_ref = (2.0 / (3 * R)) * (ref_fwd["rgb"] - tg) * keep[:, None]
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
-                                            oracle_model(cfg), oracle_opts(opts),
-                                            target_rgb=target.cpu().numpy().astype(np.float64))
+                                            oracle_model(cfg), oracle_opts(opts), grad_rgb=g_ref)
     for k in KEYS:
         assert _rel(params[k].grad.cpu().numpy(), ref[k]) <= 1e-5, k

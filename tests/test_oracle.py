@@ -508,3 +508,60 @@ def test_quaternion_gradient_is_orthogonal_to_q_and_missed_primitive_gets_zero()
     for k in ("center", "scale", "quat", "mlp"):
         assert np.all(g[k][2] == 0)
     assert np.abs(g["mlp"][0]).max() > 0
+
+
+def _one_hidden_layer(rng, L=2, W=32):
+    model = oracle.Model(pe_freqs=L, hidden_width=W, hidden_layers=1, out_dim=4)
+    theta = rng.standard_normal(model.num_params)
+    x = rng.standard_normal((64, model.in_dim))
+    return model, theta, x
+
+
+def _gates(model, theta, x):
+    fi, fo = model.layer_dims()[0]
+    w = theta[:fi * fo].reshape(fo, fi)
+    b = theta[fi * fo:fi * fo + fo]
+    return x @ w.T + b > 0, w, b
+
+
+def test_relu_margin_is_the_relative_perturbation_that_flips_a_gate():
+    """A relative perturbation of weights and bias just above the margin can
+    flip a gate; no perturbation below it can (componentwise bound on W.x + b)."""
+    rng = np.random.default_rng(11)
+    model, theta, x = _one_hidden_layer(rng)
+    m = oracle.relu_margin(theta, x, model)
+    gates, w, b = _gates(model, theta, x)
+    fi, fo = model.layer_dims()[0]
+    for row in range(0, 64, 7):
+        z = x[row] @ w.T + b
+        scale = np.abs(x[row]) @ np.abs(w).T + np.abs(b)
+        j = int(np.argmin(np.abs(z) / scale))
+        for eps, flips in ((1.01 * m[row], True), (0.99 * m[row], False)):
+            # adversarial: push unit j towards zero with every term
+            th = theta.copy()
+            sz = np.sign(z[j])
+            wj = th[:fi * fo].reshape(fo, fi)
+            wj[j] *= 1 - eps * sz * np.sign(w[j] * x[row])
+            th[fi * fo + j] *= 1 - eps * sz * np.sign(b[j])
+            g2, _, _ = _gates(model, th, x[row:row + 1])
+            assert (g2[0, j] != gates[row, j]) == flips, (row, eps)
+            if not flips:
+                # random sign patterns below the margin never flip any gate
+                for _ in range(20):
+                    th = theta.copy()
+                    th[:fi * fo + fo] *= 1 + eps * rng.choice([-1.0, 1.0], fi * fo + fo)
+                    g3, _, _ = _gates(model, th, x[row:row + 1])
+                    assert (g3[0] == gates[row]).all()
+
+
+def test_relu_margin_zero_for_a_unit_exactly_at_its_switching_point():
+    rng = np.random.default_rng(12)
+    model, theta, x = _one_hidden_layer(rng)
+    fi, fo = model.layer_dims()[0]
+    x = rng.integers(-3, 4, x.shape).astype(np.float64)
+    theta[:fi * fo] = rng.integers(-3, 4, fi * fo)
+    w = theta[:fi * fo].reshape(fo, fi)
+    theta[fi * fo + 5] = -(w[5] @ x[9])        # unit 5 of row 9 sits exactly at zero
+    m = oracle.relu_margin(theta, x, model)
+    assert m[9] == 0.0
+    assert (np.delete(m, 9) >= 0).all()
