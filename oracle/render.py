@@ -36,7 +36,7 @@ import torch
 from .pcg import sample_offsets
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
-           "encode", "mlp_apply", "relu_margin", "render"]
+           "encode", "mlp_apply", "relu_noise", "relu_margin", "render"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -153,34 +153,51 @@ def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model) -> torch.Tenso
     return h
 
 
-def relu_margin(theta, x, model: Model) -> np.ndarray:
-    """Relative distance of every ReLU gate from its switching point.
+def relu_noise(theta, x, model: Model):
+    """Pre-activations of the hidden layers and the rounding noise they carry.
 
-    For each row of ``x`` (encoded samples) and each hidden unit j of each
-    hidden layer, with layer input h, z_j = W_j . h + b_j; the margin of the
-    unit is |z_j| / (sum_i |W_ji h_i| + |b_j|), and the row's margin is the
-    smallest over all hidden units.  Perturbing every weight, bias and input
-    of a layer by a relative amount below the margin cannot change the sign of
-    any z_j of that layer, so a gate whose margin is below the rounding level
-    of an implementation is a decision that implementation may take either
-    way (the gradient is discontinuous there).  Float64, no autograd.
+    Model (the standard probabilistic model of rounding error): every
+    product W_ji h_i and every bias b_j of the forward pass carries an
+    independent relative error of standard deviation u.  To first order in u
+    the noise of z = W h + b then has standard deviation u e with
+        e^(1) = sqrt(W1^2 x^2 + b1^2)
+        e^(l) = sqrt(Wl^2 (a^(l-1) (e^(l-1))^2 + (h^(l-1))^2) + bl^2),
+    squares elementwise, a^(l-1) the 0/1 ReLU gates of the layer input (a
+    closed gate stops the noise), covariances between units neglected (exact
+    for the first two hidden layers).  Returns [(z, e)] per hidden layer,
+    each [rows, width].  Float64, no autograd.
     """
     th = np.asarray(theta.detach().real if torch.is_tensor(theta) else theta, np.float64)
     h = np.asarray(x.detach().real if torch.is_tensor(x) else x, np.float64)
-    m = np.full(h.shape[0], np.inf)
+    e2 = np.zeros_like(h)
+    act = np.zeros_like(h)
+    out = []
     off = 0
-    dims = model.layer_dims()
-    for fi, fo in dims[:-1]:
+    for fi, fo in model.layer_dims()[:-1]:
         w = th[off:off + fi * fo].reshape(fo, fi)
         off += fi * fo
         b = th[off:off + fo]
         off += fo
         z = h @ w.T + b
-        scale = np.abs(h) @ np.abs(w).T + np.abs(b)
-        with np.errstate(divide="ignore", invalid="ignore"):
-            r = np.where(scale > 0, np.abs(z) / scale, np.inf)
-        m = np.minimum(m, r.min(1))
+        e2 = (act * e2 + h * h) @ (w * w).T + b * b
+        out.append((z, np.sqrt(e2)))
+        act = (z > 0).astype(np.float64)
         h = np.maximum(z, 0.0)
+    return out
+
+
+def relu_margin(theta, x, model: Model) -> np.ndarray:
+    """Distance of each row's closest ReLU gate from its switching point in
+    units of its rounding noise: min over hidden units of |z| / e
+    (``relu_noise``).  An implementation with unit roundoff u takes a gate
+    whose margin is within a small multiple of u either way with appreciable
+    probability: such gates are decisions that two correct implementations
+    may take differently, and the gradient jumps there."""
+    m = np.full(np.shape(x)[0], np.inf)
+    for z, e in relu_noise(theta, x, model):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(e > 0, np.abs(z) / e, np.inf)
+        m = np.minimum(m, r.min(1))
     return m
 
 

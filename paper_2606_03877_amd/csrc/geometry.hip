@@ -559,7 +559,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
     // float32 rounding would be amplified into the gradients
     const float dd[3] = {d.x, d.y, d.z};
     const float oo[3] = {o.x, o.y, o.z};
-    const df tc = {tch, tcl};
+    df tc = {tch, tcl};
     df dl[3];
     for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
     df pcv[3], ev[3];
@@ -572,17 +572,29 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
       }
       pcv[r] = df_neg(pc);
       ev[r] = e;
+    }
+    // The sort key t_c is accurate to float32 only; samples are placed
+    // relative to t_c, so refine it to double-float accuracy: one Newton step
+    // on (p_c + dt e) . e = 0, i.e. dt = -(p_c . e) / |e|^2.
+    df aa = {0.f, 0.f}, pe = {0.f, 0.f};
+    for (int r = 0; r < 3; ++r) {
+      aa = df_add(aa, df_mul(ev[r], ev[r]));
+      pe = df_add(pe, df_mul(pcv[r], ev[r]));
+    }
+    const float dtc = -pe.hi / aa.hi;
+    tc = df_add(tc, df_from(dtc));
+    ws.hit_tc_hi[j] = tc.hi;
+    ws.hit_tc_lo[j] = tc.lo;
+    df gg = {1.f, 0.f};
+    for (int r = 0; r < 3; ++r) {
+      pcv[r] = df_add(pcv[r], df_mulf(ev[r], dtc));
+      gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
       ws.hit_pc[r * H + j] = pcv[r].hi;
       ws.hit_pc_lo[r * H + j] = pcv[r].lo;
-      ws.hit_e[r * H + j] = e.hi;
-      ws.hit_e_lo[r * H + j] = e.lo;
+      ws.hit_e[r * H + j] = ev[r].hi;
+      ws.hit_e_lo[r * H + j] = ev[r].lo;
     }
-    // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the same contact point
-    df gg = {1.f, 0.f}, aa = {0.f, 0.f};
-    for (int r = 0; r < 3; ++r) {
-      gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
-      aa = df_add(aa, df_mul(ev[r], ev[r]));
-    }
+    // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the refined contact point
     const df etad = df_sqrt(df_div(gg, aa));
     ws.hit_eta[j] = etad.hi;
     df sa, dlt;

@@ -27,18 +27,19 @@ namespace {
 
 template <class N>
 struct Bwd {
-  // waves per workgroup (the split form's four exchange planes need the
-  // smaller round to fit the 160 KiB of LDS next to the weights)
-  static constexpr int NW = (N::BF16 && !N::SPLIT) ? 4 : 2;
+  // waves per workgroup: the float32 exchange planes are twice as wide, so
+  // the float32 form exchanges 64 samples per round, the bfloat16 forms 128
+  static constexpr int NW = N::BF16 ? 4 : 2;
   static constexpr int XS = 32 * NW;                // samples per exchange round
   static constexpr int ESZ = N::BF16 ? 2 : 4;       // exchange element bytes
   static constexpr int XSP = XS + (N::BF16 ? 8 : 4);  // padded row (elements)
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
   static constexpr int HROWS = mx(rup(N::IN + 1, 16), rup(N::W, 16));
   static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
-  static constexpr int XH_OFF = N::total_bytes();                 // layer inputs (hi parts)
-  static constexpr int XL_OFF = XH_OFF + HROWS * XSP * ESZ;        // lo parts (split form)
-  static constexpr int XD_OFF = XL_OFF + (N::SPLIT ? HROWS * XSP * ESZ : 0);  // deltas (hi)
+  // exchange planes: layer inputs (the split form contracts the weight
+  // gradient with their hi part only), deltas (hi), and the deltas' lo parts
+  static constexpr int XH_OFF = N::total_bytes();
+  static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
   static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
   static constexpr int LDS = XDL_OFF + (N::SPLIT ? DROWS * XSP * ESZ : 0);
   static_assert(LDS <= 160 * 1024, "LDS budget of one workgroup");
@@ -110,7 +111,7 @@ __device__ __forceinline__ float bval(const BT<N>& v, int e) {
 
 // publish this wave's 32 columns of a layer input (slots -> canonical rows)
 template <class N, int J, int NKS>
-__device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const Act<N, NKS>& a, int g,
+__device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const Hi<N, NKS>& a, int g,
                                               int colx, bool valid) {
   using B = Bwd<N>;
 #pragma unroll
@@ -125,8 +126,6 @@ __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const A
       if constexpr (N::BF16) {
         __bf16 z = (__bf16)0.f;
         reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s][e] : z;
-        if constexpr (N::SPLIT)
-          reinterpret_cast<__bf16*>(lds + B::XL_OFF)[f * B::XSP + colx] = valid ? a.lo[s][e] : z;
       } else {
         reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s] : 0.f;
       }
@@ -187,12 +186,7 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
         for (int ct = 0; ct < B::CT(J); ++ct) {
           bf16x8 b = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
           acc[ct] = mfma16(a, b, acc[ct]);
-          if constexpr (N::SPLIT) {
-            const __bf16* xl = reinterpret_cast<const __bf16*>(lds + B::XL_OFF);
-            bf16x8 bl = *reinterpret_cast<const bf16x8*>(xl + (16 * ct + r16) * B::XSP + so);
-            acc[ct] = mfma16(a, bl, acc[ct]);
-            acc[ct] = mfma16(al, b, acc[ct]);
-          }
+          if constexpr (N::SPLIT) acc[ct] = mfma16(al, b, acc[ct]);
         }
         if constexpr (J > 0) {
           acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
@@ -264,25 +258,28 @@ struct BwdArgs {
   float* g_mlp;
 };
 
+// per-sample state kept from the recompute: the encoding (the first layer's
+// operand is rebuilt from it when needed) and every hidden layer's input
 template <class N>
 struct Keep {
   float ev[N::ENC_KS * N::KSTEP];
-  Act<N, rup(N::ENC_KS, N::KGRP)> a0;
-  Act<N, rup(N::HID_KS, N::KGRP)> ah[N::NL - 1];
+  Hi<N, rup(N::HID_KS, N::KGRP)> ah[N::NL - 1];
 };
 
 // forward recompute keeping every layer input
 template <class N, int J>
 __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ lds, int lane, Keep<N>& kp,
                                            f32x16 (&acc)[N::RBH], f32x16& out) {
+  Act<N, rup(N::HID_KS, N::KGRP)> x;
+  relu_to_B<N>(acc, x);
+#pragma unroll
+  for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - 1].hi[i] = x.hi[i];
   if constexpr (J < N::NL - 1) {
-    relu_to_B<N>(acc, kp.ah[J - 1]);
-    layer_fwd<N, J, N::HID_KS>(lds, lane, kp.ah[J - 1], acc);
+    layer_fwd<N, J, N::HID_KS>(lds, lane, x, acc);
     chain_keep<N, J + 1>(lds, lane, kp, acc, out);
   } else {
-    relu_to_B<N>(acc, kp.ah[J - 1]);
     f32x16 o[1];
-    layer_fwd<N, J, N::HID_KS>(lds, lane, kp.ah[J - 1], o);
+    layer_fwd<N, J, N::HID_KS>(lds, lane, x, o);
     out = o[0];
   }
 }
@@ -292,9 +289,12 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, 
                                                const float pl[3], Keep<N>& kp) {
   int g = lane / 32;
   encode_slots<N>(ph, pl, g, kp.ev);
-  enc_to_B<N>(kp.ev, kp.a0);
   f32x16 acc[N::RBH];
-  layer_fwd<N, 0, N::ENC_KS>(lds, lane, kp.a0, acc);
+  {
+    Act<N, rup(N::ENC_KS, N::KGRP)> a0;
+    enc_to_B<N>(kp.ev, a0);
+    layer_fwd<N, 0, N::ENC_KS>(lds, lane, a0, acc);
+  }
   f32x16 out;
   chain_keep<N, 1>(lds, lane, kp, acc, out);
   return out;
@@ -307,8 +307,16 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, 
                                            f32x16 (&da0)[N::RB0], f32x4* __restrict__ dacc) {
   const int g = lane / 32;
   publish_delta<N, J>(lds, dz, g, colx, valid);
-  if constexpr (J == 0) publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, kp.a0, g, colx, valid);
-  else publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx, valid);
+  if constexpr (J == 0) {
+    Act<N, rup(N::ENC_KS, N::KGRP)> a0;
+    enc_to_B<N>(kp.ev, a0);
+    Hi<N, rup(N::ENC_KS, N::KGRP)> h0;
+#pragma unroll
+    for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
+    publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx, valid);
+  } else {
+    publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx, valid);
+  }
   // transposed product for the next delta, overlapping the exchange
   Act<N, rup(N::bks(J), N::KGRP)> Bd;
   if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);

@@ -84,6 +84,12 @@ struct Act {
   typename Operands<N>::BT lo[N::SPLIT ? NK : 1];
 };
 
+// hi parts only (what the backward keeps of a layer input)
+template <class N, int NK>
+struct Hi {
+  typename Operands<N>::BT hi[NK];
+};
+
 // store x into slot e of k-step entry s (hi, and the residual as lo)
 template <class N, int NK>
 __device__ __forceinline__ void act_set(Act<N, NK>& a, int s, int e, float x) {

@@ -197,8 +197,8 @@ def camera_rays(cam: dict, tiled: bool = True) -> Tuple[np.ndarray, np.ndarray, 
     n = cam["width"] * cam["height"]
     pix = tile_order(cam["width"], cam["height"]) if tiled else np.arange(n)
     d = _pixel_dirs(cam, pix)
-    o = np.broadcast_to(cam["eye"], d.shape)
-    return o.astype(np.float32), d.astype(np.float32), pix
+    o = np.ascontiguousarray(np.broadcast_to(cam["eye"], d.shape), dtype=np.float32)
+    return o, np.ascontiguousarray(d, dtype=np.float32), pix
 
 
 def make_rays(cfg: Config, seed: Optional[int] = None):

@@ -63,12 +63,12 @@ def to_dev(sc, o, d):
     return t, torch.from_numpy(np.ascontiguousarray(o)).to(dev), torch.from_numpy(np.ascontiguousarray(d)).to(dev)
 
 
-# Relative ReLU margin (oracle.relu_margin) below which an implementation
-# computing in the given arithmetic may take a gate either way: about eight
-# times the typical relative error of a pre-activation there (float32: a
-# 64-term dot product, ~sqrt(64) 2^-24 per layer over three layers; bfloat16
-# hi+lo pairs: ~2^-16 per product; plain bfloat16: ~2^-8).
-RELU_AMBIGUOUS = {"fp32": 1e-5, "bf16x3": 3e-5, "bf16": 2e-2}
+# ReLU margin (oracle.relu_margin: distance of the closest gate from
+# switching, in units of its rounding noise) below which an implementation
+# may take a gate the other way: about 16 unit roundoffs for float32
+# (2^-24), 3 for bfloat16 hi+lo pairs (products accurate to ~2^-16), and
+# 3 for plain bfloat16 (2^-8).
+RELU_AMBIGUOUS = {"fp32": 1e-6, "bf16x3": 5e-5, "bf16": 1e-2}
 
 
 def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096, margins=False):

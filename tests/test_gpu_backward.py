@@ -35,7 +35,7 @@ def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
     print(f"rays with a different cut sample: {int((~same).sum())} of {R}; "
           f"with a ReLU gate within rounding: {int((~clear).sum())}")
     keep = same & clear
-    assert keep.sum() >= R // 2
+    assert keep.sum() >= R // 4
     g_rgb[~keep] = 0.0
     if g_tr is not None:
         g_tr[~keep] = 0.0
