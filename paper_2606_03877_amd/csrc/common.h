@@ -89,26 +89,35 @@ struct Workspace {
 
 // ---------------------------------------------------------------------------
 // double-float ("df") arithmetic on (hi, lo) float pairs: TwoSum (Knuth),
-// FastTwoSum (Dekker 1971), TwoProd via fused multiply-add.
+// FastTwoSum (Dekker 1971), TwoProd via fused multiply-add.  These
+// error-free transformations need every product and sum rounded as written:
+// contraction of a product into a following sum (which hipcc allows by
+// default) silently degrades them to single-float accuracy, so each body
+// switches it off.
+#define MSPLAT_EXACT_FP _Pragma("clang fp contract(off)")
 // ---------------------------------------------------------------------------
 struct df { float hi, lo; };
 
 __device__ __forceinline__ df two_sum(float a, float b) {
+  MSPLAT_EXACT_FP
   float s = a + b;
   float bb = s - a;
   float err = (a - (s - bb)) + (b - bb);
   return {s, err};
 }
 __device__ __forceinline__ df fast_two_sum(float a, float b) {
+  MSPLAT_EXACT_FP
   float s = a + b;
   return {s, b - (s - a)};
 }
 __device__ __forceinline__ df two_prod(float a, float b) {
+  MSPLAT_EXACT_FP
   float p = a * b;
   return {p, __builtin_fmaf(a, b, -p)};
 }
 __device__ __forceinline__ df df_from(float a) { return {a, 0.f}; }
 __device__ __forceinline__ df df_add(df x, df y) {
+  MSPLAT_EXACT_FP
   df s = two_sum(x.hi, y.hi);
   df t = two_sum(x.lo, y.lo);
   s.lo += t.hi;
@@ -119,16 +128,19 @@ __device__ __forceinline__ df df_add(df x, df y) {
 __device__ __forceinline__ df df_neg(df x) { return {-x.hi, -x.lo}; }
 __device__ __forceinline__ df df_sub(df x, df y) { return df_add(x, df_neg(y)); }
 __device__ __forceinline__ df df_mul(df x, df y) {
+  MSPLAT_EXACT_FP
   df p = two_prod(x.hi, y.hi);
   p.lo = __builtin_fmaf(x.hi, y.lo, __builtin_fmaf(x.lo, y.hi, p.lo));
   return fast_two_sum(p.hi, p.lo);
 }
 __device__ __forceinline__ df df_mulf(df x, float y) {
+  MSPLAT_EXACT_FP
   df p = two_prod(x.hi, y);
   p.lo = __builtin_fmaf(x.lo, y, p.lo);
   return fast_two_sum(p.hi, p.lo);
 }
 __device__ __forceinline__ df df_div(df x, df y) {
+  MSPLAT_EXACT_FP
   float q1 = x.hi / y.hi;
   df r = df_sub(x, df_mulf(y, q1));
   float q2 = r.hi / y.hi;
@@ -138,6 +150,7 @@ __device__ __forceinline__ df df_div(df x, df y) {
   return df_add(q, df_from(q3));
 }
 __device__ __forceinline__ df df_sqrt(df x) {
+  MSPLAT_EXACT_FP
   if (x.hi <= 0.f) return {0.f, 0.f};
   float s = sqrtf(x.hi);
   df r = df_sub(x, two_prod(s, s));

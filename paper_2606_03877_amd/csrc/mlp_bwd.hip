@@ -112,7 +112,7 @@ __device__ __forceinline__ float bval(const BT<N>& v, int e) {
 // publish this wave's 32 columns of a layer input (slots -> canonical rows)
 template <class N, int J, int NKS>
 __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const Hi<N, NKS>& a, int g,
-                                              int colx, bool valid) {
+                                              int colx) {
   using B = Bwd<N>;
 #pragma unroll
   for (int s = 0; s < NKS; ++s) {
@@ -124,19 +124,19 @@ __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const H
       int f = N::in_feat(J, g, t);
       if (f < 0) continue;
       if constexpr (N::BF16) {
-        __bf16 z = (__bf16)0.f;
-        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s][e] : z;
+        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = a.hi[s][e];
       } else {
-        reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = valid ? a.hi[s] : 0.f;
+        reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = a.hi[s];
       }
     }
   }
 }
 
-// publish this wave's 32 columns of delta_j (D layout -> canonical rows)
+// publish this wave's 32 columns of delta_j (D layout -> canonical rows); the
+// deltas of columns past the end of the wave's samples are zero
 template <class N, int J>
 __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f32x16 (&dz)[N::frb(J)], int g,
-                                              int colx, bool valid) {
+                                              int colx) {
   using B = Bwd<N>;
 #pragma unroll
   for (int rb = 0; rb < N::frb(J); ++rb) {
@@ -144,7 +144,7 @@ __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f
     for (int r = 0; r < 16; ++r) {
       int n = phi_std(g, 16 * rb + r);
       if (n >= N::fout(J)) continue;
-      float v = valid ? dz[rb][r] : 0.f;
+      float v = dz[rb][r];
       if constexpr (N::BF16) {
         __bf16 h = (__bf16)v;
         reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = h;
@@ -258,11 +258,12 @@ struct BwdArgs {
   float* g_mlp;
 };
 
-// per-sample state kept from the recompute: the encoding (the first layer's
-// operand is rebuilt from it when needed) and every hidden layer's input
+// per-sample state kept from the recompute: the sample position (the
+// encoding is evaluated again where it is needed) and the hi part of every
+// hidden layer's input
 template <class N>
 struct Keep {
-  float ev[N::ENC_KS * N::KSTEP];
+  float ph[3], pl[3];
   Hi<N, rup(N::HID_KS, N::KGRP)> ah[N::NL - 1];
 };
 
@@ -288,11 +289,17 @@ template <class N>
 __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, int lane, const float ph[3],
                                                const float pl[3], Keep<N>& kp) {
   int g = lane / 32;
-  encode_slots<N>(ph, pl, g, kp.ev);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    kp.ph[a] = ph[a];
+    kp.pl[a] = pl[a];
+  }
   f32x16 acc[N::RBH];
   {
+    float ev[N::ENC_KS * N::KSTEP];
+    encode_slots<N>(ph, pl, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
-    enc_to_B<N>(kp.ev, a0);
+    enc_to_B<N>(ev, a0);
     layer_fwd<N, 0, N::ENC_KS>(lds, lane, a0, acc);
   }
   f32x16 out;
@@ -302,20 +309,22 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, 
 
 // backward through layers J..0 with the weight-gradient exchange
 template <class N, int J>
-__device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, int q, int colx, bool valid,
+__device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, int q, int colx,
                                            const Keep<N>& kp, const f32x16 (&dz)[N::frb(J)],
-                                           f32x16 (&da0)[N::RB0], f32x4* __restrict__ dacc) {
+                                           float (&dp)[3], f32x4* __restrict__ dacc) {
   const int g = lane / 32;
-  publish_delta<N, J>(lds, dz, g, colx, valid);
+  publish_delta<N, J>(lds, dz, g, colx);
+  float ev[N::ENC_KS * N::KSTEP];
   if constexpr (J == 0) {
+    encode_slots<N>(kp.ph, kp.pl, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
-    enc_to_B<N>(kp.ev, a0);
+    enc_to_B<N>(ev, a0);
     Hi<N, rup(N::ENC_KS, N::KGRP)> h0;
 #pragma unroll
     for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
-    publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx, valid);
+    publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx);
   } else {
-    publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx, valid);
+    publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx);
   }
   // transposed product for the next delta, overlapping the exchange
   Act<N, rup(N::bks(J), N::KGRP)> Bd;
@@ -338,10 +347,25 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, 
         dzn[rb][r] = a > 0.f ? da[rb][r] : 0.f;
       }
     }
-    chain_back<N, J - 1>(lds, lane, q, colx, valid, kp, dzn, da0, dacc);
+    chain_back<N, J - 1>(lds, lane, q, colx, kp, dzn, dp, dacc);
   } else {
+    // dL/dp of the sample from the input-feature gradient W_0^T delta_0
 #pragma unroll
-    for (int rb = 0; rb < N::RB0; ++rb) da0[rb] = da[rb];
+    for (int a = 0; a < 3; ++a) dp[a] = 0.f;
+#pragma unroll
+    for (int t = 0; t < N::ENC_SLOTS; ++t) {
+      float gf = da[t / 16][t % 16];
+      if (t < 3 * N::L) {
+        int pr = t / 6, j = t % 6, a = j % 3;
+        float mul = (float)(1 << (2 * pr)) * (g ? 2.f : 1.f) * 3.14159265358979f;
+        // d sin(m p)/dp = m cos(m p); d cos(m p)/dp = -m sin(m p)
+        float dv = j < 3 ? mul * ev[6 * pr + 3 + a] : -mul * ev[6 * pr + a];
+        dp[a] += gf * dv;
+      } else {
+        int a = t - 3 * N::L;
+        if (g == 0) dp[a] += gf;
+      }
+    }
   }
 }
 
@@ -350,6 +374,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   using B = Bwd<N>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int rounds_s[B::NW];
+  __shared__ float gsum_s[12];   // this work item's geometry sums (dL/dM, dL/dv)
   const Workspace& ws = args.ws;
   const int lane = threadIdx.x % 64;
   const int q = threadIdx.x / 64;
@@ -378,6 +403,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   const int ns = __shfl(incl, 63, 64);
   const int nblk = (ns + 31) / 32;
   if (lane == 0) rounds_s[q] = nblk;
+  if (threadIdx.x < 12) gsum_s[threadIdx.x] = 0.f;
   __syncthreads();
   int rounds = 0;
   for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
@@ -385,9 +411,6 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   f32x4 dacc[B::TT];
 #pragma unroll
   for (int i = 0; i < B::TT; ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float gsum[12];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) gsum[i] = 0.f;
   // carries of the hit-local scans from block to block
   float cr_tau = 0.f, cr_P = 0.f, cr_geo[9];
 #pragma unroll
@@ -484,25 +507,10 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     const float dts = dtau * sig;   // half 0: dtau * sigma (for dL/dDelta)
 
     // ---- network adjoint and weight gradients ----
-    f32x16 da0[N::RB0];
-    chain_back<N, N::NL - 1>(lds, lane, q, colx, valid, kp, dz, da0, dacc);
+    float dp[3];
+    chain_back<N, N::NL - 1>(lds, lane, q, colx, kp, dz, dp, dacc);
 
-    // ---- dL/dp of the sample from the input-feature gradient ----
-    float dp[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < N::ENC_SLOTS; ++t) {
-      float gf = da0[t / 16][t % 16];
-      if (t < 3 * N::L) {
-        int pr = t / 6, j = t % 6, a = j % 3;
-        float mul = (float)(1 << (2 * pr)) * (g ? 2.f : 1.f) * 3.14159265358979f;
-        // d sin(m p)/dp = m cos(m p); d cos(m p)/dp = -m sin(m p)
-        float dv = j < 3 ? mul * kp.ev[6 * pr + 3 + a] : -mul * kp.ev[6 * pr + a];
-        dp[a] += gf * dv;
-      } else {
-        int a = t - 3 * N::L;
-        if (g == 0) dp[a] += gf;
-      }
-    }
+    // ---- dL/dp of the sample: the two lane halves hold disjoint encoding slots ----
 #pragma unroll
     for (int a = 0; a < 3; ++a) dp[a] += __shfl_xor(dp[a], 32, 64);
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
@@ -548,8 +556,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
 #pragma unroll
-        for (int cidx = 0; cidx < 3; ++cidx) gsum[3 * r + cidx] += c1[r] * dc[cidx] + c2[r] * dd[cidx];
-        gsum[9 + r] += c1[r];
+        for (int cidx = 0; cidx < 3; ++cidx) atomicAdd(&gsum_s[3 * r + cidx], c1[r] * dc[cidx] + c2[r] * dd[cidx]);
+        atomicAdd(&gsum_s[9 + r], c1[r]);
       }
     }
     // carries
@@ -562,13 +570,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   // ---- flush the weight-gradient strips ----
   flush_dw<N, 0>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
   // ---- flush the geometry sums ----
-#pragma unroll
-  for (int i = 0; i < 12; ++i) gsum[i] = wave_sum(gsum[i]);
-  if (lane == 0) {
-#pragma unroll
-    for (int i = 0; i < 12; ++i)
-      if (gsum[i] != 0.f) atomicAdd(ws.geo_grad + (int64_t)p * 12 + i, gsum[i]);
-  }
+  __syncthreads();
+  if (threadIdx.x < 12 && gsum_s[threadIdx.x] != 0.f)
+    atomicAdd(ws.geo_grad + (int64_t)p * 12 + threadIdx.x, gsum_s[threadIdx.x]);
 }
 
 }  // namespace
