@@ -185,15 +185,21 @@ int msplat_debug_hits(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, int64_
 /*
  * Float64 forward of the same render (finite-difference gradient checker
  * only; not a product path).  Same arguments as msplat_render_forward with
- * float64 inputs and outputs; the workspace is sized by
- * msplat_workspace_size for the same num_rays and hit count.  The network is
- * evaluated in float64 on the vector units.
+ * float64 inputs and outputs; the workspace needs 256 bytes (*need_bytes).
+ * The network is evaluated in float64 on the vector units; at most 48 hits
+ * per ray are kept (MSPLAT_E_CAPACITY beyond that).
+ * decisions [R] (uint32, may be NULL) receives a hash of each ray's discrete
+ * decisions: the depth-ordered primitives, the samples evaluated, every open
+ * ReLU gate and the termination cut.  Two calls whose hashes agree for a ray
+ * took the same decisions for it (up to hash collisions), so a central
+ * difference over that ray's loss differentiates one smooth branch.
  */
 int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
                               const double* center, const double* scale, const double* quat,
                               const double* mlp, const double* ray_o, const double* ray_d,
                               int64_t num_rays, double* rgb, double* trans, double* feat,
-                              void* ws, uint64_t ws_bytes, uint64_t* need_bytes, void* stream);
+                              uint32_t* decisions, void* ws, uint64_t ws_bytes, uint64_t* need_bytes,
+                              void* stream);
 
 #ifdef __cplusplus
 }

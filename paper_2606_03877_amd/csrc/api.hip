@@ -470,8 +470,9 @@ int msplat_debug_hits(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, int64
 int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
                               const double* center, const double* scale, const double* quat,
                               const double* mlp, const double* ray_o, const double* ray_d,
-                              int64_t R, double* rgb, double* trans, double* feat, void* wsp,
-                              uint64_t ws_bytes, uint64_t* need_bytes, void* stream) {
+                              int64_t R, double* rgb, double* trans, double* feat,
+                              uint32_t* decisions, void* wsp, uint64_t ws_bytes, uint64_t* need_bytes,
+                              void* stream) {
   NetShape n;
   if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
   if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
@@ -482,8 +483,8 @@ int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const mspl
   if (ws_bytes < 256) return MSPLAT_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
-  HIPCHK(launch_forward_f64(n, *o, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, wsp,
-                            ws_bytes, 0, s));
+  HIPCHK(launch_forward_f64(n, *o, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, decisions,
+                            wsp, ws_bytes, 0, s));
   HIPCHK(hipMemcpyAsync(ctx->host_ctr, wsp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   // more hits on one ray than the float64 checker keeps: refuse rather than truncate

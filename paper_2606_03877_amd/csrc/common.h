@@ -255,7 +255,7 @@ hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msp
 hipError_t launch_forward_f64(const NetShape& n, const msplat_opts& o, const double* center,
                               const double* scale, const double* quat, const double* mlp,
                               const double* ray_o, const double* ray_d, int64_t R,
-                              double* rgb, double* trans, double* feat, void* ws,
-                              uint64_t ws_bytes, int max_hits_per_ray, hipStream_t s);
+                              double* rgb, double* trans, double* feat, uint32_t* decisions,
+                              void* ws, uint64_t ws_bytes, int max_hits_per_ray, hipStream_t s);
 
 }  // namespace msplat

@@ -47,8 +47,11 @@ __device__ __forceinline__ Frame64 frame64(const double* center, const double* s
   return f;
 }
 
+// FNV-style mixing of the discrete decisions of a ray into one word
+__device__ __forceinline__ uint32_t mix(uint32_t h, uint32_t v) { return (h ^ v) * 16777619u; }
+
 template <int L, int W, int D, int NOUT>
-__device__ void mlp64(const double* __restrict__ th, const double p[3], double out[NOUT]) {
+__device__ void mlp64(const double* __restrict__ th, const double p[3], double out[NOUT], uint32_t& dec) {
   constexpr int IN = 3 + 6 * L;
   double x[IN];
   for (int a = 0; a < 3; ++a) x[a] = p[a];
@@ -64,6 +67,7 @@ __device__ void mlp64(const double* __restrict__ th, const double p[3], double o
     double s = th[off + IN * W + n];
     for (int k = 0; k < IN; ++k) s += th[off + n * IN + k] * x[k];
     h[n] = s > 0 ? s : 0.0;
+    if (s > 0) dec = mix(dec, (uint32_t)n + 1u);
   }
   off += IN * W + W;
   for (int j = 1; j < D; ++j) {
@@ -71,6 +75,7 @@ __device__ void mlp64(const double* __restrict__ th, const double p[3], double o
       double s = th[off + W * W + n];
       for (int k = 0; k < W; ++k) s += th[off + n * W + k] * h[k];
       h2[n] = s > 0 ? s : 0.0;
+      if (s > 0) dec = mix(dec, (uint32_t)(j * W + n) + 1u);
     }
     for (int n = 0; n < W; ++n) h[n] = h2[n];
     off += W * W + W;
@@ -87,7 +92,8 @@ __global__ __launch_bounds__(64) void forward_f64_kernel(
     const double* __restrict__ center, const double* __restrict__ scale, const double* __restrict__ quat,
     const double* __restrict__ mlp, int n_params, int P, const double* __restrict__ ray_o,
     const double* __restrict__ ray_d, int64_t R, msplat_opts opt, double* __restrict__ rgb,
-    double* __restrict__ trans, double* __restrict__ feat, int32_t* __restrict__ overflow) {
+    double* __restrict__ trans, double* __restrict__ feat, uint32_t* __restrict__ decisions,
+    int32_t* __restrict__ overflow) {
   int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (ray >= R) return;
   double o[3] = {ray_o[3 * ray], ray_o[3 * ray + 1], ray_o[3 * ray + 2]};
@@ -130,8 +136,10 @@ __global__ __launch_bounds__(64) void forward_f64_kernel(
   double S = 0.0;
   bool stop = false;
   uint32_t seed_hash = pcg_hash(opt.jitter_seed);
+  uint32_t dec = 2166136261u;
   for (int i = 0; i < n && !stop; ++i) {
     int p = hp[i];
+    dec = mix(dec, 0x80000000u | (uint32_t)p);
     Frame64 f = frame64(center, scale, quat, p, o, d);
     double Lh = hb[i] - ha[i];
     int K;
@@ -148,11 +156,12 @@ __global__ __launch_bounds__(64) void forward_f64_kernel(
       double tk = ha[i] + (k + u) * dlt;
       double pk[3] = {f.ol[0] + tk * f.dl[0], f.ol[1] + tk * f.dl[1], f.ol[2] + tk * f.dl[2]};
       double out[NOUT];
-      mlp64<L, W, D, NOUT>(th, pk, out);
+      mlp64<L, W, D, NOUT>(th, pk, out, dec);
       double sig = out[3] > 0 ? out[3] + log1p(exp(-out[3])) : log1p(exp(out[3]));
       double tau = sig * dlt;
       double tb = exp(-S);
       if (opt.t_stop > 0.f && tb < (double)opt.t_stop) {
+        dec = mix(dec, 0x40000000u | (uint32_t)k);
         stop = true;
         break;
       }
@@ -166,6 +175,7 @@ __global__ __launch_bounds__(64) void forward_f64_kernel(
   for (int r = 0; r < 3; ++r) rgb[3 * ray + r] = c[r] + t * (double)opt.background[r];
   trans[ray] = t;
   for (int r = 0; r < CF; ++r) feat[ray * CF + r] = fe[r];
+  if (decisions) decisions[ray] = dec;
 }
 
 }  // namespace
@@ -173,8 +183,8 @@ __global__ __launch_bounds__(64) void forward_f64_kernel(
 hipError_t launch_forward_f64(const NetShape& n, const msplat_opts& o, const double* center,
                               const double* scale, const double* quat, const double* mlp,
                               const double* ray_o, const double* ray_d, int64_t R, double* rgb,
-                              double* trans, double* feat, void* ws, uint64_t ws_bytes,
-                              int max_hits_per_ray, hipStream_t s) {
+                              double* trans, double* feat, uint32_t* decisions, void* ws,
+                              uint64_t ws_bytes, int max_hits_per_ray, hipStream_t s) {
   (void)ws_bytes;
   (void)max_hits_per_ray;
   if (R <= 0) return hipSuccess;
@@ -185,7 +195,7 @@ hipError_t launch_forward_f64(const NetShape& n, const msplat_opts& o, const dou
 #define X(L_, W_, D_, O_)                                                                                   \
   if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_) {                                              \
     hipLaunchKernelGGL((forward_f64_kernel<L_, W_, D_, O_>), grid, block, 0, s, center, scale, quat, mlp, \
-                       n.n_params, n.P, ray_o, ray_d, R, o, rgb, trans, feat, overflow);                  \
+                       n.n_params, n.P, ray_o, ray_d, R, o, rgb, trans, feat, decisions, overflow);       \
     return hipGetLastError();                                                                             \
   }
   X(4, 32, 2, 4)

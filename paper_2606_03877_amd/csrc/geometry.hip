@@ -514,7 +514,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
       }
     }
   }
-  if (!valid) return;
+  // (lanes of rays past the end have n = 0 and stay for the wave-wide steps below)
   // pass 2: insertion sort of this ray's segment by (t_c, prim)
   for (int i = 1; i < n; ++i) {
     int64_t ji = off + i;
@@ -543,77 +543,97 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
   }
   // pass 3: per-hit local record and grouping by primitive
   int64_t H = ws.hit_cap;
-  for (int i = 0; i < n; ++i) {
+  int nmax = n;
+#pragma unroll
+  for (int sh = 32; sh >= 1; sh >>= 1) nmax = max(nmax, __shfl_xor(nmax, sh, 64));
+  for (int i = 0; i < nmax; ++i) {
+    const bool act = i < n;
     int64_t j = off + i;
-    int p = ws.hit_prim[j];
-    const float* gp = geo + (int64_t)p * kGeoStride;
-    const float* Mh = gp + G_M_HI;
-    const float* Ml = gp + G_M_LO;
-    float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j];
-    int kk = ws.hit_k[j];
-    bool clipped = kk < 0;
-    int K = clipped ? -kk : kk;
-    // residual delta = (mu - o) - t_c d and the local contact point
-    // p_c = -M delta and direction e = M d, all as double-floats: sample
-    // positions feed an encoding of frequency up to 2^(L-1) pi, so their
-    // float32 rounding would be amplified into the gradients
-    const float dd[3] = {d.x, d.y, d.z};
-    const float oo[3] = {o.x, o.y, o.z};
-    df tc = {tch, tcl};
-    df dl[3];
-    for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
-    df pcv[3], ev[3];
-    for (int r = 0; r < 3; ++r) {
-      df pc = {0.f, 0.f}, e = {0.f, 0.f};
-      for (int c = 0; c < 3; ++c) {
-        const df m = {Mh[3 * r + c], Ml[3 * r + c]};
-        pc = df_add(pc, df_mul(m, dl[c]));
-        e = df_add(e, df_mulf(m, dd[c]));
+    int p = act ? ws.hit_prim[j] : -1;
+    if (act) {
+      const float* gp = geo + (int64_t)p * kGeoStride;
+      const float* Mh = gp + G_M_HI;
+      const float* Ml = gp + G_M_LO;
+      float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j];
+      int kk = ws.hit_k[j];
+      bool clipped = kk < 0;
+      int K = clipped ? -kk : kk;
+      // residual delta = (mu - o) - t_c d and the local contact point
+      // p_c = -M delta and direction e = M d, all as double-floats: sample
+      // positions feed an encoding of frequency up to 2^(L-1) pi, so their
+      // float32 rounding would be amplified into the gradients
+      const float dd[3] = {d.x, d.y, d.z};
+      const float oo[3] = {o.x, o.y, o.z};
+      df tc = {tch, tcl};
+      df dl[3];
+      for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
+      df pcv[3], ev[3];
+      for (int r = 0; r < 3; ++r) {
+        df pc = {0.f, 0.f}, e = {0.f, 0.f};
+        for (int c = 0; c < 3; ++c) {
+          const df m = {Mh[3 * r + c], Ml[3 * r + c]};
+          pc = df_add(pc, df_mul(m, dl[c]));
+          e = df_add(e, df_mulf(m, dd[c]));
+        }
+        pcv[r] = df_neg(pc);
+        ev[r] = e;
       }
-      pcv[r] = df_neg(pc);
-      ev[r] = e;
+      // The sort key t_c is accurate to float32 only; samples are placed
+      // relative to t_c, so refine it to double-float accuracy: one Newton step
+      // on (p_c + dt e) . e = 0, i.e. dt = -(p_c . e) / |e|^2.
+      df aa = {0.f, 0.f}, pe = {0.f, 0.f};
+      for (int r = 0; r < 3; ++r) {
+        aa = df_add(aa, df_mul(ev[r], ev[r]));
+        pe = df_add(pe, df_mul(pcv[r], ev[r]));
+      }
+      const float dtc = -pe.hi / aa.hi;
+      tc = df_add(tc, df_from(dtc));
+      ws.hit_tc_hi[j] = tc.hi;
+      ws.hit_tc_lo[j] = tc.lo;
+      df gg = {1.f, 0.f};
+      for (int r = 0; r < 3; ++r) {
+        pcv[r] = df_add(pcv[r], df_mulf(ev[r], dtc));
+        gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
+        ws.hit_pc[r * H + j] = pcv[r].hi;
+        ws.hit_pc_lo[r * H + j] = pcv[r].lo;
+        ws.hit_e[r * H + j] = ev[r].hi;
+        ws.hit_e_lo[r * H + j] = ev[r].lo;
+      }
+      // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the refined contact point
+      const df etad = df_sqrt(df_div(gg, aa));
+      ws.hit_eta[j] = etad.hi;
+      df sa, dlt;
+      const df Kd = {(float)K, 0.f};
+      if (clipped) {
+        sa = df_neg(tc);
+        dlt = df_div(df_add(tc, etad), Kd);
+      } else {
+        sa = df_neg(etad);
+        dlt = df_div(df_mulf(etad, 2.f), Kd);
+      }
+      ws.hit_sa[j] = sa.hi;
+      ws.hit_sa_lo[j] = sa.lo;
+      ws.hit_dlt[j] = dlt.hi;
+      ws.hit_dlt_lo[j] = dlt.lo;
+      ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
+      ws.hit_ray[j] = (int32_t)ray;
     }
-    // The sort key t_c is accurate to float32 only; samples are placed
-    // relative to t_c, so refine it to double-float accuracy: one Newton step
-    // on (p_c + dt e) . e = 0, i.e. dt = -(p_c . e) / |e|^2.
-    df aa = {0.f, 0.f}, pe = {0.f, 0.f};
-    for (int r = 0; r < 3; ++r) {
-      aa = df_add(aa, df_mul(ev[r], ev[r]));
-      pe = df_add(pe, df_mul(pcv[r], ev[r]));
+    // slots in the per-primitive lists: one atomic per distinct primitive of
+    // the wave (coherent packets share few), ranks within it by lane
+    uint64_t pending = __ballot(act);
+    int slot = 0;
+    while (pending) {
+      const int leader = __builtin_ctzll(pending);
+      const int lp = __shfl(p, leader, 64);
+      const bool mine = act && p == lp;
+      const uint64_t same = __ballot(mine);
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&ws.prim_cursor[lp], __popcll(same));
+      base = __shfl(base, leader, 64);
+      if (mine) slot = base + __popcll(same & ((1ull << lane) - 1ull));
+      pending &= ~same;
     }
-    const float dtc = -pe.hi / aa.hi;
-    tc = df_add(tc, df_from(dtc));
-    ws.hit_tc_hi[j] = tc.hi;
-    ws.hit_tc_lo[j] = tc.lo;
-    df gg = {1.f, 0.f};
-    for (int r = 0; r < 3; ++r) {
-      pcv[r] = df_add(pcv[r], df_mulf(ev[r], dtc));
-      gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
-      ws.hit_pc[r * H + j] = pcv[r].hi;
-      ws.hit_pc_lo[r * H + j] = pcv[r].lo;
-      ws.hit_e[r * H + j] = ev[r].hi;
-      ws.hit_e_lo[r * H + j] = ev[r].lo;
-    }
-    // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the refined contact point
-    const df etad = df_sqrt(df_div(gg, aa));
-    ws.hit_eta[j] = etad.hi;
-    df sa, dlt;
-    const df Kd = {(float)K, 0.f};
-    if (clipped) {
-      sa = df_neg(tc);
-      dlt = df_div(df_add(tc, etad), Kd);
-    } else {
-      sa = df_neg(etad);
-      dlt = df_div(df_mulf(etad, 2.f), Kd);
-    }
-    ws.hit_sa[j] = sa.hi;
-    ws.hit_sa_lo[j] = sa.lo;
-    ws.hit_dlt[j] = dlt.hi;
-    ws.hit_dlt_lo[j] = dlt.lo;
-    ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
-    ws.hit_ray[j] = (int32_t)ray;
-    int slot = atomicAdd(&ws.prim_cursor[p], 1);
-    ws.phit[slot] = (int32_t)j;
+    if (act) ws.phit[slot] = (int32_t)j;
   }
 }
 
@@ -689,17 +709,18 @@ __global__ __launch_bounds__(256) void composite_adjoint_kernel(
   // d(rgb)/d(tau_k) = T_{k+1} c_k - sum_{j>k} w_j c_j - T_final bg, and
   // d(T_final)/d(tau_k) = -T_final: the suffix starts with T_final (g.bg + g_T)
   float gt = grad_trans ? grad_trans[ray] : 0.f;
-  float acc = tf * (g0 * opt.background[0] + g1 * opt.background[1] + g2 * opt.background[2] + gt);
+  // suffix sum over the later hits, kept compensated (double-float)
+  df acc = df_from(tf * (g0 * opt.background[0] + g1 * opt.background[1] + g2 * opt.background[2] + gt));
   for (int64_t j = b - 1; j >= a; --j) {
     if (ws.hit_nused[j] <= 0) continue;
-    ws.hit_gsa[j] = acc;
+    ws.hit_gsa[j] = acc.hi + acc.lo;
     float tb = __expf(-(ws.hit_sb_hi[j] + ws.hit_sb_lo[j]));
     float gc = g0 * ws.hit_cloc[0 * H + j] + g1 * ws.hit_cloc[1 * H + j] + g2 * ws.hit_cloc[2 * H + j];
     if (grad_feat)
       for (int k = 0; k < cf; ++k) gc += grad_feat[ray * cf + k] * ws.hit_cloc[(3 + k) * H + j];
     ws.hit_tb[j] = tb;
     ws.hit_gtot[j] = tb * gc;
-    acc = __builtin_fmaf(tb, gc, acc);
+    acc = df_add(acc, two_prod(tb, gc));
   }
 }
 

@@ -172,12 +172,12 @@ def msplat_debug_hits(ctx: Context, ws: torch.Tensor, num_rays: int, num_hits: i
 
 
 def msplat_render_forward_f64(ctx: Context, spec: NetSpec, opts: RenderOpts, center, scale, quat, mlp,
-                              ray_o, ray_d, rgb, trans, feat, ws, stream=None):
+                              ray_o, ray_d, rgb, trans, feat, ws, decisions=None, stream=None):
     need = ctypes.c_uint64(0)
     st = ctx.lib.msplat_render_forward_f64(
         ctx.handle, ctypes.byref(spec.c()), ctypes.byref(opts.c()), _p(center), _p(scale), _p(quat),
-        _p(mlp), _p(ray_o), _p(ray_d), int(ray_o.shape[0]), _p(rgb), _p(trans), _p(feat), _p(ws),
-        ws.numel(), ctypes.byref(need), _stream(stream))
+        _p(mlp), _p(ray_o), _p(ray_d), int(ray_o.shape[0]), _p(rgb), _p(trans), _p(feat),
+        _p(decisions), _p(ws), ws.numel(), ctypes.byref(need), _stream(stream))
     return st, int(need.value)
 
 

@@ -5,10 +5,11 @@ forward on 32 parameters against the analytic backward, in FP32 and in the
 split-bfloat16 form.
 
 A step of a parameter may move a discrete decision of some rays (a ray
-entering or leaving a support, two hits swapping depth order): the loss is
-not differentiable there, so for each parameter the rays whose hit lists
-differ at the two perturbed points (read from the float32 forward) are
-masked out of the loss, on both sides of the comparison."""
+entering or leaving a support, two hits swapping depth order, a ReLU gate
+switching): the loss is not differentiable there, so for each parameter the
+rays whose decisions differ at the two perturbed points (hit lists of the
+float32 forward, the decision hash of the float64 forward) are masked out of
+the loss, on both sides of the comparison."""
 import numpy as np
 import pytest
 import torch
@@ -21,16 +22,17 @@ pytestmark = pytest.mark.gpu
 KEYS = ("center", "scale", "quat", "mlp")
 
 
-def _f64_render(ctx, spec, opts, p64, o64, d64):
+def _f64_render(ctx, spec, opts, p64, o64, d64, with_decisions=False):
     from paper_2606_03877_amd import msplat_render_forward_f64
     R = o64.shape[0]
     rgb = torch.empty((R, 3), dtype=torch.float64, device="cuda")
     tr = torch.empty((R,), dtype=torch.float64, device="cuda")
+    dec = torch.empty((R,), dtype=torch.int32, device="cuda") if with_decisions else None
     ws = torch.empty(4096, dtype=torch.uint8, device="cuda")
     st, _ = msplat_render_forward_f64(ctx, spec, opts, p64["center"], p64["scale"], p64["quat"], p64["mlp"],
-                                      o64, d64, rgb, tr, None, ws)
+                                      o64, d64, rgb, tr, None, ws, decisions=dec)
     assert st == 0, st
-    return rgb
+    return (rgb, dec) if with_decisions else rgb
 
 
 def _hit_lists(r, p32, ro, rd):
@@ -107,14 +109,16 @@ def test_batch_gradient_matches_central_differences(precision, tol):
         for q in (pp, pm):
             q32 = {k: v.float().contiguous() for k, v in q.items()}
             keep &= _same_lists(base, _hit_lists(r, q32, ro, rd))
+        # every discrete decision of the float64 forward (hit order, samples,
+        # open ReLU gates) must agree at the two points, or the ray is masked
+        out_p, dec_p = _f64_render(r.ctx, spec, opts, pp, o64, d64, with_decisions=True)
+        out_m, dec_m = _f64_render(r.ctx, spec, opts, pm, o64, d64, with_decisions=True)
+        keep &= (dec_p == dec_m).cpu().numpy()
         masked.append(int((~keep).sum()))
         mk = torch.from_numpy(keep.astype(np.float64)).to(dev)[:, None]
-
-        def loss64(q):
-            out = _f64_render(r.ctx, spec, opts, q, o64, d64)
-            return float((((out - target) ** 2) * mk).sum() / (3 * R))
-
-        fd = (loss64(pp) - loss64(pm)) / (2 * h)
+        lp = float((((out_p - target) ** 2) * mk).sum() / (3 * R))
+        lm = float((((out_m - target) ** 2) * mk).sum() / (3 * R))
+        fd = (lp - lm) / (2 * h)
         g_rgb = ((2.0 / (3 * R)) * (rgb.double() - target) * mk).float()
         grads = r.backward(ws, p32["center"], p32["scale"], p32["quat"], p32["mlp"], ro, rd, g_rgb)
         gk = grads[KEYS.index(key)].double().cpu().numpy()
