@@ -149,16 +149,26 @@ def cpu_baseline(cfg, sc, o, d, target, opts, budget_s=12.0, chunk=2048, seed=5)
                       f"(autograd FP64), {dt:.1f} s"}
 
 
-def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per launch from a committed counter summary, if one matches."""
+def traffic_from_profiles(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE counters, each scaled by
+    its reading for a copy of known size) from profiles/traffic.json, if the
+    record matches the kernel, workload and precision and the kernel's sources
+    are unchanged since the counters were taken; else None."""
+    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
-        e = rec.get(workload, {}).get(kernel)
-        return None if e is None else float(e["bytes_per_launch"])
-    except Exception:
+        e = json.load(open(path)).get(workload, {}).get(kernel)
+        if e is None or e.get("precision") != precision:
+            return None
+        h = hashlib.sha1()
+        for src in e["sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != e["sources_sha1"]:
+            return None
+        return float(e["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
         return None
 
 
@@ -232,7 +242,7 @@ def main():
         achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"],
                 "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16"],
-                "traffic": traffic_from_profiles(dom, f"config{cfg.idx}"),
+                "traffic": traffic_from_profiles(dom, f"config{cfg.idx}", MAIN),
                 "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops[dom]}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
