@@ -101,6 +101,7 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ lds, int l
       }
     }
     acc[rb] = c;
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -192,6 +193,7 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
           acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
           if constexpr (N::SPLIT) acc[B::CT(J)] = mfma16(al, ones, acc[B::CT(J)]);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     } else {
       const float* xd = reinterpret_cast<const float*>(lds + B::XD_OFF);
@@ -433,12 +435,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     const float dlt = ws.hit_dlt[hit];
     float ph[3], pl[3];
     const float sk = sample_position(ws, hit, k, u, ph, pl);
-    float pc[3], ee[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      pc[a] = ws.hit_pc[a * H + hit];
-      ee[a] = ws.hit_e[a * H + hit];
-    }
+    const float om = ((float)k + u) / (float)K;
+    const bool last = valid && k == K - 1;
     Keep<N> kp;
     f32x16 o = forward_keep<N>(lds, lane, ph, pl, kp);
 
@@ -504,7 +502,11 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
         int f = phi_std(g, r) - 4;
         if (f >= 0 && f < N::CF) dz[0][r] = w * gfv[r];
       }
-    const float dts = dtau * sig;   // half 0: dtau * sigma (for dL/dDelta)
+    // half 0 holds dtau * sigma (for dL/dDelta); both halves take it
+    const float dts = __shfl(dtau * sig, col, 64);
+    // carries of the compositing scans into the next block
+    cr_tau = __shfl(tincl, 31, 32);
+    cr_P = __shfl(P, 31, 32);
 
     // ---- network adjoint and weight gradients ----
     float dp[3];
@@ -516,16 +518,20 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
 
     // ---- per-hit geometry sums ----
+    float pc[3], ee[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      pc[a] = ws.hit_pc[a * H + hit];
+      ee[a] = ws.hit_e[a * H + hit];
+    }
     const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
-    const float om = ((float)k + u) / (float)K;
-    float gv[9] = {dp[0], dp[1], dp[2], sk * dp[0], sk * dp[1], sk * dp[2], dtk, om * dtk,
-                   __shfl(dts, col, 64)};
+    float gv[9] = {dp[0], dp[1], dp[2], sk * dp[0], sk * dp[1], sk * dp[2], dtk, om * dtk, dts};
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       gv[i] = sc.incl(gv[i]);
       if (!sc.seen_head) gv[i] += cr_geo[i];
     }
-    if (valid && g == 0 && k == K - 1) {
+    if (last && g == 0) {
       const float* gp = ws.geo + (int64_t)p * kGeoStride;
       const int kraw = ws.hit_k[hit];
       const bool clipped = (kraw & kClippedBit) != 0;
@@ -560,9 +566,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
         atomicAdd(&gsum_s[9 + r], c1[r]);
       }
     }
-    // carries
-    cr_tau = __shfl(tincl, 31, 32);
-    cr_P = __shfl(P, 31, 32);
+    // carries of the geometry scans
 #pragma unroll
     for (int i = 0; i < 9; ++i) cr_geo[i] = __shfl(gv[i], 31, 32);
   }

@@ -147,6 +147,8 @@ __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ lds, int l
       }
     }
     acc[rb] = c;
+    // one row block's operands in flight at a time (bounds register pressure)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
