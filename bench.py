@@ -32,6 +32,23 @@ PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}     # MI355X dense matrix-core pea
 HBM_PEAK_GBS = 8000.0
 
 
+def workload_name(cfg) -> str:
+    views = cfg.views
+    if len(views) == 1:
+        frames = f"{views[0][0]}x{views[0][1]} frame"
+    else:
+        kinds = {}
+        for w, h in views:
+            kinds[(w, h)] = kinds.get((w, h), 0) + 1
+        frames = f"{len(views)} views (" + ", ".join(f"{n}x {w}x{h}" for (w, h), n in kinds.items()) + ")"
+    if cfg.batch_rays:
+        frames = f"{cfg.batch_rays}-ray batch over " + frames
+    k = f"K={cfg.samples_fixed}" if cfg.samples_fixed else \
+        f"K=clamp(ceil({cfg.samples_per_unit:g} L), {cfg.samples_min}, {cfg.samples_max})"
+    return (f"config{cfg.idx}-{cfg.name}: {frames}, {cfg.num_prims} primitives, "
+            f"{cfg.in_dim}-{cfg.hidden_width}x{cfg.hidden_layers}-{cfg.out_dim} MLPs, {k}, T_stop={cfg.t_stop:g}")
+
+
 def mlp_flops_per_sample(cfg) -> int:
     import synth
     return sum(2 * i * o for i, o in synth.layer_dims(cfg))
@@ -264,10 +281,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "bf16",
-        "data": "synthetic (seeded scene, 800x800 pinhole frame, target frame from a second seeded scene)",
-        "config": {"workload": f"config{cfg.idx}-{cfg.name}: {cfg.views[0][0]}x{cfg.views[0][1]} frame, "
-                               f"{cfg.num_prims} primitives, {cfg.in_dim}-{cfg.hidden_width}x{cfg.hidden_layers}-"
-                               f"{cfg.out_dim} MLPs, K={cfg.samples_fixed}, T_stop={cfg.t_stop}",
+        "data": "synthetic (seeded scene and pinhole cameras, target frames rendered from a second seeded scene)",
+        "config": {"workload": workload_name(cfg),
                    "rays": R, "hits": int(st["num_hits"]), "samples": int(st["num_samples"]),
                    "terminated_rays": int(st["num_terminated"]),
                    "mlp_precision": "bf16 hi+lo operand pairs (3 products), fp32 accumulate"},

@@ -95,22 +95,22 @@ __global__ void pack_weights_kernel(const float* __restrict__ mlp, uint8_t* __re
 
 // full network of one 32-sample block; returns the output layer's D registers
 template <class N, int J>
-__device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ lds, int lane,
+__device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ wb, int lane,
                                                f32x16 (&acc)[N::RBH]) {
   Act<N, rup(N::HID_KS, N::KGRP)> Bh;
   relu_to_B<N>(acc, Bh);
   if constexpr (J < N::NL - 1) {
-    layer_fwd<N, J, N::HID_KS>(lds, lane, Bh, acc);
-    return hidden_chain<N, J + 1>(lds, lane, acc);
+    layer_fwd<N, J, N::HID_KS>(wb, lane, Bh, acc);
+    return hidden_chain<N, J + 1>(wb, lane, acc);
   } else {
     f32x16 out[1];
-    layer_fwd<N, J, N::HID_KS>(lds, lane, Bh, out);
+    layer_fwd<N, J, N::HID_KS>(wb, lane, Bh, out);
     return out[0];
   }
 }
 
 template <class N>
-__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ lds, int lane, const float ph[3],
+__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, int lane, const float ph[3],
                                                 const float pl[3]) {
   int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
@@ -118,8 +118,8 @@ __device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ lds,
   Act<N, rup(N::ENC_KS, N::KGRP)> B0;
   enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
-  layer_fwd<N, 0, N::ENC_KS>(lds, lane, B0, acc);
-  return hidden_chain<N, 1>(lds, lane, acc);
+  layer_fwd<N, 0, N::ENC_KS>(wb, lane, B0, acc);
+  return hidden_chain<N, 1>(wb, lane, acc);
 }
 
 // ------------------------------------------------------------- forward --
@@ -152,13 +152,16 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
     if ((int)threadIdx.x < nh) flag = ws.hit_nused[ws.phit[first + threadIdx.x]] == -1;
     if (!__syncthreads_or(flag)) return;
   }
-  // stage the primitive's packed forward operands
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(ws.wpack + (int64_t)p * ws.wpack_bytes);
+  // the primitive's packed forward operands: staged in LDS, or read where
+  // they are (global memory, L2-resident) for wide networks
+  const uint8_t* wts = ws.wpack + (int64_t)p * ws.wpack_bytes;
+  if constexpr (!N::WIDE) {
+    const uint4* src = reinterpret_cast<const uint4*>(wts);
     uint4* dst = reinterpret_cast<uint4*>(lds);
     for (int i = threadIdx.x; i < N::fwd_bytes() / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    wts = lds;
   }
-  __syncthreads();
   // this wave's hits
   const int h0 = (nh * wv) / 4, h1 = (nh * (wv + 1)) / 4;
   const int c = h1 - h0;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
     const float dlt = ws.hit_dlt[hit];
     float ph[3], pl[3];
     sample_position(ws, hit, k, u, ph, pl);
-    f32x16 o = forward_block<N>(lds, lane, ph, pl);
+    f32x16 o = forward_block<N>(wts, lane, ph, pl);
     // density of the column (held by half 0), shared with half 1
     float tau0 = valid ? softplusf_(o[3]) * dlt : 0.f;
     const float tau = __shfl(tau0, col, 64);
@@ -312,7 +315,7 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
                            float* rgb, float* trans, float* feat, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   FwdArgs a{ws, o, mode, P, rgb, trans, feat};
-  size_t lds = N::fwd_bytes();
+  size_t lds = N::WIDE ? 0 : N::fwd_bytes();
   hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3(items), dim3(256), lds, s, a);
   return hipGetLastError();
 }

@@ -38,7 +38,7 @@ struct Bwd {
   static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
   // exchange planes: layer inputs (the split form contracts the weight
   // gradient with their hi part only), deltas (hi), and the deltas' lo parts
-  static constexpr int XH_OFF = N::total_bytes();
+  static constexpr int XH_OFF = N::WIDE ? 0 : N::total_bytes();
   static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
   static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
   static constexpr int LDS = XDL_OFF + (N::SPLIT ? DROWS * XSP * ESZ : 0);
@@ -51,6 +51,10 @@ struct Bwd {
   static constexpr int OWN(int j) { return (RT(j) + NW - 1) / NW; }
   static constexpr int TOFF(int j) { return j == 0 ? 0 : TOFF(j - 1) + OWN(j - 1) * CTB(j - 1); }
   static constexpr int TT = TOFF(N::NL);
+  // pass JP < 0 accumulates every layer's weight gradient; pass JP >= 0 (wide
+  // networks) only layer JP's
+  static constexpr int tiles(int jp) { return jp < 0 ? TT : OWN(jp) * CTB(jp); }
+  static constexpr int toff(int jp, int j) { return jp < 0 ? TOFF(j) : 0; }
 };
 
 template <class N>
@@ -73,12 +77,12 @@ __device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB],
 
 // transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j)
 template <class N, int J>
-__device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ lds, int lane,
+__device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int lane,
                                           const Act<N, rup(N::bks(J), N::KGRP)>& B,
                                           f32x16 (&acc)[N::brb(J)]) {
   constexpr int RB = N::brb(J);
   constexpr int NG = N::groups(N::bks(J));
-  const uint8_t* A = lds + N::bwdA_off(J);
+  const uint8_t* A = wb + N::bwdA_off(J);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     f32x16 c;
@@ -160,7 +164,7 @@ __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f
 
 // accumulate this wave's row strips of dW_J (and db_J) over the round
 template <class N, int J>
-__device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4* __restrict__ dacc, int q,
+__device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4* __restrict__ dj, int q,
                                          int lane) {
   using B = Bwd<N>;
   const int r16 = lane % 16, kg = lane / 16;
@@ -168,7 +172,7 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
   for (int i = 0; i < B::OWN(J); ++i) {
     int rt = q + i * B::NW;
     if (rt >= B::RT(J)) continue;
-    f32x4* acc = dacc + B::TOFF(J) + i * B::CTB(J);
+    f32x4* acc = dj + i * B::CTB(J);
     if constexpr (N::BF16) {
       const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
       const __bf16* xh = reinterpret_cast<const __bf16*>(lds + B::XH_OFF);
@@ -218,9 +222,10 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
   }
 }
 
-// add this wave's weight-gradient strips of layers J.. to the global gradient
+// add this wave's weight-gradient strips of layer J (tiles from dj) to the
+// global gradient
 template <class N, int J>
-__device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dacc, float* __restrict__ gm, int q,
+__device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __restrict__ gm, int q,
                                          int lane) {
   using B = Bwd<N>;
   const int r16 = lane % 16, rq = lane / 16;
@@ -230,7 +235,7 @@ __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dacc, float* 
     if (rt >= B::RT(J)) continue;
 #pragma unroll
     for (int ct = 0; ct < B::CTB(J); ++ct) {
-      f32x4 v = dacc[B::TOFF(J) + i * B::CTB(J) + ct];
+      f32x4 v = dj[i * B::CTB(J) + ct];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int n = 16 * rt + 4 * rq + r;
@@ -246,7 +251,13 @@ __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dacc, float* 
       }
     }
   }
-  if constexpr (J + 1 < N::NL) flush_dw<N, J + 1>(dacc, gm, q, lane);
+}
+
+template <class N, int J>
+__device__ __forceinline__ void flush_all(const f32x4* __restrict__ dacc, float* __restrict__ gm, int q,
+                                          int lane) {
+  flush_dw<N, J>(dacc + Bwd<N>::TOFF(J), gm, q, lane);
+  if constexpr (J + 1 < N::NL) flush_all<N, J + 1>(dacc, gm, q, lane);
 }
 
 struct BwdArgs {
@@ -261,35 +272,58 @@ struct BwdArgs {
 };
 
 // per-sample state kept from the recompute: the sample position (the
-// encoding is evaluated again where it is needed) and the hi part of every
-// hidden layer's input
-template <class N>
+// encoding is evaluated again where it is needed) and, for pass JP < 0, the
+// hi part of every hidden layer's input (its ReLU gates and the weight-
+// gradient operand); for a wide network's pass JP >= 0, the gates of every
+// hidden layer as bits and the hi part of layer JP's input only.
+template <class N, int JP>
 struct Keep {
   float ph[3], pl[3];
-  Hi<N, rup(N::HID_KS, N::KGRP)> ah[N::NL - 1];
+  Hi<N, rup(N::HID_KS, N::KGRP)> ah[JP < 0 ? N::NL - 1 : 1];
+  Gates<N> gt[JP < 0 ? 1 : N::NL - 1];
 };
 
-// forward recompute keeping every layer input
-template <class N, int J>
-__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ lds, int lane, Keep<N>& kp,
+template <class N, int JP, int J>
+__device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_hi(const Keep<N, JP>& kp) {
+  if constexpr (JP < 0) return kp.ah[J - 1]; else return kp.ah[0];
+}
+
+// ReLU gate of slot t of layer J's input (its pre-activation was positive)
+template <class N, int JP, int J>
+__device__ __forceinline__ bool gate(const Keep<N, JP>& kp, int t) {
+  if constexpr (JP < 0) return bval<N>(kp.ah[J - 1].hi[t / N::KSTEP], t % N::KSTEP) > 0.f;
+  else return (kp.gt[J - 1].w[t / 32] >> (t % 32)) & 1u;
+}
+
+// forward recompute keeping what the backward needs
+template <class N, int J, int JP>
+__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int lane, Keep<N, JP>& kp,
                                            f32x16 (&acc)[N::RBH], f32x16& out) {
   Act<N, rup(N::HID_KS, N::KGRP)> x;
   relu_to_B<N>(acc, x);
+  if constexpr (JP < 0) {
 #pragma unroll
-  for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - 1].hi[i] = x.hi[i];
+    for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - 1].hi[i] = x.hi[i];
+  } else {
+    gates_of<N>(acc, kp.gt[J - 1]);
+    if constexpr (J == JP) {
+#pragma unroll
+      for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[0].hi[i] = x.hi[i];
+    }
+  }
   if constexpr (J < N::NL - 1) {
-    layer_fwd<N, J, N::HID_KS>(lds, lane, x, acc);
-    chain_keep<N, J + 1>(lds, lane, kp, acc, out);
+    layer_fwd<N, J, N::HID_KS>(wb, lane, x, acc);
+    chain_keep<N, J + 1, JP>(wb, lane, kp, acc, out);
   } else {
     f32x16 o[1];
-    layer_fwd<N, J, N::HID_KS>(lds, lane, x, o);
+    layer_fwd<N, J, N::HID_KS>(wb, lane, x, o);
     out = o[0];
   }
 }
 
-template <class N>
-__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, int lane, const float ph[3],
-                                               const float pl[3], Keep<N>& kp) {
+template <class N, int JP>
+__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, int lane, const float ph[3],
+                                               const float pl[3], Keep<N, JP>& kp) {
   int g = lane / 32;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -302,55 +336,62 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ lds, 
     encode_slots<N>(ph, pl, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
-    layer_fwd<N, 0, N::ENC_KS>(lds, lane, a0, acc);
+    layer_fwd<N, 0, N::ENC_KS>(wb, lane, a0, acc);
   }
   f32x16 out;
-  chain_keep<N, 1>(lds, lane, kp, acc, out);
+  chain_keep<N, 1, JP>(wb, lane, kp, acc, out);
   return out;
 }
 
-// backward through layers J..0 with the weight-gradient exchange
-template <class N, int J>
-__device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, int q, int colx,
-                                           const Keep<N>& kp, const f32x16 (&dz)[N::frb(J)],
-                                           float (&dp)[3], f32x4* __restrict__ dacc) {
+// backward through layer J (and below): the transposed product towards layer
+// J-1, and, where the pass accumulates layer J's weight gradient, the
+// exchange of the block's deltas and inputs with the other waves
+template <class N, int J, int JP>
+__device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint8_t* __restrict__ wb, int lane,
+                                           int q, int colx, const Keep<N, JP>& kp,
+                                           const f32x16 (&dz)[N::frb(J)], float (&dp)[3],
+                                           f32x4* __restrict__ dacc) {
+  constexpr bool DW = JP < 0 || J == JP;                     // layer J's weight gradient
+  constexpr bool DOWN = J > 0 && (JP < 0 || J - 1 >= JP);    // continue to layer J-1
   const int g = lane / 32;
-  publish_delta<N, J>(lds, dz, g, colx);
   float ev[N::ENC_KS * N::KSTEP];
-  if constexpr (J == 0) {
-    encode_slots<N>(kp.ph, kp.pl, g, ev);
-    Act<N, rup(N::ENC_KS, N::KGRP)> a0;
-    enc_to_B<N>(ev, a0);
-    Hi<N, rup(N::ENC_KS, N::KGRP)> h0;
+  if constexpr (J == 0) encode_slots<N>(kp.ph, kp.pl, g, ev);
+  if constexpr (DW) {
+    publish_delta<N, J>(lds, dz, g, colx);
+    if constexpr (J == 0) {
+      Act<N, rup(N::ENC_KS, N::KGRP)> a0;
+      enc_to_B<N>(ev, a0);
+      Hi<N, rup(N::ENC_KS, N::KGRP)> h0;
 #pragma unroll
-    for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
-    publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx);
-  } else {
-    publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, kp.ah[J - 1], g, colx);
+      for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
+      publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx);
+    } else {
+      publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, input_hi<N, JP, J>(kp), g, colx);
+    }
   }
-  // transposed product for the next delta, overlapping the exchange
-  Act<N, rup(N::bks(J), N::KGRP)> Bd;
-  if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
-  else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
+  // transposed product for the next delta (or the input gradient), overlapping the exchange
   f32x16 da[N::brb(J)];
-  layer_bwd<N, J>(lds, lane, Bd, da);
-  __syncthreads();
-  dw_tiles<N, J>(lds, dacc, q, lane);
-  __syncthreads();
-  if constexpr (J > 0) {
+  if constexpr (DOWN || J == 0) {
+    Act<N, rup(N::bks(J), N::KGRP)> Bd;
+    if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
+    else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
+    layer_bwd<N, J>(wb, lane, Bd, da);
+  }
+  if constexpr (DW) {
+    __syncthreads();
+    dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(JP, J), q, lane);
+    __syncthreads();
+  }
+  if constexpr (DOWN) {
     // relu': the layer input a_J = relu(z_{J-1}) is positive where z_{J-1} is
     f32x16 dzn[N::RBH];
 #pragma unroll
     for (int rb = 0; rb < N::RBH; ++rb) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        int t = 16 * rb + r;
-        float a = bval<N>(kp.ah[J - 1].hi[t / N::KSTEP], t % N::KSTEP);
-        dzn[rb][r] = a > 0.f ? da[rb][r] : 0.f;
-      }
+      for (int r = 0; r < 16; ++r) dzn[rb][r] = gate<N, JP, J>(kp, 16 * rb + r) ? da[rb][r] : 0.f;
     }
-    chain_back<N, J - 1>(lds, lane, q, colx, kp, dzn, dp, dacc);
-  } else {
+    chain_back<N, J - 1, JP>(lds, wb, lane, q, colx, kp, dzn, dp, dacc);
+  } else if constexpr (J == 0) {
     // dL/dp of the sample from the input-feature gradient W_0^T delta_0
 #pragma unroll
     for (int a = 0; a < 3; ++a) dp[a] = 0.f;
@@ -371,7 +412,10 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, int lane, 
   }
 }
 
-template <class N>
+// JP < 0: one pass over every layer (weights staged in LDS); JP >= 0: the
+// pass of a wide network that accumulates layer JP's weight gradient (and,
+// for JP = 0, the geometry gradient), weights read from global memory
+template <class N, int JP>
 __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   using B = Bwd<N>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -388,10 +432,12 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * kHitsPerItem;
   const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(ws.wpack + (int64_t)p * ws.wpack_bytes);
+  const uint8_t* wts = ws.wpack + (int64_t)p * ws.wpack_bytes;
+  if constexpr (!N::WIDE) {
+    const uint4* src = reinterpret_cast<const uint4*>(wts);
     uint4* dst = reinterpret_cast<uint4*>(lds);
     for (int i = threadIdx.x; i < N::total_bytes() / 16; i += blockDim.x) dst[i] = src[i];
+    wts = lds;   // read after the barrier below
   }
   const int h0 = (nh * q) / B::NW, h1 = (nh * (q + 1)) / B::NW;
   const int c = h1 - h0;
@@ -410,9 +456,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   int rounds = 0;
   for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
   const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
-  f32x4 dacc[B::TT];
+  f32x4 dacc[B::tiles(JP)];
 #pragma unroll
-  for (int i = 0; i < B::TT; ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < B::tiles(JP); ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   // carries of the hit-local scans from block to block
   float cr_tau = 0.f, cr_P = 0.f, cr_geo[9];
 #pragma unroll
@@ -437,8 +483,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     const float sk = sample_position(ws, hit, k, u, ph, pl);
     const float om = ((float)k + u) / (float)K;
     const bool last = valid && k == K - 1;
-    Keep<N> kp;
-    f32x16 o = forward_keep<N>(lds, lane, ph, pl, kp);
+    Keep<N, JP> kp;
+    f32x16 o = forward_keep<N, JP>(wts, lane, ph, pl, kp);
 
     // ---- compositing adjoint of the column ----
     const int nused = valid ? ws.hit_nused[hit] : 0;
@@ -509,8 +555,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     cr_P = __shfl(P, 31, 32);
 
     // ---- network adjoint and weight gradients ----
-    float dp[3];
-    chain_back<N, N::NL - 1>(lds, lane, q, colx, kp, dz, dp, dacc);
+    float dp[3] = {0.f, 0.f, 0.f};
+    chain_back<N, N::NL - 1, JP>(lds, wts, lane, q, colx, kp, dz, dp, dacc);
+    if constexpr (JP > 0) continue;   // this pass has no geometry gradient
 
     // ---- dL/dp of the sample: the two lane halves hold disjoint encoding slots ----
 #pragma unroll
@@ -572,7 +619,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   }
 
   // ---- flush the weight-gradient strips ----
-  flush_dw<N, 0>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
+  if constexpr (JP < 0) flush_all<N, 0>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
+  else flush_dw<N, JP>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
   // ---- flush the geometry sums ----
   __syncthreads();
   if (threadIdx.x < 12 && gsum_s[threadIdx.x] != 0.f)
@@ -581,22 +629,32 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 
 }  // namespace
 
+template <class N, int JP>
+static hipError_t bwd_pass(const BwdArgs& a, int items, hipStream_t s) {
+  size_t lds = Bwd<N>::LDS;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)mlp_backward_kernel<N, JP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((mlp_backward_kernel<N, JP>), dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if constexpr (JP >= 0 && JP + 1 < N::NL) {
+    if (e == hipSuccess) return bwd_pass<N, JP + 1>(a, items, s);
+  }
+  return e;
+}
+
 template <class N>
 static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items, int P, int n_params,
                            const float* ray_d, const float* grad_rgb, const float* grad_feat,
                            float* g_mlp, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   BwdArgs a{ws, o, P, n_params, ray_d, grad_rgb, grad_feat, g_mlp};
-  size_t lds = Bwd<N>::LDS;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)mlp_backward_kernel<N>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
-  hipLaunchKernelGGL(mlp_backward_kernel<N>, dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
-  return hipGetLastError();
+  if constexpr (N::WIDE) return bwd_pass<N, 0>(a, items, s);
+  else return bwd_pass<N, -1>(a, items, s);
 }
 
 hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,

@@ -67,6 +67,10 @@ struct Net {
   static constexpr int OUT_SLOTS = 4 * ((NOUT + 7) / 8);
   static constexpr int OUT_KS = rup(OUT_SLOTS, KSTEP) / KSTEP;
   static constexpr int RB0 = (ENC_SLOTS + 15) / 16;   // row blocks of the input-gradient
+  // wide networks read their weight operands from global memory (they stay
+  // in L2 while a primitive's work items run) instead of staging them in LDS,
+  // and split the backward into one pass per layer's weight gradient
+  static constexpr bool WIDE = W > 64;
   static_assert(L % 2 == 0, "encoding split needs an even number of levels");
   static_assert(W % 32 == 0, "hidden width must be a multiple of 32");
   static_assert(NOUT >= 4 && NOUT <= 24, "4..24 outputs");
@@ -124,10 +128,11 @@ __device__ __forceinline__ float net_weight(const float* th, int j, int n, int f
 }
 
 // Compiled networks: (pe_freqs, hidden width, hidden layers, outputs, precision).
-#define MSPLAT_NETS(X)                                                              \
-  X(4, 32, 2, 4, MSPLAT_FP32) X(4, 32, 2, 4, MSPLAT_BF16) X(4, 32, 2, 4, MSPLAT_BF16X3) \
-  X(6, 64, 3, 4, MSPLAT_FP32) X(6, 64, 3, 4, MSPLAT_BF16) X(6, 64, 3, 4, MSPLAT_BF16X3) \
-  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3)
+#define MSPLAT_NETS(X)                                                                 \
+  X(4, 32, 2, 4, MSPLAT_FP32) X(4, 32, 2, 4, MSPLAT_BF16) X(4, 32, 2, 4, MSPLAT_BF16X3)    \
+  X(6, 64, 3, 4, MSPLAT_FP32) X(6, 64, 3, 4, MSPLAT_BF16) X(6, 64, 3, 4, MSPLAT_BF16X3)    \
+  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3) \
+  X(6, 128, 4, 20, MSPLAT_FP32) X(6, 128, 4, 20, MSPLAT_BF16) X(6, 128, 4, 20, MSPLAT_BF16X3)
 #define MSPLAT_NET(L_, W_, D_, O_, P_) Net<L_, W_, D_, O_, (P_) != MSPLAT_FP32, (P_) == MSPLAT_BF16X3>
 #define MSPLAT_MATCH(L_, W_, D_, O_, P_) \
   if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && n.prec == (P_))

@@ -102,20 +102,21 @@ __device__ __forceinline__ void act_set(Act<N, NK>& a, int s, int e, float x) {
   }
 }
 
-// one dense layer on the matrix cores: acc[rb] = bias + W_j x
+// one dense layer on the matrix cores: acc[rb] = bias + W_j x.  `wb` is the
+// primitive's packed operands, staged in LDS or (wide networks) in global memory.
 template <class N, int J, int KS>
-__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ lds, int lane,
+__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
                                           const Act<N, rup(KS, N::KGRP)>& B,
                                           f32x16 (&acc)[N::frb(J)]) {
   constexpr int RB = N::frb(J);
   constexpr int NG = N::groups(KS);
-  const uint8_t* A = lds + N::fwdA_off(J);
+  const uint8_t* A = wb + N::fwdA_off(J);
   int g = lane / 32;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     f32x16 c;
     if constexpr (J > 0) {
-      const uint8_t* bp = lds + N::bias_off(J) + ((rb * 2 + g) * 16) * 4;
+      const uint8_t* bp = wb + N::bias_off(J) + ((rb * 2 + g) * 16) * 4;
       f32x4 b0 = as_f32x4(lds16(bp)), b1 = as_f32x4(lds16(bp + 16)), b2 = as_f32x4(lds16(bp + 32)),
             b3 = as_f32x4(lds16(bp + 48));
 #pragma unroll
@@ -162,6 +163,25 @@ __device__ __forceinline__ void relu_to_B(const f32x16 (&acc)[N::RBH],
     for (int r = 0; r < 16; ++r) {
       int t = 16 * rb + r;
       act_set<N>(B, t / N::KSTEP, t % N::KSTEP, fmaxf(acc[rb][r], 0.f));
+    }
+  }
+}
+
+// ReLU gates of a hidden layer's D registers as bits (slot t = 16 rb + r)
+template <class N>
+struct Gates {
+  uint32_t w[(16 * N::RBH + 31) / 32];
+};
+template <class N>
+__device__ __forceinline__ void gates_of(const f32x16 (&acc)[N::RBH], Gates<N>& m) {
+#pragma unroll
+  for (int i = 0; i < (16 * N::RBH + 31) / 32; ++i) m.w[i] = 0u;
+#pragma unroll
+  for (int rb = 0; rb < N::RBH; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      int t = 16 * rb + r;
+      if (acc[rb][r] > 0.f) m.w[t / 32] |= 1u << (t % 32);
     }
   }
 }

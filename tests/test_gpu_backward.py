@@ -11,7 +11,7 @@ from gpu_cases import (RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(0, 40, 36), (1, 64, 50), (4, 44, 40)]
+CASES = [(0, 40, 36), (1, 64, 50), (4, 44, 40), (3, 40, 30)]
 KEYS = ("center", "scale", "quat", "mlp")
 
 
@@ -24,6 +24,8 @@ def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
     rng = np.random.default_rng(1000 * ci + 4)
     g_rgb = (rng.standard_normal((R, 3)) / R).astype(np.float32)
     g_tr = (rng.standard_normal(R) / R).astype(np.float32) if with_trans else None
+    cf = cfg.out_dim - 4
+    g_ft = (rng.standard_normal((R, cf)) / R).astype(np.float32) if cf > 0 else None
     g = gpu_render(ci, precision, sc, o, d, opts)
     # a termination cut on a neighbouring sample (threshold crossing within
     # rounding) and a ReLU gate within rounding of its switching point are
@@ -39,13 +41,16 @@ def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
     g_rgb[~keep] = 0.0
     if g_tr is not None:
         g_tr[~keep] = 0.0
+    if g_ft is not None:
+        g_ft[~keep] = 0.0
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
                                             oracle_model(cfg), oracle_opts(opts), grad_rgb=g_rgb,
-                                            grad_trans=g_tr)
+                                            grad_trans=g_tr, grad_feat=g_ft)
     t, to, td = g["dev"]
     gt = None if g_tr is None else torch.from_numpy(g_tr).cuda()
+    gf = None if g_ft is None else torch.from_numpy(g_ft).cuda()
     gc, gs, gq, gm = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
-                                            torch.from_numpy(g_rgb).cuda(), gt)
+                                            torch.from_numpy(g_rgb).cuda(), gt, gf)
     got = {"center": gc.cpu().numpy(), "scale": gs.cpu().numpy(), "quat": gq.cpu().numpy(),
            "mlp": gm.cpu().numpy()}
     return got, ref, sc

@@ -4,14 +4,14 @@ import pytest
 import torch
 
 import synth
-from gpu_cases import (compare_rgb, gpu_render, opts_of, oracle_render, scene, spec_of, to_dev,
-                       view_rays)
+from gpu_cases import (compare_rgb, gpu_render, opts_of, oracle_render, ray_nused, scene, spec_of,
+                       to_dev, view_rays)
 
 pytestmark = pytest.mark.gpu
 
 # (config, width, height): small frames that span several 8x8 tiles and a
 # ragged tail of rays (counts not a multiple of 64)
-CASES = [(0, 64, 64), (1, 100, 75), (4, 90, 70)]
+CASES = [(0, 64, 64), (1, 100, 75), (4, 90, 70), (3, 72, 41)]
 
 
 def _case(ci, w, h, t_stop=None):
@@ -41,6 +41,12 @@ def test_forward_matches_oracle(ci, w, h, precision, tol):
     c = compare_rgb(g, ref, tol, opts.t_stop)
     print(f"config {ci} {precision}: {c}")
     assert c["max_err"] <= tol
+    if g["feat"] is not None:
+        # feature channels are composited like colour
+        same = ray_nused(g) == ref["n_used"]
+        ferr = float(np.abs(g["feat"] - ref["feat"])[same].max())
+        print(f"feature max err {ferr:.3g}")
+        assert ferr <= tol * max(1.0, float(np.abs(ref["feat"]).max()))
     assert c["max_terr"] <= max(tol, 1e-5) * 4
     # a cut that falls on a neighbouring sample changes the pixel by < T_stop
     assert c["cut_mismatch_err"] <= opts.t_stop + tol
