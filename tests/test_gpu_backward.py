@@ -124,3 +124,47 @@ def test_autograd_function_mse_matches_direct_backward():
                                             oracle_model(cfg), oracle_opts(opts), grad_rgb=g_ref)
     for k in KEYS:
         assert _rel(params[k].grad.cpu().numpy(), ref[k]) <= 1e-5, k
+
+
+@pytest.mark.parametrize("ci,precision", [(1, "fp32"), (1, "bf16x3"), (3, "bf16x3"), (4, "fp32"),
+                                          (4, "bf16x3")])
+def test_full_size_gradient_of_sampled_rays(ci, precision):
+    """Full-size backward (all hits and work items of the benchmark's launch)
+    with upstream gradient on 256 seeded rays only: the result is the gradient
+    of those rays' pixels, which the oracle computes on the subset."""
+    tol = {"fp32": 1e-5, "bf16x3": 2e-3}[precision]
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d, _ = synth.make_rays(cfg)
+    opts = opts_of(cfg)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    idx = np.sort(np.random.default_rng(78).choice(len(o), 256, replace=False))
+    ref_fwd = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx, margins=True)
+    keep = (ray_nused(g)[idx] == ref_fwd["n_used"]) & (ref_fwd["relu_margin"] >= RELU_AMBIGUOUS[precision])
+    rng = np.random.default_rng(1000 * ci + 5)
+    g_sub = rng.standard_normal((len(idx), 3)) / len(idx)
+    g_sub[~keep] = 0.0
+    cf = cfg.out_dim - 4
+    f_sub = rng.standard_normal((len(idx), cf)) / len(idx) if cf > 0 else None
+    if f_sub is not None:
+        f_sub[~keep] = 0.0
+    g_rgb = np.zeros((len(o), 3), np.float32)
+    g_rgb[idx] = g_sub
+    g_ft = None
+    if f_sub is not None:
+        g_ft = np.zeros((len(o), cf), np.float32)
+        g_ft[idx] = f_sub
+    t, to, td = g["dev"]
+    out = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                 torch.from_numpy(g_rgb).cuda(), None,
+                                 None if g_ft is None else torch.from_numpy(g_ft).cuda())
+    got = dict(zip(KEYS, [x.cpu().numpy() for x in out]))
+    _, _, _, ref, _ = oracle.loss_and_grads(sc, o[idx].astype(np.float64), d[idx].astype(np.float64),
+                                            oracle_model(cfg), oracle_opts(opts),
+                                            grad_rgb=g_rgb[idx].astype(np.float64),
+                                            grad_feat=None if g_ft is None else g_ft[idx].astype(np.float64),
+                                            ray_ids=idx)
+    errs = {k: _rel(got[k], ref[k]) for k in KEYS}
+    print(f"config {ci} full size {precision}: {int(keep.sum())} of 256 rays kept, rel errors {errs}")
+    for k in KEYS:
+        assert errs[k] <= tol, (k, errs[k])

@@ -42,11 +42,15 @@ def test_forward_matches_oracle(ci, w, h, precision, tol):
     print(f"config {ci} {precision}: {c}")
     assert c["max_err"] <= tol
     if g["feat"] is not None:
-        # feature channels are composited like colour
+        # feature channels are composited like colour but leave the network
+        # unsquashed: the sigmoid in front of RGB has slope <= 1/4, so the same
+        # raw-output accuracy that keeps RGB within tol keeps features within
+        # 4 tol, relative to their magnitude
         same = ray_nused(g) == ref["n_used"]
         ferr = float(np.abs(g["feat"] - ref["feat"])[same].max())
-        print(f"feature max err {ferr:.3g}")
-        assert ferr <= tol * max(1.0, float(np.abs(ref["feat"]).max()))
+        fmax = float(np.abs(ref["feat"]).max())
+        print(f"feature max err {ferr:.3g} (max |feature| {fmax:.3g})")
+        assert ferr <= 4 * tol * max(1.0, fmax)
     assert c["max_terr"] <= max(tol, 1e-5) * 4
     # a cut that falls on a neighbouring sample changes the pixel by < T_stop
     assert c["cut_mismatch_err"] <= opts.t_stop + tol
@@ -54,21 +58,31 @@ def test_forward_matches_oracle(ci, w, h, precision, tol):
     assert c["n_cut_mismatch"] <= max(1, len(o) // (100 if precision == "bf16" else 1000))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 2e-3)])
-def test_full_frame_800_sampled_rays(precision, tol):
-    """Config 1 at its full 800x800 size, checked on 1024 seeded pixels."""
-    ci = 1
+TOL = {"fp32": 1e-5, "bf16": 2e-3, "bf16x3": 2e-3}
+
+
+@pytest.mark.parametrize("ci,precision", [(1, "fp32"), (1, "bf16"), (1, "bf16x3"), (3, "fp32"),
+                                          (3, "bf16x3"), (4, "fp32"), (4, "bf16x3")])
+def test_full_size_sampled_rays(ci, precision):
+    """Configs 1 (800x800), 3 (1920x1080, 128-wide networks) and 4 (16 views,
+    7 M rays) rendered at full size in one call, as the benchmark launches
+    them, checked on 512 seeded rays against the oracle."""
+    tol = TOL[precision]
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
     o, d, _ = synth.make_rays(cfg)
     opts = opts_of(cfg)
     g = gpu_render(ci, precision, sc, o, d, opts)
-    idx = np.sort(np.random.default_rng(77).choice(len(o), 1024, replace=False))
-    # make sure sampled rays include hits
+    idx = np.sort(np.random.default_rng(77).choice(len(o), 512, replace=False))
     ref = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx)
     c = compare_rgb(g, ref, tol, opts.t_stop, idx=idx)
-    print(f"800x800 {precision}: {c} stats {g['stats']}")
+    print(f"config {ci} full size {precision}: {c} stats {g['stats']}")
     assert c["max_err"] <= tol
+    assert c["cut_mismatch_err"] <= opts.t_stop + tol
+    if g["feat"] is not None:
+        same = ray_nused(g)[idx] == ref["n_used"]
+        ferr = float(np.abs(g["feat"][idx] - ref["feat"])[same].max())
+        assert ferr <= 4 * tol * max(1.0, float(np.abs(ref["feat"]).max()))
 
 
 def test_forward_is_deterministic_and_label_invariant():
