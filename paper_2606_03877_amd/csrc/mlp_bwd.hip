@@ -51,10 +51,9 @@ struct Bwd {
   static constexpr int OWN(int j) { return (RT(j) + NW - 1) / NW; }
   static constexpr int TOFF(int j) { return j == 0 ? 0 : TOFF(j - 1) + OWN(j - 1) * CTB(j - 1); }
   static constexpr int TT = TOFF(N::NL);
-  // pass JP < 0 accumulates every layer's weight gradient; pass JP >= 0 (wide
-  // networks) only layer JP's
-  static constexpr int tiles(int jp) { return jp < 0 ? TT : OWN(jp) * CTB(jp); }
-  static constexpr int toff(int jp, int j) { return jp < 0 ? TOFF(j) : 0; }
+  // a pass accumulates the weight gradients of layers LO..HI
+  static constexpr int tiles(int lo, int hi) { return TOFF(hi + 1) - TOFF(lo); }
+  static constexpr int toff(int lo, int j) { return TOFF(j) - TOFF(lo); }
 };
 
 template <class N>
@@ -253,11 +252,11 @@ __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __
   }
 }
 
-template <class N, int J>
-__device__ __forceinline__ void flush_all(const f32x4* __restrict__ dacc, float* __restrict__ gm, int q,
-                                          int lane) {
-  flush_dw<N, J>(dacc + Bwd<N>::TOFF(J), gm, q, lane);
-  if constexpr (J + 1 < N::NL) flush_all<N, J + 1>(dacc, gm, q, lane);
+template <class N, int J, int LO, int HI>
+__device__ __forceinline__ void flush_range(const f32x4* __restrict__ dacc, float* __restrict__ gm, int q,
+                                            int lane) {
+  flush_dw<N, J>(dacc + Bwd<N>::toff(LO, J), gm, q, lane);
+  if constexpr (J < HI) flush_range<N, J + 1, LO, HI>(dacc, gm, q, lane);
 }
 
 struct BwdArgs {
@@ -271,49 +270,47 @@ struct BwdArgs {
   float* g_mlp;
 };
 
-// per-sample state kept from the recompute: the sample position (the
-// encoding is evaluated again where it is needed) and, for pass JP < 0, the
-// hi part of every hidden layer's input (its ReLU gates and the weight-
-// gradient operand); for a wide network's pass JP >= 0, the gates of every
-// hidden layer as bits and the hi part of layer JP's input only.
-template <class N, int JP>
+// per-sample state kept from the recompute for a pass over layers LO..HI:
+// the sample position (the encoding is evaluated again where it is needed),
+// the hi part of the inputs of layers max(LO,1)..HI (their ReLU gates and the
+// weight-gradient operand), and the gates of the layers above HI as bits
+template <class N, int LO, int HI>
 struct Keep {
+  static constexpr int H0 = LO > 1 ? LO : 1;
+  static constexpr int NH = HI - H0 + 1;
+  static constexpr int NG = N::NL - 1 - HI;
   float ph[3], pl[3];
-  Hi<N, rup(N::HID_KS, N::KGRP)> ah[JP < 0 ? N::NL - 1 : 1];
-  Gates<N> gt[JP < 0 ? 1 : N::NL - 1];
+  Hi<N, rup(N::HID_KS, N::KGRP)> ah[NH > 0 ? NH : 1];
+  Gates<N> gt[NG > 0 ? NG : 1];
 };
 
-template <class N, int JP, int J>
-__device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_hi(const Keep<N, JP>& kp) {
-  if constexpr (JP < 0) return kp.ah[J - 1]; else return kp.ah[0];
+template <class N, int LO, int HI, int J>
+__device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_hi(const Keep<N, LO, HI>& kp) {
+  return kp.ah[J - Keep<N, LO, HI>::H0];
 }
 
 // ReLU gate of slot t of layer J's input (its pre-activation was positive)
-template <class N, int JP, int J>
-__device__ __forceinline__ bool gate(const Keep<N, JP>& kp, int t) {
-  if constexpr (JP < 0) return bval<N>(kp.ah[J - 1].hi[t / N::KSTEP], t % N::KSTEP) > 0.f;
-  else return (kp.gt[J - 1].w[t / 32] >> (t % 32)) & 1u;
+template <class N, int LO, int HI, int J>
+__device__ __forceinline__ bool gate(const Keep<N, LO, HI>& kp, int t) {
+  if constexpr (J <= HI) return bval<N>(input_hi<N, LO, HI, J>(kp).hi[t / N::KSTEP], t % N::KSTEP) > 0.f;
+  else return (kp.gt[J - HI - 1].w[t / 32] >> (t % 32)) & 1u;
 }
 
 // forward recompute keeping what the backward needs
-template <class N, int J, int JP>
-__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int lane, Keep<N, JP>& kp,
+template <class N, int J, int LO, int HI>
+__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int lane, Keep<N, LO, HI>& kp,
                                            f32x16 (&acc)[N::RBH], f32x16& out) {
   Act<N, rup(N::HID_KS, N::KGRP)> x;
   relu_to_B<N>(acc, x);
-  if constexpr (JP < 0) {
+  if constexpr (J >= Keep<N, LO, HI>::H0 && J <= HI) {
 #pragma unroll
-    for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - 1].hi[i] = x.hi[i];
-  } else {
-    gates_of<N>(acc, kp.gt[J - 1]);
-    if constexpr (J == JP) {
-#pragma unroll
-      for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[0].hi[i] = x.hi[i];
-    }
+    for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - Keep<N, LO, HI>::H0].hi[i] = x.hi[i];
+  } else if constexpr (J > HI) {
+    gates_of<N>(acc, kp.gt[J - HI - 1]);
   }
   if constexpr (J < N::NL - 1) {
     layer_fwd<N, J, N::HID_KS>(wb, lane, x, acc);
-    chain_keep<N, J + 1, JP>(wb, lane, kp, acc, out);
+    chain_keep<N, J + 1, LO, HI>(wb, lane, kp, acc, out);
   } else {
     f32x16 o[1];
     layer_fwd<N, J, N::HID_KS>(wb, lane, x, o);
@@ -321,9 +318,9 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int l
   }
 }
 
-template <class N, int JP>
+template <class N, int LO, int HI>
 __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, int lane, const float ph[3],
-                                               const float pl[3], Keep<N, JP>& kp) {
+                                               const float pl[3], Keep<N, LO, HI>& kp) {
   int g = lane / 32;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -339,20 +336,20 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, i
     layer_fwd<N, 0, N::ENC_KS>(wb, lane, a0, acc);
   }
   f32x16 out;
-  chain_keep<N, 1, JP>(wb, lane, kp, acc, out);
+  chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);
   return out;
 }
 
 // backward through layer J (and below): the transposed product towards layer
 // J-1, and, where the pass accumulates layer J's weight gradient, the
 // exchange of the block's deltas and inputs with the other waves
-template <class N, int J, int JP>
+template <class N, int J, int LO, int HI>
 __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint8_t* __restrict__ wb, int lane,
-                                           int q, int colx, const Keep<N, JP>& kp,
+                                           int q, int colx, const Keep<N, LO, HI>& kp,
                                            const f32x16 (&dz)[N::frb(J)], float (&dp)[3],
                                            f32x4* __restrict__ dacc) {
-  constexpr bool DW = JP < 0 || J == JP;                     // layer J's weight gradient
-  constexpr bool DOWN = J > 0 && (JP < 0 || J - 1 >= JP);    // continue to layer J-1
+  constexpr bool DW = J >= LO && J <= HI;     // layer J's weight gradient
+  constexpr bool DOWN = J > 0 && J - 1 >= LO;  // continue to layer J-1
   const int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
   if constexpr (J == 0) encode_slots<N>(kp.ph, kp.pl, g, ev);
@@ -366,7 +363,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
       for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
       publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx);
     } else {
-      publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, input_hi<N, JP, J>(kp), g, colx);
+      publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, input_hi<N, LO, HI, J>(kp), g, colx);
     }
   }
   // transposed product for the next delta (or the input gradient), overlapping the exchange
@@ -379,7 +376,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   }
   if constexpr (DW) {
     __syncthreads();
-    dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(JP, J), q, lane);
+    dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(LO, J), q, lane);
     __syncthreads();
   }
   if constexpr (DOWN) {
@@ -388,9 +385,9 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
 #pragma unroll
     for (int rb = 0; rb < N::RBH; ++rb) {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dzn[rb][r] = gate<N, JP, J>(kp, 16 * rb + r) ? da[rb][r] : 0.f;
+      for (int r = 0; r < 16; ++r) dzn[rb][r] = gate<N, LO, HI, J>(kp, 16 * rb + r) ? da[rb][r] : 0.f;
     }
-    chain_back<N, J - 1, JP>(lds, wb, lane, q, colx, kp, dzn, dp, dacc);
+    chain_back<N, J - 1, LO, HI>(lds, wb, lane, q, colx, kp, dzn, dp, dacc);
   } else if constexpr (J == 0) {
     // dL/dp of the sample from the input-feature gradient W_0^T delta_0
 #pragma unroll
@@ -412,10 +409,11 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   }
 }
 
-// JP < 0: one pass over every layer (weights staged in LDS); JP >= 0: the
-// pass of a wide network that accumulates layer JP's weight gradient (and,
-// for JP = 0, the geometry gradient), weights read from global memory
-template <class N, int JP>
+// one pass of the backward: recompute the network, chain the adjoint down to
+// layer LO and accumulate the weight gradients of layers LO..HI (and, when LO
+// is 0, the geometry gradient).  Weights are staged in LDS, or read from
+// global memory for wide networks.
+template <class N, int LO, int HI>
 __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   using B = Bwd<N>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -456,9 +454,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   int rounds = 0;
   for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
   const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
-  f32x4 dacc[B::tiles(JP)];
+  f32x4 dacc[B::tiles(LO, HI)];
 #pragma unroll
-  for (int i = 0; i < B::tiles(JP); ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < B::tiles(LO, HI); ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   // carries of the hit-local scans from block to block
   float cr_tau = 0.f, cr_P = 0.f, cr_geo[9];
 #pragma unroll
@@ -483,8 +481,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     const float sk = sample_position(ws, hit, k, u, ph, pl);
     const float om = ((float)k + u) / (float)K;
     const bool last = valid && k == K - 1;
-    Keep<N, JP> kp;
-    f32x16 o = forward_keep<N, JP>(wts, lane, ph, pl, kp);
+    Keep<N, LO, HI> kp;
+    f32x16 o = forward_keep<N, LO, HI>(wts, lane, ph, pl, kp);
 
     // ---- compositing adjoint of the column ----
     const int nused = valid ? ws.hit_nused[hit] : 0;
@@ -556,8 +554,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 
     // ---- network adjoint and weight gradients ----
     float dp[3] = {0.f, 0.f, 0.f};
-    chain_back<N, N::NL - 1, JP>(lds, wts, lane, q, colx, kp, dz, dp, dacc);
-    if constexpr (JP > 0) continue;   // this pass has no geometry gradient
+    chain_back<N, N::NL - 1, LO, HI>(lds, wts, lane, q, colx, kp, dz, dp, dacc);
+    if constexpr (LO > 0) continue;   // this pass has no geometry gradient
 
     // ---- dL/dp of the sample: the two lane halves hold disjoint encoding slots ----
 #pragma unroll
@@ -619,8 +617,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   }
 
   // ---- flush the weight-gradient strips ----
-  if constexpr (JP < 0) flush_all<N, 0>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
-  else flush_dw<N, JP>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
+  flush_range<N, LO, LO, HI>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
   // ---- flush the geometry sums ----
   __syncthreads();
   if (threadIdx.x < 12 && gsum_s[threadIdx.x] != 0.f)
@@ -629,20 +626,26 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 
 }  // namespace
 
-template <class N, int JP>
+template <class N, int LO, int HI>
 static hipError_t bwd_pass(const BwdArgs& a, int items, hipStream_t s) {
   size_t lds = Bwd<N>::LDS;
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)mlp_backward_kernel<N, JP>,
+    hipError_t e = hipFuncSetAttribute((const void*)mlp_backward_kernel<N, LO, HI>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((mlp_backward_kernel<N, JP>), dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
-  hipError_t e = hipGetLastError();
-  if constexpr (JP >= 0 && JP + 1 < N::NL) {
-    if (e == hipSuccess) return bwd_pass<N, JP + 1>(a, items, s);
+  hipLaunchKernelGGL((mlp_backward_kernel<N, LO, HI>), dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
+  return hipGetLastError();
+}
+
+// wide networks: one pass per layer, from layer J up
+template <class N, int J>
+static hipError_t wide_passes(const BwdArgs& a, int items, hipStream_t s) {
+  hipError_t e = bwd_pass<N, J, J>(a, items, s);
+  if constexpr (J + 1 < N::NL) {
+    if (e == hipSuccess) return wide_passes<N, J + 1>(a, items, s);
   }
   return e;
 }
@@ -653,8 +656,16 @@ static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items,
                            float* g_mlp, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   BwdArgs a{ws, o, P, n_params, ray_d, grad_rgb, grad_feat, g_mlp};
-  if constexpr (N::WIDE) return bwd_pass<N, 0>(a, items, s);
-  else return bwd_pass<N, -1>(a, items, s);
+  if constexpr (N::WIDE) {
+    return wide_passes<N, 0>(a, items, s);
+  } else if constexpr (N::PASSES) {
+    // the upper half of the layers, then the lower half with the geometry
+    constexpr int M = N::NL / 2;
+    hipError_t e = bwd_pass<N, M, N::NL - 1>(a, items, s);
+    return e != hipSuccess ? e : bwd_pass<N, 0, M - 1>(a, items, s);
+  } else {
+    return bwd_pass<N, 0, N::NL - 1>(a, items, s);
+  }
 }
 
 hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,

@@ -71,6 +71,10 @@ struct Net {
   // in L2 while a primitive's work items run) instead of staging them in LDS,
   // and split the backward into one pass per layer's weight gradient
   static constexpr bool WIDE = W > 64;
+  // backward split into two passes over halves of the layers (fewer live
+  // weight-gradient accumulators, the network recomputed twice); measured
+  // slower than one spilling pass for the 64-wide split form, so off
+  static constexpr bool PASSES = false;
   static_assert(L % 2 == 0, "encoding split needs an even number of levels");
   static_assert(W % 32 == 0, "hidden width must be a multiple of 32");
   static_assert(NOUT >= 4 && NOUT <= 24, "4..24 outputs");
