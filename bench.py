@@ -161,9 +161,35 @@ def cpu_baseline(cfg, sc, o, d, target, opts, budget_s=12.0, chunk=2048, seed=5)
                               target_rgb=target[idx].astype(np.float64), chunk=chunk, ray_ids=idx)
         done += len(idx)
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "rays/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{done} seeded rays of the same frame in chunks of {chunk}, forward+backward "
-                      f"(autograd FP64), {dt:.1f} s"}
+    out = {"value": done / dt, "unit": "rays/s", "cores": torch.get_num_threads(), "kind": "oracle",
+           "sample": f"{done} seeded rays of the same frame in chunks of {chunk}, forward+backward "
+                     f"(autograd FP64), {dt:.1f} s"}
+    # the same on one host thread, over a third of the budget
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        done1 = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s / 3 and done1 < len(o):
+            idx = np.sort(order[done1:done1 + chunk // 4])
+            oracle.loss_and_grads(sc, o[idx].astype(np.float64), d[idx].astype(np.float64), m, oo,
+                                  target_rgb=target[idx].astype(np.float64), chunk=chunk, ray_ids=idx)
+            done1 += len(idx)
+        out["value_1_thread"] = done1 / (time.perf_counter() - t0)
+    finally:
+        torch.set_num_threads(nthreads)
+    out["host_cpu"] = _cpu_model()
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip() + f", {os.cpu_count()} logical CPUs visible"
+    except OSError:
+        pass
+    return "unknown"
 
 
 def traffic_from_profiles(kernel: str, workload: str, precision: str):
@@ -294,7 +320,12 @@ def main():
         "cpu_baseline": cpu,
     }
     out["legs"] = {k: {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"],
+                       "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
                        "fwd_ms": v["fwd_ms"], "fwdbwd_ms": v["fwdbwd_ms"]} for k, v in legs.items()}
+    if "fp32" in legs:
+        out["speedup_vs_fp32"] = {k: {"fwd": v["fwd_rays_per_s"] / legs["fp32"]["fwd_rays_per_s"],
+                                      "fwdbwd": v["fwdbwd_rays_per_s"] / legs["fp32"]["fwdbwd_rays_per_s"]}
+                                  for k, v in legs.items() if k != "fp32"}
     print(json.dumps(out), flush=True)
 
 

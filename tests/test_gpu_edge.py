@@ -1,0 +1,72 @@
+"""GPU parity in the corners of the option space: rays starting inside a
+primitive (chord clipped at t = 0), a non-black background, midpoint samples
+(no jitter), chord-proportional sample counts up to the 128 maximum, and an
+early-termination threshold high enough to cut most rays."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_cases import (RELU_AMBIGUOUS, compare_rgb, gpu_render, oracle_model, oracle_opts, oracle_render,
+                       ray_nused, scene)
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("center", "scale", "quat", "mlp")
+TOL = {"fp32": 1e-5, "bf16x3": 2e-3}
+
+
+def _rays_from_inside(ci, n, seed):
+    """n rays from the centre of primitive 0 (so its chord starts at t = 0)
+    plus n rays from a camera outside, in seeded random directions."""
+    sc = scene(ci)
+    rng = np.random.default_rng(seed)
+    d = rng.standard_normal((2 * n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.empty((2 * n, 3))
+    o[:n] = sc["center"][0]
+    o[n:] = [0.2, -2.5, 0.4]
+    return sc, o.astype(np.float32), d.astype(np.float32)
+
+
+def _opts(t_stop):
+    from paper_2606_03877_amd import RenderOpts
+    return RenderOpts(samples_fixed=0, samples_min=8, samples_max=128, samples_per_unit=400.0,
+                      t_stop=t_stop, jitter=0, jitter_seed=0, background=(0.3, 0.5, 0.7))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("t_stop", [0.0, 0.3])
+def test_clipped_chords_background_midpoints(precision, t_stop):
+    ci = 0
+    sc, o, d = _rays_from_inside(ci, 600, seed=31)
+    opts = _opts(t_stop)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    ref = oracle_render(ci, sc, o, d, opts, margins=True)
+    np.testing.assert_array_equal(g["ray_off"], ref["ray_off"])
+    np.testing.assert_array_equal(g["prim"], ref["prim"])
+    c = compare_rgb(g, ref, TOL[precision], opts.t_stop)
+    K = np.asarray(oracle.render(*[oracle.to_tensors(sc)[k] for k in KEYS],
+                                 torch.from_numpy(o[:4].astype(np.float64)),
+                                 torch.from_numpy(d[:4].astype(np.float64)),
+                                 oracle_model(synth.CONFIGS[ci]), oracle_opts(opts))["K"])
+    print(f"{precision} t_stop={t_stop}: {c}; K of the first hits {K}")
+    assert c["max_err"] <= TOL[precision]
+    assert c["cut_mismatch_err"] <= opts.t_stop + TOL[precision]
+    # gradients, rays with a cut or gate decided within rounding left out
+    same = ray_nused(g) == ref["n_used"]
+    keep = same & (ref["relu_margin"] >= RELU_AMBIGUOUS[precision])
+    g_rgb = (np.random.default_rng(32).standard_normal((len(o), 3)) / len(o)).astype(np.float32)
+    g_rgb[~keep] = 0.0
+    t, to, td = g["dev"]
+    out = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                 torch.from_numpy(g_rgb).cuda())
+    got = dict(zip(KEYS, [x.cpu().numpy() for x in out]))
+    _, _, _, grads, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
+                                              oracle_model(synth.CONFIGS[ci]), oracle_opts(opts),
+                                              grad_rgb=g_rgb)
+    for k in KEYS:
+        err = float(np.abs(got[k] - grads[k]).max() / max(np.abs(grads[k]).max(), 1e-30))
+        print(f"  {k}: {err:.2e}")
+        assert err <= TOL[precision], k
