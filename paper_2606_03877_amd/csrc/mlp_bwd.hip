@@ -227,6 +227,9 @@ template <class N, int J>
 __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __restrict__ gm, int q,
                                          int lane) {
   using B = Bwd<N>;
+  // folded here: the recursive offset helpers are not inlined when called
+  // from a run-time expression, and a call costs the kernel its registers
+  constexpr int OW = N::off_w(J), OB = N::off_b(J), OB0 = N::off_b(0);
   const int r16 = lane % 16, rq = lane / 16;
 #pragma unroll
   for (int i = 0; i < B::OWN(J); ++i) {
@@ -242,10 +245,10 @@ __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __
         if (ct < B::CT(J)) {
           int f = 16 * ct + r16;
           if (f >= B::inp(J)) continue;
-          int idx = (J == 0 && f == N::IN) ? N::off_b(0) + n : N::off_w(J) + n * N::fin(J) + f;
+          int idx = (J == 0 && f == N::IN) ? OB0 + n : OW + n * N::fin(J) + f;
           atomicAdd(gm + idx, v[r]);
         } else if (r16 == 0) {
-          atomicAdd(gm + N::off_b(J) + n, v[r]);
+          atomicAdd(gm + OB + n, v[r]);
         }
       }
     }
@@ -477,16 +480,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     float u = 0.5f;
     if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
-    float ph[3], pl[3];
-    const float sk = sample_position(ws, hit, k, u, ph, pl);
-    const float om = ((float)k + u) / (float)K;
-    const bool last = valid && k == K - 1;
-    Keep<N, LO, HI> kp;
-    f32x16 o = forward_keep<N, LO, HI>(wts, lane, ph, pl, kp);
-
-    // ---- compositing adjoint of the column ----
+    // the hit's compositing records and the ray's upstream gradient are
+    // loaded before the recompute so that their latency overlaps it
     const int nused = valid ? ws.hit_nused[hit] : 0;
-    const bool used = valid && k < nused;
     const float tb = valid ? ws.hit_tb[hit] : 0.f;
     const float gtot = valid ? ws.hit_gtot[hit] : 0.f;
     const float gsa = valid ? ws.hit_gsa[hit] : 0.f;
@@ -495,6 +491,15 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 #pragma unroll
       for (int r = 0; r < 3; ++r) gr[r] = args.grad_rgb[3 * ray + r];
     }
+    float ph[3], pl[3];
+    const float sk = sample_position(ws, hit, k, u, ph, pl);
+    const float om = ((float)k + u) / (float)K;
+    const bool last = valid && k == K - 1;
+    Keep<N, LO, HI> kp;
+    f32x16 o = forward_keep<N, LO, HI>(wts, lane, ph, pl, kp);
+
+    // ---- compositing adjoint of the column ----
+    const bool used = valid && k < nused;
     float cc[3], sig = 0.f, sgm = 0.f;
 #pragma unroll
     for (int r = 0; r < 3; ++r) cc[r] = sigmoidf_(o[r]);
