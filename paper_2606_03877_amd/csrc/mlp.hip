@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
   }
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
-  const int ns = __shfl(incl, 63, 64);
+  const int ns = __builtin_amdgcn_readlane(incl, 63);
   const int nblk = (ns + 31) / 32;
   const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
   const float t_stop = args.opt.t_stop;
@@ -186,14 +186,17 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
   for (int b = 0; b < nblk; ++b) {
     const int x = 32 * b + col;
     const bool valid = x < ns;
-    int slot = 0;
-    for (int l = 1; l < c; ++l)
-      if (__shfl(my_off, l, 64) <= x) slot = l;
-    // cross-lane reads run on every lane: a lane that is switched off by a
-    // branch does not serve its value to the others
-    const int hit = __shfl(my_hit, slot, 64);
-    const int K = __shfl(my_k, slot, 64);
-    const int hoff = __shfl(my_off, slot, 64);
+    // the hit of this column: the last of the wave's hits whose samples
+    // start at or before it (hit records read from lanes into scalar registers)
+    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
+    for (int l = 1; l < c; ++l) {
+      const int ol = __builtin_amdgcn_readlane(my_off, l);
+      if (ol <= x) {
+        hit = __builtin_amdgcn_readlane(my_hit, l);
+        K = __builtin_amdgcn_readlane(my_k, l);
+        hoff = ol;
+      }
+    }
     const int k = valid ? x - hoff : 0;
     // sample position in the primitive's frame: p = p_c + (t_k - t_c) e
     const int ray = ws.hit_ray[hit];
@@ -205,12 +208,12 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
     f32x16 o = forward_block<N>(wts, lane, ph, pl);
     // density of the column (held by half 0), shared with half 1
     float tau0 = valid ? softplusf_(o[3]) * dlt : 0.f;
-    const float tau = __shfl(tau0, col, 64);
+    const float tau = from_lower_half(tau0);
     const bool head = (k == 0);
     SegScan sc(head, col);
     float tincl = sc.incl(tau);
     if (!sc.seen_head) tincl += cr_tau;
-    float texcl = __shfl_up(tincl, 1, 32);
+    float texcl = col_below(tincl, col);
     if (head) texcl = 0.f;
     else if (col == 0) texcl = cr_tau;
     bool used = valid;
@@ -288,13 +291,15 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
       }
     }
     // carry column 31 into the next block
-    cr_tau = __shfl(tincl, 31, 32);
-    cr_tu = __shfl(tu, 31, 32);
-    cr_cnt = __shfl(cnt, 31, 32);
+    // (the optical depths are the same in both halves; colour and feature
+    // sums are per half)
+    cr_tau = col31_same(tincl);
+    cr_tu = col31_same(tu);
+    cr_cnt = col31_same(cnt);
 #pragma unroll
-    for (int r = 0; r < 3; ++r) cr_c[r] = __shfl(cs[r], 31, 32);
+    for (int r = 0; r < 3; ++r) cr_c[r] = col31(cs[r], g);
 #pragma unroll
-    for (int r = 0; r < N::OUT_SLOTS; ++r) cr_q[r] = __shfl(qs[r], 31, 32);
+    for (int r = 0; r < N::OUT_SLOTS; ++r) cr_q[r] = col31(qs[r], g);
   }
 }
 

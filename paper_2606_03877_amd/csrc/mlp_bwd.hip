@@ -449,7 +449,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   }
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
-  const int ns = __shfl(incl, 63, 64);
+  const int ns = __builtin_amdgcn_readlane(incl, 63);
   const int nblk = (ns + 31) / 32;
   if (lane == 0) rounds_s[q] = nblk;
   if (threadIdx.x < 12) gsum_s[threadIdx.x] = 0.f;
@@ -468,13 +468,17 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   for (int b = 0; b < rounds; ++b) {
     const int x = 32 * b + col;
     const bool valid = x < ns;
-    int slot = 0;
-    for (int l = 1; l < c; ++l)
-      if (__shfl(my_off, l, 64) <= x) slot = l;
-    // cross-lane reads run on every lane (an inactive source lane serves garbage)
-    const int hit = __shfl(my_hit, slot, 64);
-    const int K = __shfl(my_k, slot, 64);
-    const int hoff = __shfl(my_off, slot, 64);
+    // the hit of this column: the last of the wave's hits whose samples
+    // start at or before it (hit records read from lanes into scalar registers)
+    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
+    for (int l = 1; l < c; ++l) {
+      const int ol = __builtin_amdgcn_readlane(my_off, l);
+      if (ol <= x) {
+        hit = __builtin_amdgcn_readlane(my_hit, l);
+        K = __builtin_amdgcn_readlane(my_k, l);
+        hoff = ol;
+      }
+    }
     const int k = valid ? x - hoff : 0;
     const int ray = ws.hit_ray[hit];
     float u = 0.5f;
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
       sgm = sigmoidf_(o[3]);
     }
     float tau0 = valid ? sig * dlt : 0.f;
-    const float tau = __shfl(tau0, col, 64);
+    const float tau = from_lower_half(tau0);
     // g . (colour, features) of the sample: half 0 holds RGB, both halves features
     float gcf = g == 0 ? gr[0] * cc[0] + gr[1] * cc[1] + gr[2] * cc[2] : 0.f;
     float gfv[N::OUT_SLOTS];
@@ -523,12 +527,12 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
         }
       }
     }
-    const float gc = gcf + __shfl_xor(gcf, 32, 64);
+    const float gc = gcf + other_half(gcf, g);
     const bool head = (k == 0);
     SegScan sc(head, col);
     float tincl = sc.incl(tau);
     if (!sc.seen_head) tincl += cr_tau;
-    float texcl = __shfl_up(tincl, 1, 32);
+    float texcl = col_below(tincl, col);
     if (head) texcl = 0.f;
     else if (col == 0) texcl = cr_tau;
     const float alpha = -expm1f(-tau);
@@ -552,10 +556,11 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
         if (f >= 0 && f < N::CF) dz[0][r] = w * gfv[r];
       }
     // half 0 holds dtau * sigma (for dL/dDelta); both halves take it
-    const float dts = __shfl(dtau * sig, col, 64);
+    const float dts = from_lower_half(dtau * sig);
     // carries of the compositing scans into the next block
-    cr_tau = __shfl(tincl, 31, 32);
-    cr_P = __shfl(P, 31, 32);
+    // (both halves hold the same scans)
+    cr_tau = col31_same(tincl);
+    cr_P = col31_same(P);
 
     // ---- network adjoint and weight gradients ----
     float dp[3] = {0.f, 0.f, 0.f};
@@ -564,7 +569,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
 
     // ---- dL/dp of the sample: the two lane halves hold disjoint encoding slots ----
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dp[a] += __shfl_xor(dp[a], 32, 64);
+    for (int a = 0; a < 3; ++a) dp[a] += other_half(dp[a], g);
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
 
     // ---- per-hit geometry sums ----
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     }
     // carries of the geometry scans
 #pragma unroll
-    for (int i = 0; i < 9; ++i) cr_geo[i] = __shfl(gv[i], 31, 32);
+    for (int i = 0; i < 9; ++i) cr_geo[i] = col31_same(gv[i]);
   }
 
   // ---- flush the weight-gradient strips ----

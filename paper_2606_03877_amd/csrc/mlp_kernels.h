@@ -200,35 +200,99 @@ __device__ __forceinline__ void enc_to_B(const float (&ev)[N::ENC_KS * N::KSTEP]
   }
 }
 
+// ------------------------------------------------------ cross-lane moves --
+//
+// A block's 32 columns sit in lanes 0-31 and again in lanes 32-63 (the two
+// lane halves hold different rows of the same samples).  The moves below run
+// on the vector ALU (DPP row shifts and broadcasts, the 32-lane half swap and
+// lane reads into scalar registers) instead of the LDS permute path, whose
+// latency a single wave per SIMD cannot hide.
+
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL, ROWS>(__float_as_int(v)));
+}
+// value of the lane D below within the 16-lane row (0 where that leaves the row)
+template <int D>
+__device__ __forceinline__ float row_shr(float v) { return dpp_f<0x110 + D>(v); }
+template <int D>
+__device__ __forceinline__ int row_shr_i(int v) { return dpp_i<0x110 + D>(v); }
+// lanes of rows 1 and 3 (columns 16-31 of each half) receive lane 15 of the
+// row below; rows 0 and 2 receive 0
+__device__ __forceinline__ float row_bcast15(float v) { return dpp_f<0x142, 0xA>(v); }
+__device__ __forceinline__ int row_bcast15_i(int v) { return dpp_i<0x142, 0xA>(v); }
+
+// both halves receive the lower half's value of the same column
+__device__ __forceinline__ float from_lower_half(float v) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]);
+}
+// each half receives the other half's value of the same column
+__device__ __forceinline__ float other_half(float v, int g) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(g ? r[0] : r[1]);
+}
+// column 31 of the lane's own half
+__device__ __forceinline__ float col31(float v, int g) {
+  float lo = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 31));
+  float hi = __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 63));
+  return g ? hi : lo;
+}
+// column 31 where both halves hold the same values
+__device__ __forceinline__ float col31_same(float v) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), 31));
+}
+
 // ------------------------------------------------------ segmented scans --
 
-// step masks of a segmented inclusive scan over the 32 columns of a lane half
+// segmented inclusive scan over the 32 columns of a lane half: four shift
+// steps inside each 16-lane row, then the rows of columns 16-31 add the
+// running sum of column 15 where no segment head lies between
 struct SegScan {
-  uint32_t mask;   // bit i: add the value from column - 2^i at step i
+  uint32_t mask;   // bit i < 4: add the column 2^i below at step i; bit 4: add column 15
   bool seen_head;  // a segment head lies at or before this column
   __device__ __forceinline__ SegScan(bool head, int col) {
-    bool f = head;
+    int f = head;
     mask = 0;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      int d = 1 << i;
-      int fp = __shfl_up((int)f, d, 32);
-      if (col >= d) {
-        if (!f) mask |= 1u << i;
-        f = f || fp;
-      }
-    }
-    seen_head = f;
+    const int c16 = col & 15;
+    int fp;
+    fp = row_shr_i<1>(f);
+    if (c16 >= 1) { if (!f) mask |= 1u; f |= fp; }
+    fp = row_shr_i<2>(f);
+    if (c16 >= 2) { if (!f) mask |= 2u; f |= fp; }
+    fp = row_shr_i<4>(f);
+    if (c16 >= 4) { if (!f) mask |= 4u; f |= fp; }
+    fp = row_shr_i<8>(f);
+    if (c16 >= 8) { if (!f) mask |= 8u; f |= fp; }
+    fp = row_bcast15_i(f);
+    if (col >= 16) { if (!f) mask |= 16u; f |= fp; }
+    seen_head = f != 0;
   }
   __device__ __forceinline__ float incl(float v) const {
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      float vp = __shfl_up(v, 1 << i, 32);
-      if (mask & (1u << i)) v += vp;
-    }
+    float vp;
+    vp = row_shr<1>(v);
+    if (mask & 1u) v += vp;
+    vp = row_shr<2>(v);
+    if (mask & 2u) v += vp;
+    vp = row_shr<4>(v);
+    if (mask & 4u) v += vp;
+    vp = row_shr<8>(v);
+    if (mask & 8u) v += vp;
+    vp = row_bcast15(v);
+    if (mask & 16u) v += vp;
     return v;
   }
 };
+
+// the column below's value within the lane half (column 0 receives 0)
+__device__ __forceinline__ float col_below(float v, int col) {
+  float a = row_shr<1>(v), b = row_bcast15(v);
+  return (col & 15) ? a : (col ? b : 0.f);
+}
 
 __device__ __forceinline__ int find_prim(const int32_t* __restrict__ wi_off, int P, int wi) {
   int lo = 0, hi = P;   // wi_off[lo] <= wi < wi_off[hi]
