@@ -64,14 +64,7 @@ template <class N, int NSLOT, int RB>
 __device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB],
                                        Act<N, rup(rup(NSLOT, N::KSTEP) / N::KSTEP, N::KGRP)>& B) {
   constexpr int KS = rup(NSLOT, N::KSTEP) / N::KSTEP;
-#pragma unroll
-  for (int s = 0; s < rup(KS, N::KGRP); ++s) {
-#pragma unroll
-    for (int e = 0; e < N::KSTEP; ++e) {
-      int t = N::KSTEP * s + e;
-      act_set<N>(B, s, e, t < NSLOT ? acc[t / 16][t % 16] : 0.f);
-    }
-  }
+  act_fill<N, rup(KS, N::KGRP)>(B, [&](int t) { return t < NSLOT ? acc[t / 16][t % 16] : 0.f; });
 }
 
 // transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j)
@@ -137,25 +130,27 @@ __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const H
 }
 
 // publish this wave's 32 columns of delta_j (D layout -> canonical rows); the
-// deltas of columns past the end of the wave's samples are zero
-template <class N, int J>
-__device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f32x16 (&dz)[N::frb(J)], int g,
-                                              int colx) {
+// deltas of columns past the end of the wave's samples are zero.  The
+// bfloat16 forms publish the operand already converted for the transposed
+// product (hi, and lo in the split form).
+template <class N, int J, int NK>
+__device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f32x16 (&dz)[N::frb(J)],
+                                              const Act<N, NK>& bd, int g, int colx) {
   using B = Bwd<N>;
 #pragma unroll
   for (int rb = 0; rb < N::frb(J); ++rb) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      int n = phi_std(g, 16 * rb + r);
+      const int t = 16 * rb + r;
+      const int n = phi_std(g, t);
       if (n >= N::fout(J)) continue;
-      float v = dz[rb][r];
       if constexpr (N::BF16) {
-        __bf16 h = (__bf16)v;
-        reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = h;
+        if (t / 8 >= NK) continue;   // (rows past the operand's slots are padding)
+        reinterpret_cast<__bf16*>(lds + B::XD_OFF)[n * B::XSP + colx] = bd.hi[t / 8][t % 8];
         if constexpr (N::SPLIT)
-          reinterpret_cast<__bf16*>(lds + B::XDL_OFF)[n * B::XSP + colx] = (__bf16)(v - (float)h);
+          reinterpret_cast<__bf16*>(lds + B::XDL_OFF)[n * B::XSP + colx] = bd.lo[t / 8][t % 8];
       } else {
-        reinterpret_cast<float*>(lds + B::XD_OFF)[n * B::XSP + colx] = v;
+        reinterpret_cast<float*>(lds + B::XD_OFF)[n * B::XSP + colx] = dz[rb][r];
       }
     }
   }
@@ -356,8 +351,14 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   const int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
   if constexpr (J == 0) encode_slots<N>(kp.ph, kp.pl, g, ev);
+  // the delta as the transposed product's B operand (also what is published)
+  Act<N, rup(N::bks(J), N::KGRP)> Bd;
+  if constexpr (DW || DOWN || J == 0) {
+    if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
+    else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
+  }
   if constexpr (DW) {
-    publish_delta<N, J>(lds, dz, g, colx);
+    publish_delta<N, J, rup(N::bks(J), N::KGRP)>(lds, dz, Bd, g, colx);
     if constexpr (J == 0) {
       Act<N, rup(N::ENC_KS, N::KGRP)> a0;
       enc_to_B<N>(ev, a0);
@@ -371,12 +372,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   }
   // transposed product for the next delta (or the input gradient), overlapping the exchange
   f32x16 da[N::brb(J)];
-  if constexpr (DOWN || J == 0) {
-    Act<N, rup(N::bks(J), N::KGRP)> Bd;
-    if constexpr (J == N::NL - 1) d_to_B<N, N::OUT_SLOTS, N::frb(J)>(dz, Bd);
-    else d_to_B<N, 16 * N::RBH, N::frb(J)>(dz, Bd);
-    layer_bwd<N, J>(wb, lane, Bd, da);
-  }
+  if constexpr (DOWN || J == 0) layer_bwd<N, J>(wb, lane, Bd, da);
   if constexpr (DW) {
     __syncthreads();
     dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(LO, J), q, lane);

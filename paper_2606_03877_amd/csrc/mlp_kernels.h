@@ -90,18 +90,6 @@ struct Hi {
   typename Operands<N>::BT hi[NK];
 };
 
-// store x into slot e of k-step entry s (hi, and the residual as lo)
-template <class N, int NK>
-__device__ __forceinline__ void act_set(Act<N, NK>& a, int s, int e, float x) {
-  if constexpr (N::BF16) {
-    __bf16 h = (__bf16)x;
-    a.hi[s][e] = h;
-    if constexpr (N::SPLIT) a.lo[s][e] = (__bf16)(x - (float)h);
-  } else {
-    a.hi[s] = x;
-  }
-}
-
 // one dense layer on the matrix cores: acc[rb] = bias + W_j x.  `wb` is the
 // primitive's packed operands, staged in LDS or (wide networks) in global memory.
 template <class N, int J, int KS>
@@ -153,18 +141,48 @@ __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int la
   }
 }
 
+// k-step s of a bfloat16 B operand from its 8 slot values, converted in pairs
+template <class N, int NK>
+__device__ __forceinline__ void act_set8(Act<N, NK>& a, int s, const float (&x)[8]) {
+  uint4 h, l;
+  split_pk(x[0], x[1], h.x, l.x);
+  split_pk(x[2], x[3], h.y, l.y);
+  split_pk(x[4], x[5], h.z, l.z);
+  split_pk(x[6], x[7], h.w, l.w);
+  a.hi[s] = as_bf16x8(h);
+  if constexpr (N::SPLIT) a.lo[s] = as_bf16x8(l);
+}
+template <class N, int NK>
+__device__ __forceinline__ void act_set8_hi(Act<N, NK>& a, int s, const float (&x)[8]) {
+  uint4 h;
+  h.x = pk_bf16(x[0], x[1]);
+  h.y = pk_bf16(x[2], x[3]);
+  h.z = pk_bf16(x[4], x[5]);
+  h.w = pk_bf16(x[6], x[7]);
+  a.hi[s] = as_bf16x8(h);
+}
+// B operand of NKS k-steps from slot values v(t) (t = KSTEP s + e)
+template <class N, int NK, class F>
+__device__ __forceinline__ void act_fill(Act<N, NK>& a, F v) {
+#pragma unroll
+  for (int s = 0; s < NK; ++s) {
+    if constexpr (N::BF16) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = v(8 * s + e);
+      if constexpr (N::SPLIT) act_set8<N, NK>(a, s, x);
+      else act_set8_hi<N, NK>(a, s, x);
+    } else {
+      a.hi[s] = v(s);
+    }
+  }
+}
+
 // ReLU and conversion of a hidden layer's D registers into the next B operand
 template <class N>
 __device__ __forceinline__ void relu_to_B(const f32x16 (&acc)[N::RBH],
                                           Act<N, rup(N::HID_KS, N::KGRP)>& B) {
-#pragma unroll
-  for (int rb = 0; rb < N::RBH; ++rb) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      int t = 16 * rb + r;
-      act_set<N>(B, t / N::KSTEP, t % N::KSTEP, fmaxf(acc[rb][r], 0.f));
-    }
-  }
+  act_fill<N, rup(N::HID_KS, N::KGRP)>(B, [&](int t) { return t < 16 * N::RBH ? fmaxf(acc[t / 16][t % 16], 0.f) : 0.f; });
 }
 
 // ReLU gates of a hidden layer's D registers as bits (slot t = 16 rb + r)
@@ -190,14 +208,7 @@ __device__ __forceinline__ void gates_of(const f32x16 (&acc)[N::RBH], Gates<N>& 
 template <class N>
 __device__ __forceinline__ void enc_to_B(const float (&ev)[N::ENC_KS * N::KSTEP],
                                          Act<N, rup(N::ENC_KS, N::KGRP)>& B) {
-#pragma unroll
-  for (int s = 0; s < rup(N::ENC_KS, N::KGRP); ++s) {
-#pragma unroll
-    for (int e = 0; e < N::KSTEP; ++e) {
-      int t = N::KSTEP * s + e;
-      act_set<N>(B, s, e, t < N::ENC_KS * N::KSTEP ? ev[t] : 0.f);
-    }
-  }
+  act_fill<N, rup(N::ENC_KS, N::KGRP)>(B, [&](int t) { return t < N::ENC_KS * N::KSTEP ? ev[t] : 0.f; });
 }
 
 // ------------------------------------------------------ cross-lane moves --
