@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsplat.so")
-SOURCES = ["api.hip", "geometry.hip", "mlp.hip", "mlp_bwd.hip", "f64.hip"]
+SOURCES = ["api.hip", "geometry.hip", "mlp.hip", "mlp_bwd.hip", "mlp_wide.hip", "mlp_bwd_wide.hip", "f64.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -24,9 +24,11 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-# The MLP kernels keep their matrix-core accumulators in ordinary VGPRs and let
-# the compiler sink instructions towards their uses: with the default AGPR form
-# the split-bfloat16 backward spilled about 450 bytes per lane to scratch.
+# The MLP kernels of networks up to 64 wide keep their matrix-core accumulators
+# in ordinary VGPRs and let the compiler sink instructions towards their uses:
+# with the default AGPR form the split-bfloat16 backward spilled about 450
+# bytes per lane to scratch.  (The wide networks' units keep the default: the
+# VGPR form crashes this compiler on some of them.)
 MLP_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-sink-insts-to-avoid-spills"]
 EXTRA_FLAGS = {"mlp.hip": MLP_FLAGS, "mlp_bwd.hip": MLP_FLAGS}
 

@@ -325,6 +325,7 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
   return hipGetLastError();
 }
 
+#ifndef MSPLAT_WIDE_TU
 bool mlp_supported(const NetShape& n) {
 #define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return true;
   MSPLAT_NETS(X)
@@ -339,18 +340,38 @@ int64_t mlp_wpack_bytes(const NetShape& n) {
   return 0;
 }
 
+hipError_t launch_pack_weights_wide(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s);
+hipError_t launch_mlp_forward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
+                                   int mode, float* rgb, float* trans, float* feat, hipStream_t s);
+hipError_t launch_pack_weights_narrow(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s);
+hipError_t launch_mlp_forward_narrow(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
+                                     int mode, float* rgb, float* trans, float* feat, hipStream_t s);
+
 hipError_t launch_pack_weights(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s) {
-#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return pack_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, mlp, n.P, s);
-  MSPLAT_NETS(X)
-#undef X
-  return hipErrorInvalidValue;
+  return wide_net(n.W) ? launch_pack_weights_wide(n, ws, mlp, s) : launch_pack_weights_narrow(n, ws, mlp, s);
 }
 
 hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
                               int mode, float* rgb, float* trans, float* feat, hipStream_t s) {
+  return wide_net(n.W) ? launch_mlp_forward_wide(n, ws, o, items, mode, rgb, trans, feat, s)
+                       : launch_mlp_forward_narrow(n, ws, o, items, mode, rgb, trans, feat, s);
+}
+#endif
+
+hipError_t MSPLAT_TU_FN(launch_pack_weights)(const NetShape& n, const Workspace& ws, const float* mlp,
+                                             hipStream_t s) {
+#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return pack_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, mlp, n.P, s);
+  MSPLAT_TU_NETS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t MSPLAT_TU_FN(launch_mlp_forward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
+                                            int items, int mode, float* rgb, float* trans, float* feat,
+                                            hipStream_t s) {
 #define X(L_, W_, D_, O_, P_) \
   MSPLAT_MATCH(L_, W_, D_, O_, P_) return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, mode, n.P, rgb, trans, feat, s);
-  MSPLAT_NETS(X)
+  MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;
 }

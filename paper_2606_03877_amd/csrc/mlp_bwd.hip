@@ -67,7 +67,8 @@ __device__ __forceinline__ void d_to_B(const f32x16 (&acc)[RB],
   act_fill<N, rup(KS, N::KGRP)>(B, [&](int t) { return t < NSLOT ? acc[t / 16][t % 16] : 0.f; });
 }
 
-// transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j)
+// transposed layer: out[rb] = W_j^T delta (rows = input slots of layer j),
+// with the next row block's operands requested ahead as in layer_fwd
 template <class N, int J>
 __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int lane,
                                           const Act<N, rup(N::bks(J), N::KGRP)>& B,
@@ -75,27 +76,15 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int la
   constexpr int RB = N::brb(J);
   constexpr int NG = N::groups(N::bks(J));
   const uint8_t* A = wb + N::bwdA_off(J);
+  RowOps<N, NG, false> ops[2];
+  load_row<N, NG, false>(A, N::bwdA_single(J), nullptr, 0, lane, ops[0]);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
+    if (rb + 1 < RB) load_row<N, NG, false>(A, N::bwdA_single(J), nullptr, rb + 1, lane, ops[(rb + 1) & 1]);
     f32x16 c;
 #pragma unroll
     for (int e = 0; e < 16; ++e) c[e] = 0.f;
-#pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-      const int idx = ((rb * NG + gi) * 64 + lane) * 16;
-      uint4 raw = lds16(A + idx);
-      if constexpr (N::BF16) {
-        c = mfma32(as_bf16x8(raw), B.hi[gi], c);
-        if constexpr (N::SPLIT) {
-          c = mfma32(as_bf16x8(raw), B.lo[gi], c);
-          c = mfma32(as_bf16x8(lds16(A + N::bwdA_single(J) + idx)), B.hi[gi], c);
-        }
-      } else {
-        f32x4 a4 = as_f32x4(raw);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B.hi[4 * gi + e], c);
-      }
-    }
+    row_mfma<N, NG, false>(ops[rb & 1], B, c);
     acc[rb] = c;
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -169,27 +158,38 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
     f32x4* acc = dj + i * B::CTB(J);
     if constexpr (N::BF16) {
       const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
+      const __bf16* xdl = reinterpret_cast<const __bf16*>(lds + B::XDL_OFF);
       const __bf16* xh = reinterpret_cast<const __bf16*>(lds + B::XH_OFF);
       bf16x8 ones;
 #pragma unroll
       for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
+      // operands of one 32-sample k-step: delta strip (hi, lo) and input tiles;
+      // the next k-step's are requested before this one's products
+      struct KOps {
+        bf16x8 a, al, b[B::CT(J)];
+      };
+      auto load = [&](int kk, KOps& o) {
+        const int so = 32 * kk + 8 * kg;
+        o.a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
+        if constexpr (N::SPLIT) o.al = *reinterpret_cast<const bf16x8*>(xdl + (16 * rt + r16) * B::XSP + so);
+#pragma unroll
+        for (int ct = 0; ct < B::CT(J); ++ct)
+          o.b[ct] = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
+      };
+      KOps ko[2];
+      load(0, ko[0]);
 #pragma unroll
       for (int kk = 0; kk < B::XS / 32; ++kk) {
-        int so = 32 * kk + 8 * kg;
-        bf16x8 a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
-        bf16x8 al;
-        if constexpr (N::SPLIT)
-          al = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const __bf16*>(lds + B::XDL_OFF) +
-                                                 (16 * rt + r16) * B::XSP + so);
+        if (kk + 1 < B::XS / 32) load(kk + 1, ko[(kk + 1) & 1]);
+        const KOps& o = ko[kk & 1];
 #pragma unroll
         for (int ct = 0; ct < B::CT(J); ++ct) {
-          bf16x8 b = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
-          acc[ct] = mfma16(a, b, acc[ct]);
-          if constexpr (N::SPLIT) acc[ct] = mfma16(al, b, acc[ct]);
+          acc[ct] = mfma16(o.a, o.b[ct], acc[ct]);
+          if constexpr (N::SPLIT) acc[ct] = mfma16(o.al, o.b[ct], acc[ct]);
         }
         if constexpr (J > 0) {
-          acc[B::CT(J)] = mfma16(a, ones, acc[B::CT(J)]);
-          if constexpr (N::SPLIT) acc[B::CT(J)] = mfma16(al, ones, acc[B::CT(J)]);
+          acc[B::CT(J)] = mfma16(o.a, ones, acc[B::CT(J)]);
+          if constexpr (N::SPLIT) acc[B::CT(J)] = mfma16(o.al, ones, acc[B::CT(J)]);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -674,16 +674,29 @@ static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items,
   }
 }
 
-hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                                    const float* ray_d, const float* grad_rgb, const float* grad_feat,
-                                    float* g_mlp, hipStream_t s) {
+hipError_t MSPLAT_TU_FN(launch_mlp_backward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
+                                             int items, const float* ray_d, const float* grad_rgb,
+                                             const float* grad_feat, float* g_mlp, hipStream_t s) {
 #define X(L_, W_, D_, O_, P_)                                                                   \
   MSPLAT_MATCH(L_, W_, D_, O_, P_)                                                              \
   return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, \
                                                   grad_feat, g_mlp, s);
-  MSPLAT_NETS(X)
+  MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;
 }
+
+#ifndef MSPLAT_WIDE_TU
+hipError_t launch_mlp_backward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
+                                    const float* ray_d, const float* grad_rgb, const float* grad_feat,
+                                    float* g_mlp, hipStream_t s);
+
+hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
+                               const float* ray_d, const float* grad_rgb, const float* grad_feat,
+                               float* g_mlp, hipStream_t s) {
+  return wide_net(n.W) ? launch_mlp_backward_wide(n, ws, o, items, ray_d, grad_rgb, grad_feat, g_mlp, s)
+                       : launch_mlp_backward_narrow(n, ws, o, items, ray_d, grad_rgb, grad_feat, g_mlp, s);
+}
+#endif
 
 }  // namespace msplat

@@ -42,6 +42,8 @@ __host__ __device__ constexpr int phi_enc(int L, int g, int t) {
 }
 
 __host__ __device__ constexpr int rup(int a, int b) { return (a + b - 1) / b * b; }
+// networks wider than this read their weights from global memory (see Net::WIDE)
+__host__ __device__ constexpr bool wide_net(int W) { return W > 64; }
 
 // SPLIT_: bfloat16 operands carried as a sum of two bfloat16 values (hi, lo);
 // a product of two such operands is taken as hi*hi + hi*lo + lo*hi on the
@@ -70,7 +72,7 @@ struct Net {
   // wide networks read their weight operands from global memory (they stay
   // in L2 while a primitive's work items run) instead of staging them in LDS,
   // and split the backward into one pass per layer's weight gradient
-  static constexpr bool WIDE = W > 64;
+  static constexpr bool WIDE = wide_net(W);
   // backward split into two passes over halves of the layers (fewer live
   // weight-gradient accumulators, the network recomputed twice); measured
   // slower than one spilling pass for the 64-wide split form, so off
@@ -132,11 +134,24 @@ __device__ __forceinline__ float net_weight(const float* th, int j, int n, int f
 }
 
 // Compiled networks: (pe_freqs, hidden width, hidden layers, outputs, precision).
-#define MSPLAT_NETS(X)                                                                 \
+// Networks up to 64 wide and wider ones are compiled in separate units (the
+// wide kernels with the compiler's default register assignment).
+#define MSPLAT_NETS_NARROW(X)                                                          \
   X(4, 32, 2, 4, MSPLAT_FP32) X(4, 32, 2, 4, MSPLAT_BF16) X(4, 32, 2, 4, MSPLAT_BF16X3)    \
   X(6, 64, 3, 4, MSPLAT_FP32) X(6, 64, 3, 4, MSPLAT_BF16) X(6, 64, 3, 4, MSPLAT_BF16X3)    \
-  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3) \
+  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3)
+#define MSPLAT_NETS_WIDE(X) \
   X(6, 128, 4, 20, MSPLAT_FP32) X(6, 128, 4, 20, MSPLAT_BF16) X(6, 128, 4, 20, MSPLAT_BF16X3)
+#define MSPLAT_NETS(X) MSPLAT_NETS_NARROW(X) MSPLAT_NETS_WIDE(X)
+
+// the networks of this translation unit, and the suffix of its launchers
+#ifdef MSPLAT_WIDE_TU
+#define MSPLAT_TU_NETS MSPLAT_NETS_WIDE
+#define MSPLAT_TU_FN(name) name##_wide
+#else
+#define MSPLAT_TU_NETS MSPLAT_NETS_NARROW
+#define MSPLAT_TU_FN(name) name##_narrow
+#endif
 #define MSPLAT_NET(L_, W_, D_, O_, P_) Net<L_, W_, D_, O_, (P_) != MSPLAT_FP32, (P_) == MSPLAT_BF16X3>
 #define MSPLAT_MATCH(L_, W_, D_, O_, P_) \
   if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && n.prec == (P_))

@@ -90,53 +90,85 @@ struct Hi {
   typename Operands<N>::BT hi[NK];
 };
 
+// LDS (or global) operands of one row block of a layer: the A groups (hi,
+// and lo in the split form) and, for the forward of a hidden or output
+// layer, the lane's 16 biases
+template <class N, int NG, bool BIAS>
+struct RowOps {
+  uint4 a[NG];
+  uint4 al[N::SPLIT ? NG : 1];
+  uint4 b[BIAS ? 4 : 1];
+};
+
+template <class N, int NG, bool BIAS>
+__device__ __forceinline__ void load_row(const uint8_t* __restrict__ A, int single, const uint8_t* __restrict__ bp,
+                                         int rb, int lane, RowOps<N, NG, BIAS>& o) {
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    const int idx = ((rb * NG + gi) * 64 + lane) * 16;
+    o.a[gi] = lds16(A + idx);
+    if constexpr (N::SPLIT) o.al[gi] = lds16(A + single + idx);
+  }
+  if constexpr (BIAS) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o.b[i] = lds16(bp + 16 * i);
+  }
+}
+
+// c += A_rb x over the row block's groups (three products per pair in the split form)
+template <class N, int NG, bool BIAS, int NK>
+__device__ __forceinline__ void row_mfma(const RowOps<N, NG, BIAS>& o, const Act<N, NK>& B, f32x16& c) {
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    if constexpr (N::BF16) {
+      c = mfma32(as_bf16x8(o.a[gi]), B.hi[gi], c);
+      if constexpr (N::SPLIT) {
+        c = mfma32(as_bf16x8(o.a[gi]), B.lo[gi], c);
+        c = mfma32(as_bf16x8(o.al[gi]), B.hi[gi], c);
+      }
+    } else {
+      f32x4 a4 = as_f32x4(o.a[gi]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B.hi[4 * gi + e], c);
+    }
+  }
+}
+
 // one dense layer on the matrix cores: acc[rb] = bias + W_j x.  `wb` is the
-// primitive's packed operands, staged in LDS or (wide networks) in global memory.
+// primitive's packed operands, staged in LDS or (wide networks) in global
+// memory.  The operands of row block rb+1 are requested before the products
+// of row block rb, so their latency overlaps the matrix cores' work; at most
+// two row blocks' operands are in flight (bounds register pressure).
 template <class N, int J, int KS>
 __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
                                           const Act<N, rup(KS, N::KGRP)>& B,
                                           f32x16 (&acc)[N::frb(J)]) {
   constexpr int RB = N::frb(J);
   constexpr int NG = N::groups(KS);
+  constexpr bool BIAS = J > 0;
   const uint8_t* A = wb + N::fwdA_off(J);
-  int g = lane / 32;
+  const int g = lane / 32;
+  const uint8_t* bp = wb + N::bias_off(J) + (g * 16) * 4;   // + rb * 128
+  RowOps<N, NG, BIAS> ops[2];
+  load_row<N, NG, BIAS>(A, N::fwdA_single(J), bp, 0, lane, ops[0]);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
+    if (rb + 1 < RB) load_row<N, NG, BIAS>(A, N::fwdA_single(J), bp + (rb + 1) * 128, rb + 1, lane, ops[(rb + 1) & 1]);
+    const RowOps<N, NG, BIAS>& o = ops[rb & 1];
     f32x16 c;
-    if constexpr (J > 0) {
-      const uint8_t* bp = wb + N::bias_off(J) + ((rb * 2 + g) * 16) * 4;
-      f32x4 b0 = as_f32x4(lds16(bp)), b1 = as_f32x4(lds16(bp + 16)), b2 = as_f32x4(lds16(bp + 32)),
-            b3 = as_f32x4(lds16(bp + 48));
+    if constexpr (BIAS) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        c[e] = b0[e];
-        c[4 + e] = b1[e];
-        c[8 + e] = b2[e];
-        c[12 + e] = b3[e];
+      for (int i = 0; i < 4; ++i) {
+        f32x4 b = as_f32x4(o.b[i]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c[4 * i + e] = b[e];
       }
     } else {
 #pragma unroll
       for (int e = 0; e < 16; ++e) c[e] = 0.f;
     }
-#pragma unroll
-    for (int gi = 0; gi < NG; ++gi) {
-      const int idx = ((rb * NG + gi) * 64 + lane) * 16;
-      uint4 raw = lds16(A + idx);
-      if constexpr (N::BF16) {
-        c = mfma32(as_bf16x8(raw), B.hi[gi], c);
-        if constexpr (N::SPLIT) {
-          bf16x8 alo = as_bf16x8(lds16(A + N::fwdA_single(J) + idx));
-          c = mfma32(as_bf16x8(raw), B.lo[gi], c);
-          c = mfma32(alo, B.hi[gi], c);
-        }
-      } else {
-        f32x4 a4 = as_f32x4(raw);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) c = mfma32(a4[e], B.hi[4 * gi + e], c);
-      }
-    }
+    row_mfma<N, NG, BIAS>(o, B, c);
     acc[rb] = c;
-    // one row block's operands in flight at a time (bounds register pressure)
     __builtin_amdgcn_sched_barrier(0);
   }
 }
