@@ -37,11 +37,16 @@ struct Bwd {
   static constexpr int HROWS = mx(rup(N::IN + 1, 16), rup(N::W, 16));
   static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
   // exchange planes: layer inputs (the split form contracts the weight
-  // gradient with their hi part only), deltas (hi), and the deltas' lo parts
-  static constexpr int XH_OFF = N::WIDE ? 0 : N::total_bytes();
+  // gradient with their hi part only), deltas (hi), and the deltas' lo parts.
+  // They sit at the bottom of LDS, where every access of theirs is a base
+  // register plus an immediate offset; the staged weights follow.
+  static constexpr int XH_OFF = 0;
   static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
   static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
-  static constexpr int LDS = XDL_OFF + (N::SPLIT ? DROWS * XSP * ESZ : 0);
+  static constexpr int PLANES = XDL_OFF + (N::SPLIT ? DROWS * XSP * ESZ : 0);
+  static_assert(N::WIDE || PLANES <= 65536, "exchange planes addressed by immediate offsets");
+  static constexpr int W_OFF = rup(PLANES, 256);
+  static constexpr int LDS = N::WIDE ? PLANES : W_OFF + N::total_bytes();
   static_assert(LDS <= 160 * 1024, "LDS budget of one workgroup");
   // weight-gradient tiles (16 x 16) of layer j
   static constexpr int inp(int j) { return j == 0 ? N::IN + 1 : N::W; }
@@ -290,7 +295,15 @@ __device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_hi(const 
 // ReLU gate of slot t of layer J's input (its pre-activation was positive)
 template <class N, int LO, int HI, int J>
 __device__ __forceinline__ bool gate(const Keep<N, LO, HI>& kp, int t) {
-  if constexpr (J <= HI) return bval<N>(input_hi<N, LO, HI, J>(kp).hi[t / N::KSTEP], t % N::KSTEP) > 0.f;
+  if constexpr (J <= HI) {
+    if constexpr (N::BF16) {
+      // the kept input is relu(z) >= +0 rounded to bfloat16: open iff its bits are non-zero
+      const uint32_t w = __builtin_bit_cast(uint4, input_hi<N, LO, HI, J>(kp).hi[t / 8])[(t % 8) / 2];
+      return (t % 2) ? w > 0xffffu : (uint16_t)w != 0;
+    } else {
+      return input_hi<N, LO, HI, J>(kp).hi[t] > 0.f;
+    }
+  }
   else return (kp.gt[J - HI - 1].w[t / 32] >> (t % 32)) & 1u;
 }
 
@@ -432,9 +445,9 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   const uint8_t* wts = ws.wpack + (int64_t)p * ws.wpack_bytes;
   if constexpr (!N::WIDE) {
     const uint4* src = reinterpret_cast<const uint4*>(wts);
-    uint4* dst = reinterpret_cast<uint4*>(lds);
+    uint4* dst = reinterpret_cast<uint4*>(lds + B::W_OFF);
     for (int i = threadIdx.x; i < N::total_bytes() / 16; i += blockDim.x) dst[i] = src[i];
-    wts = lds;   // read after the barrier below
+    wts = lds + B::W_OFF;   // read after the barrier below
   }
   const int h0 = (nh * q) / B::NW, h1 = (nh * (q + 1)) / B::NW;
   const int c = h1 - h0;

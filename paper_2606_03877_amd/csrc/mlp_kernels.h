@@ -210,11 +210,16 @@ __device__ __forceinline__ void act_fill(Act<N, NK>& a, F v) {
   }
 }
 
+// max(x, 0) as an integer maximum of the bit pattern (negative floats, -0
+// included, are negative integers): one instruction, where a float maximum
+// also canonicalises its operand
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 // ReLU and conversion of a hidden layer's D registers into the next B operand
 template <class N>
 __device__ __forceinline__ void relu_to_B(const f32x16 (&acc)[N::RBH],
                                           Act<N, rup(N::HID_KS, N::KGRP)>& B) {
-  act_fill<N, rup(N::HID_KS, N::KGRP)>(B, [&](int t) { return t < 16 * N::RBH ? fmaxf(acc[t / 16][t % 16], 0.f) : 0.f; });
+  act_fill<N, rup(N::HID_KS, N::KGRP)>(B, [&](int t) { return t < 16 * N::RBH ? relu(acc[t / 16][t % 16]) : 0.f; });
 }
 
 // ReLU gates of a hidden layer's D registers as bits (slot t = 16 rb + r)
