@@ -27,40 +27,64 @@ namespace {
 
 template <class N>
 struct Bwd {
-  // waves per workgroup: the float32 exchange planes are twice as wide, so
-  // the float32 form exchanges 64 samples per round, the bfloat16 forms 128
-  static constexpr int NW = N::BF16 ? 4 : 2;
-  static constexpr int XS = 32 * NW;                // samples per exchange round
-  static constexpr int ESZ = N::BF16 ? 2 : 4;       // exchange element bytes
-  static constexpr int XSP = XS + (N::BF16 ? 8 : 4);  // padded row (elements)
   static constexpr int mx(int a, int b) { return a > b ? a : b; }
+  static constexpr int ESZ = N::BF16 ? 2 : 4;       // exchange element bytes
   static constexpr int HROWS = mx(rup(N::IN + 1, 16), rup(N::W, 16));
   static constexpr int DROWS = mx(rup(N::W, 16), rup(N::NOUT, 16));
-  // exchange planes: layer inputs (the split form contracts the weight
-  // gradient with their hi part only), deltas (hi), and the deltas' lo parts.
-  // They sit at the bottom of LDS, where every access of theirs is a base
-  // register plus an immediate offset; the staged weights follow.
-  static constexpr int XH_OFF = 0;
-  static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
-  static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
   // The split form contracts the weight gradient from the hi parts of both
   // operands (delta and layer input), one product per pair: a single rounding
   // of each factor, not compounded through the chain, keeps dW within about
   // 6e-4 of the FP64 result at the sizes tested; the transposed chain keeps
   // all three products.  (true: also delta_lo x_hi, with its own LDS plane.)
   static constexpr bool DWS = false;
-  static constexpr int PLANES = XDL_OFF + (DWS ? DROWS * XSP * ESZ : 0);
-  static_assert(N::WIDE || PLANES <= 65536, "exchange planes addressed by immediate offsets");
+  // exchange planes of nw waves (32 samples each; rows padded by 16 bytes,
+  // which keeps the 16-row operand reads free of bank conflicts): layer
+  // inputs (the split form contracts the weight gradient with their hi part
+  // only), deltas (hi), and the deltas' lo parts
+  static constexpr int xsp(int nw) { return 32 * nw + (N::BF16 ? 8 : 4); }
+  static constexpr int planes(int nw) { return (HROWS + DROWS * (DWS ? 2 : 1)) * xsp(nw) * ESZ; }
+  // Weights staged in LDS beside the planes.  Where they do not all fit, the
+  // first layer's forward operands (requested ahead of the encoding, which
+  // covers their latency) are read from global memory instead, L2-resident
+  // while a primitive's work items run; wide networks read all of them there.
+  static constexpr int LDS_MAX = 160 * 1024 - 256;   // (less the static arrays)
+  static constexpr int staged(int nw, int skip) { return rup(planes(nw), 256) + N::total_bytes() - skip; }
+  // Waves per workgroup.  The bfloat16 forms of networks up to 64 wide run
+  // eight where their weights fit beside eight waves' planes (two waves per
+  // SIMD sharing one LDS copy of the weights, so that one wave's LDS and
+  // barrier waits overlap the other's work); otherwise four; the float32
+  // form (whose exchange planes are twice as wide) two.
+  static constexpr bool FIT8 = N::BF16 && !N::WIDE && staged(8, N::fwdA_bytes(0)) <= LDS_MAX;
+  static constexpr int NW = N::BF16 ? (FIT8 ? 8 : 4) : 2;
+  static constexpr int XS = 32 * NW;                // samples per exchange round
+  static constexpr int XSP = xsp(NW);               // padded row (elements)
+  // plane offsets: at the bottom of LDS, where (up to 64 KiB) an access is a
+  // base register plus an immediate offset; the staged weights follow
+  static constexpr int XH_OFF = 0;
+  static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
+  static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
+  static constexpr int PLANES = planes(NW);
   static constexpr int W_OFF = rup(PLANES, 256);
-  static constexpr int LDS = N::WIDE ? PLANES : W_OFF + N::total_bytes();
+  static constexpr bool G0 = !N::WIDE && staged(NW, 0) > LDS_MAX;
+  static constexpr int SKIP = G0 ? N::fwdA_bytes(0) : 0;   // = fwdA_off(1): staged from here
+  static constexpr bool GW = N::WIDE || staged(NW, SKIP) > LDS_MAX;
+  static constexpr int LDS = GW ? PLANES : staged(NW, SKIP);
   static_assert(LDS <= 160 * 1024, "LDS budget of one workgroup");
   // weight-gradient tiles (16 x 16) of layer j
   static constexpr int inp(int j) { return j == 0 ? N::IN + 1 : N::W; }
   static constexpr int RT(int j) { return (N::fout(j) + 15) / 16; }
   static constexpr int CT(int j) { return (inp(j) + 15) / 16; }
   static constexpr int CTB(int j) { return CT(j) + (j > 0 ? 1 : 0); }
-  static constexpr int OWN(int j) { return (RT(j) + NW - 1) / NW; }
-  static constexpr int TOFF(int j) { return j == 0 ? 0 : TOFF(j - 1) + OWN(j - 1) * CTB(j - 1); }
+  // ownership: the tiles of layer j are cut into units of one row tile and
+  // CPG(j) consecutive column tiles (CG(j) units per row tile, enough for
+  // every wave to own one where the layer has fewer row tiles than waves);
+  // wave q owns units q, q + NW, ...
+  static constexpr int mn(int a, int b) { return a < b ? a : b; }
+  static constexpr int CG(int j) { return mn(CTB(j), (NW + RT(j) - 1) / RT(j)); }
+  static constexpr int CPG(int j) { return (CTB(j) + CG(j) - 1) / CG(j); }
+  static constexpr int UNITS(int j) { return RT(j) * CG(j); }
+  static constexpr int OWN(int j) { return (UNITS(j) + NW - 1) / NW; }
+  static constexpr int TOFF(int j) { return j == 0 ? 0 : TOFF(j - 1) + OWN(j - 1) * CPG(j - 1); }
   static constexpr int TT = TOFF(N::NL);
   // a pass accumulates the weight gradients of layers LO..HI
   static constexpr int tiles(int lo, int hi) { return TOFF(hi + 1) - TOFF(lo); }
@@ -156,7 +180,8 @@ __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f
   }
 }
 
-// accumulate this wave's row strips of dW_J (and db_J) over the round
+// accumulate this wave's units of dW_J (and db_J) over the round: unit u =
+// q + i NW is row tile u % RT and column tiles [CPG (u / RT), +CPG)
 template <class N, int J>
 __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4* __restrict__ dj, int q,
                                          int lane) {
@@ -164,9 +189,10 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
   const int r16 = lane % 16, kg = lane / 16;
 #pragma unroll
   for (int i = 0; i < B::OWN(J); ++i) {
-    int rt = q + i * B::NW;
-    if (rt >= B::RT(J)) continue;
-    f32x4* acc = dj + i * B::CTB(J);
+    const int u = q + i * B::NW;
+    if (u >= B::UNITS(J)) continue;
+    const int rt = u % B::RT(J), c0 = (u / B::RT(J)) * B::CPG(J);
+    f32x4* acc = dj + i * B::CPG(J);
     if constexpr (N::BF16) {
       const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
       const __bf16* xdl = reinterpret_cast<const __bf16*>(lds + B::XDL_OFF);
@@ -174,18 +200,22 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
       bf16x8 ones;
 #pragma unroll
       for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
-      // operands of one 32-sample k-step: delta strip (hi, lo) and input tiles;
-      // the next k-step's are requested before this one's products
+      // operands of one 32-sample k-step: delta row strip (hi, lo) and the
+      // unit's input tiles (the bias tile contracts with ones); the next
+      // k-step's are requested before this one's products
       struct KOps {
-        bf16x8 a, al, b[B::CT(J)];
+        bf16x8 a, al, b[B::CPG(J)];
       };
       auto load = [&](int kk, KOps& o) {
         const int so = 32 * kk + 8 * kg;
         o.a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
         if constexpr (B::DWS) o.al = *reinterpret_cast<const bf16x8*>(xdl + (16 * rt + r16) * B::XSP + so);
 #pragma unroll
-        for (int ct = 0; ct < B::CT(J); ++ct)
-          o.b[ct] = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
+        for (int c = 0; c < B::CPG(J); ++c) {
+          const int ct = c0 + c;
+          if (ct < B::CT(J)) o.b[c] = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
+          else o.b[c] = ones;
+        }
       };
       KOps ko[2];
       load(0, ko[0]);
@@ -194,13 +224,10 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
         if (kk + 1 < B::XS / 32) load(kk + 1, ko[(kk + 1) & 1]);
         const KOps& o = ko[kk & 1];
 #pragma unroll
-        for (int ct = 0; ct < B::CT(J); ++ct) {
-          acc[ct] = mfma16(o.a, o.b[ct], acc[ct]);
-          if constexpr (B::DWS) acc[ct] = mfma16(o.al, o.b[ct], acc[ct]);
-        }
-        if constexpr (J > 0) {
-          acc[B::CT(J)] = mfma16(o.a, ones, acc[B::CT(J)]);
-          if constexpr (B::DWS) acc[B::CT(J)] = mfma16(o.al, ones, acc[B::CT(J)]);
+        for (int c = 0; c < B::CPG(J); ++c) {
+          if (c0 + c >= B::CTB(J)) continue;
+          acc[c] = mfma16(o.a, o.b[c], acc[c]);
+          if constexpr (B::DWS) acc[c] = mfma16(o.al, o.b[c], acc[c]);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -213,21 +240,24 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
         int so = 16 * kk + 4 * kg;
         f32x4 a = *reinterpret_cast<const f32x4*>(xd + (16 * rt + r16) * B::XSP + so);
 #pragma unroll
-        for (int ct = 0; ct < B::CT(J); ++ct) {
-          f32x4 b = *reinterpret_cast<const f32x4*>(xh + (16 * ct + r16) * B::XSP + so);
+        for (int c = 0; c < B::CPG(J); ++c) {
+          const int ct = c0 + c;
+          if (ct >= B::CTB(J)) continue;
+          if (ct < B::CT(J)) {
+            f32x4 b = *reinterpret_cast<const f32x4*>(xh + (16 * ct + r16) * B::XSP + so);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[ct] = mfma16(a[e], b[e], acc[ct]);
-        }
-        if constexpr (J > 0) {
+            for (int e = 0; e < 4; ++e) acc[c] = mfma16(a[e], b[e], acc[c]);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[B::CT(J)] = mfma16(a[e], one, acc[B::CT(J)]);
+            for (int e = 0; e < 4; ++e) acc[c] = mfma16(a[e], one, acc[c]);
+          }
         }
       }
     }
   }
 }
 
-// add this wave's weight-gradient strips of layer J (tiles from dj) to the
+// add this wave's weight-gradient units of layer J (tiles from dj) to the
 // global gradient
 template <class N, int J>
 __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __restrict__ gm, int q,
@@ -239,11 +269,14 @@ __device__ __forceinline__ void flush_dw(const f32x4* __restrict__ dj, float* __
   const int r16 = lane % 16, rq = lane / 16;
 #pragma unroll
   for (int i = 0; i < B::OWN(J); ++i) {
-    int rt = q + i * B::NW;
-    if (rt >= B::RT(J)) continue;
+    const int u = q + i * B::NW;
+    if (u >= B::UNITS(J)) continue;
+    const int rt = u % B::RT(J), c0 = (u / B::RT(J)) * B::CPG(J);
 #pragma unroll
-    for (int ct = 0; ct < B::CTB(J); ++ct) {
-      f32x4 v = dj[i * B::CTB(J) + ct];
+    for (int c = 0; c < B::CPG(J); ++c) {
+      const int ct = c0 + c;
+      if (ct >= B::CTB(J)) continue;
+      f32x4 v = dj[i * B::CPG(J) + c];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int n = 16 * rt + 4 * rq + r;
@@ -335,9 +368,12 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int l
   }
 }
 
+// (wb0: where the first layer's forward operands are read, which may differ
+// from wb; they are requested before the encoding is computed)
 template <class N, int LO, int HI>
-__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, int lane, const float ph[3],
-                                               const float pl[3], Keep<N, LO, HI>& kp) {
+__device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wb0,
+                                               int lane, const float ph[3], const float pl[3],
+                                               Keep<N, LO, HI>& kp) {
   int g = lane / 32;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -346,11 +382,13 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, i
   }
   f32x16 acc[N::RBH];
   {
+    FwdOps<N, 0, N::ENC_KS> first;
+    fwd_row_load<N, 0, N::ENC_KS>(wb0, lane, 0, first);
     float ev[N::ENC_KS * N::KSTEP];
     encode_slots<N>(ph, pl, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
-    layer_fwd<N, 0, N::ENC_KS>(wb, lane, a0, acc);
+    layer_fwd_from<N, 0, N::ENC_KS>(wb0, lane, a0, acc, first);
   }
   f32x16 out;
   chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);
@@ -432,7 +470,7 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
 // is 0, the geometry gradient).  Weights are staged in LDS, or read from
 // global memory for wide networks.
 template <class N, int LO, int HI>
-__global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
+__global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs args) {
   using B = Bwd<N>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int rounds_s[B::NW];
@@ -448,13 +486,17 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
   const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * kHitsPerItem;
   const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
-  const uint8_t* wts = ws.wpack + (int64_t)p * ws.wpack_bytes;
-  if constexpr (!N::WIDE) {
-    const uint4* src = reinterpret_cast<const uint4*>(wts);
+  const uint8_t* wglb = ws.wpack + (int64_t)p * ws.wpack_bytes;
+  const uint8_t* wts = wglb;
+  if constexpr (!B::GW) {
+    // packed bytes [SKIP, total) go to LDS at W_OFF; wts is the (LDS) base
+    // that the packed offsets of the staged sections are taken from
+    const uint4* src = reinterpret_cast<const uint4*>(wglb + B::SKIP);
     uint4* dst = reinterpret_cast<uint4*>(lds + B::W_OFF);
-    for (int i = threadIdx.x; i < N::total_bytes() / 16; i += blockDim.x) dst[i] = src[i];
-    wts = lds + B::W_OFF;   // read after the barrier below
+    for (int i = threadIdx.x; i < (N::total_bytes() - B::SKIP) / 16; i += blockDim.x) dst[i] = src[i];
+    wts = lds + B::W_OFF - B::SKIP;   // read after the barrier below
   }
+  const uint8_t* wts0 = B::G0 ? wglb : wts;
   const int h0 = (nh * q) / B::NW, h1 = (nh * (q + 1)) / B::NW;
   const int c = h1 - h0;
   int my_hit = 0, my_k = 0;
@@ -515,7 +557,7 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(BwdArgs args) {
     const float om = ((float)k + u) / (float)K;
     const bool last = valid && k == K - 1;
     Keep<N, LO, HI> kp;
-    f32x16 o = forward_keep<N, LO, HI>(wts, lane, ph, pl, kp);
+    f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lane, ph, pl, kp);
 
     // ---- compositing adjoint of the column ----
     const bool used = valid && k < nused;

@@ -134,27 +134,36 @@ __device__ __forceinline__ void row_mfma(const RowOps<N, NG, BIAS>& o, const Act
   }
 }
 
-// one dense layer on the matrix cores: acc[rb] = bias + W_j x.  `wb` is the
-// primitive's packed operands, staged in LDS or (wide networks) in global
-// memory.  The operands of row block rb+1 are requested before the products
-// of row block rb, so their latency overlaps the matrix cores' work; at most
-// two row blocks' operands are in flight (bounds register pressure).
+// operands of one row block of forward layer J
 template <class N, int J, int KS>
-__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
-                                          const Act<N, rup(KS, N::KGRP)>& B,
-                                          f32x16 (&acc)[N::frb(J)]) {
+using FwdOps = RowOps<N, N::groups(KS), (J > 0)>;
+
+template <class N, int J, int KS>
+__device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, int lane, int rb,
+                                             FwdOps<N, J, KS>& o) {
+  const uint8_t* bp = wb + N::bias_off(J) + ((lane / 32) * 16) * 4 + rb * 128;
+  load_row<N, N::groups(KS), (J > 0)>(wb + N::fwdA_off(J), N::fwdA_single(J), bp, rb, lane, o);
+}
+
+// one dense layer on the matrix cores: acc[rb] = bias + W_j x, given the
+// operands of row block 0 (`first`).  `wb` is the primitive's packed
+// operands, staged in LDS or in global memory.  The operands of row block
+// rb+1 are requested before the products of row block rb, so their latency
+// overlaps the matrix cores' work; at most two row blocks' operands are in
+// flight (bounds register pressure).
+template <class N, int J, int KS>
+__device__ __forceinline__ void layer_fwd_from(const uint8_t* __restrict__ wb, int lane,
+                                               const Act<N, rup(KS, N::KGRP)>& B,
+                                               f32x16 (&acc)[N::frb(J)], const FwdOps<N, J, KS>& first) {
   constexpr int RB = N::frb(J);
   constexpr int NG = N::groups(KS);
   constexpr bool BIAS = J > 0;
-  const uint8_t* A = wb + N::fwdA_off(J);
-  const int g = lane / 32;
-  const uint8_t* bp = wb + N::bias_off(J) + (g * 16) * 4;   // + rb * 128
-  RowOps<N, NG, BIAS> ops[2];
-  load_row<N, NG, BIAS>(A, N::fwdA_single(J), bp, 0, lane, ops[0]);
+  FwdOps<N, J, KS> ops[2];
+  ops[0] = first;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    if (rb + 1 < RB) load_row<N, NG, BIAS>(A, N::fwdA_single(J), bp + (rb + 1) * 128, rb + 1, lane, ops[(rb + 1) & 1]);
-    const RowOps<N, NG, BIAS>& o = ops[rb & 1];
+    if (rb + 1 < RB) fwd_row_load<N, J, KS>(wb, lane, rb + 1, ops[(rb + 1) & 1]);
+    const FwdOps<N, J, KS>& o = ops[rb & 1];
     f32x16 c;
     if constexpr (BIAS) {
 #pragma unroll
@@ -171,6 +180,15 @@ __device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int la
     acc[rb] = c;
     __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+template <class N, int J, int KS>
+__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
+                                          const Act<N, rup(KS, N::KGRP)>& B,
+                                          f32x16 (&acc)[N::frb(J)]) {
+  FwdOps<N, J, KS> first;
+  fwd_row_load<N, J, KS>(wb, lane, 0, first);
+  layer_fwd_from<N, J, KS>(wb, lane, B, acc, first);
 }
 
 // k-step s of a bfloat16 B operand from its 8 slot values, converted in pairs
