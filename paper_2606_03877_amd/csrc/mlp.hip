@@ -134,8 +134,14 @@ struct FwdArgs {
   float* feat;
 };
 
+// waves per workgroup: eight for networks whose weights are staged in LDS
+// (one copy serves eight waves, and LDS then admits two workgroups, four
+// waves per SIMD), four for wide networks
 template <class N>
-__global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
+constexpr int fwd_waves() { return N::WIDE ? 4 : 8; }
+
+template <class N>
+__global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_waves<N>() / 2) void mlp_forward_kernel(FwdArgs args) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const Workspace& ws = args.ws;
   const int lane = threadIdx.x % 64;
@@ -163,7 +169,8 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(FwdArgs args) {
     wts = lds;
   }
   // this wave's hits
-  const int h0 = (nh * wv) / 4, h1 = (nh * (wv + 1)) / 4;
+  constexpr int NWF = fwd_waves<N>();
+  const int h0 = (nh * wv) / NWF, h1 = (nh * (wv + 1)) / NWF;
   const int c = h1 - h0;
   int my_hit = 0, my_k = 0;
   if (lane < c) {
@@ -321,7 +328,7 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
   if (items <= 0) return hipSuccess;
   FwdArgs a{ws, o, mode, P, rgb, trans, feat};
   size_t lds = N::WIDE ? 0 : N::fwd_bytes();
-  hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3(items), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3(items), dim3(64 * fwd_waves<N>()), lds, s, a);
   return hipGetLastError();
 }
 
