@@ -170,11 +170,13 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_waves<N>() / 2) void mlp_f
   }
   // this wave's hits
   constexpr int NWF = fwd_waves<N>();
-  const int h0 = (nh * wv) / NWF, h1 = (nh * (wv + 1)) / NWF;
-  const int c = h1 - h0;
+  // hits dealt round-robin over the waves (neighbouring hits of a primitive
+  // come from neighbouring rays and have similar sample counts): wave wv
+  // takes hits wv, wv + NW, ...
+  const int c = wv < nh ? (nh - wv + NWF - 1) / NWF : 0;
   int my_hit = 0, my_k = 0;
   if (lane < c) {
-    my_hit = ws.phit[first + h0 + lane];
+    my_hit = ws.phit[first + wv + lane * NWF];
     int kk = ws.hit_k[my_hit] & kKMask;
     my_k = (args.mode == 0 || ws.hit_nused[my_hit] == -1) ? kk : 0;
   }

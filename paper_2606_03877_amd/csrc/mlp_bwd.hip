@@ -497,11 +497,13 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     wts = lds + B::W_OFF - B::SKIP;   // read after the barrier below
   }
   const uint8_t* wts0 = B::G0 ? wglb : wts;
-  const int h0 = (nh * q) / B::NW, h1 = (nh * (q + 1)) / B::NW;
-  const int c = h1 - h0;
+  // hits dealt round-robin over the waves (neighbouring hits of a primitive
+  // come from neighbouring rays and have similar sample counts): wave q
+  // takes hits q, q + NW, ...
+  const int c = q < nh ? (nh - q + B::NW - 1) / B::NW : 0;
   int my_hit = 0, my_k = 0;
   if (lane < c) {
-    my_hit = ws.phit[first + h0 + lane];
+    my_hit = ws.phit[first + q + lane * B::NW];
     my_k = ws.hit_nused[my_hit] > 0 ? (ws.hit_k[my_hit] & kKMask) : 0;
   }
   int incl = wave_incl_scan(my_k);
