@@ -24,24 +24,31 @@ CFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-# The MLP kernels of networks up to 64 wide keep their matrix-core accumulators
-# in ordinary VGPRs and let the compiler sink instructions towards their uses:
-# with the default AGPR form the split-bfloat16 backward spilled about 450
-# bytes per lane to scratch.  (The wide networks' units keep the default: the
-# VGPR form crashes this compiler on some of them.)
+# The MLP kernels keep their matrix-core accumulators in ordinary VGPRs and
+# let the compiler sink instructions towards their uses: with the default AGPR
+# form the split-bfloat16 backward spilled about 450 bytes per lane to
+# scratch.  The VGPR form has crashed this compiler on some versions of the
+# wide networks' kernels; a unit whose compile fails with these options is
+# compiled again without them (slower code, same results).
 MLP_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-sink-insts-to-avoid-spills"]
-EXTRA_FLAGS = {"mlp.hip": MLP_FLAGS, "mlp_bwd.hip": MLP_FLAGS}
+EXTRA_FLAGS = {"mlp.hip": MLP_FLAGS, "mlp_bwd.hip": MLP_FLAGS,
+               "mlp_wide.hip": MLP_FLAGS, "mlp_bwd_wide.hip": MLP_FLAGS}
 
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, "-c", *CFLAGS, *EXTRA_FLAGS.get(src, []), os.path.join(CSRC, src), "-o", obj]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
-    return obj
+    extra = EXTRA_FLAGS.get(src, [])
+    for flags in ([extra, []] if extra else [[]]):
+        cmd = [HIPCC, "-c", *CFLAGS, *flags, os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode == 0:
+            return obj
+        if flags:
+            print(f"warning: hipcc failed for {src} with {' '.join(flags)}; compiling it without them",
+                  file=sys.stderr, flush=True)
+    raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
 
 
 def build(verbose: bool = False) -> str:

@@ -139,9 +139,13 @@ struct FwdArgs {
 // waves per SIMD), four for wide networks
 template <class N>
 constexpr int fwd_waves() { return N::WIDE ? 4 : 8; }
+// waves per SIMD the register allocation must leave room for (two
+// workgroups of eight; wide networks take the whole register file)
+template <class N>
+constexpr int fwd_min_waves() { return N::WIDE ? 1 : 4; }
 
 template <class N>
-__global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_waves<N>() / 2) void mlp_forward_kernel(FwdArgs args) {
+__global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_forward_kernel(FwdArgs args) {
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const Workspace& ws = args.ws;
   const int lane = threadIdx.x % 64;

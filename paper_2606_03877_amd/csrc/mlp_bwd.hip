@@ -709,12 +709,13 @@ static hipError_t bwd_pass(const BwdArgs& a, int items, hipStream_t s) {
   return hipGetLastError();
 }
 
-// wide networks: one pass per layer, from layer J up
-template <class N, int J>
+// wide networks: passes over ranges of WSPAN layers, from layer LO up
+template <class N, int LO>
 static hipError_t wide_passes(const BwdArgs& a, int items, hipStream_t s) {
-  hipError_t e = bwd_pass<N, J, J>(a, items, s);
-  if constexpr (J + 1 < N::NL) {
-    if (e == hipSuccess) return wide_passes<N, J + 1>(a, items, s);
+  constexpr int HI = LO + N::WSPAN - 1 < N::NL - 1 ? LO + N::WSPAN - 1 : N::NL - 1;
+  hipError_t e = bwd_pass<N, LO, HI>(a, items, s);
+  if constexpr (HI + 1 < N::NL) {
+    if (e == hipSuccess) return wide_passes<N, HI + 1>(a, items, s);
   }
   return e;
 }

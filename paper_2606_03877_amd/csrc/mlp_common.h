@@ -71,8 +71,13 @@ struct Net {
   static constexpr int RB0 = (ENC_SLOTS + 15) / 16;   // row blocks of the input-gradient
   // wide networks read their weight operands from global memory (they stay
   // in L2 while a primitive's work items run) instead of staging them in LDS,
-  // and split the backward into one pass per layer's weight gradient
+  // and split the backward into passes over ranges of layers
   static constexpr bool WIDE = wide_net(W);
+  // layers per backward pass of a wide network: each pass recomputes the
+  // network and holds its layers' weight-gradient accumulators.  For
+  // 39-128x4-20, 3 (two passes) measured 251 ms per backward on a 1080p
+  // frame, against 407 ms for one pass per layer and 254 ms for one pass.
+  static constexpr int WSPAN = 3;
   // backward split into two passes over halves of the layers (fewer live
   // weight-gradient accumulators, the network recomputed twice); measured
   // slower than one spilling pass for the 64-wide split form, so off
