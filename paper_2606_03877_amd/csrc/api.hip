@@ -12,11 +12,11 @@ using namespace msplat;
 // around each launch; pairs are harvested when read (or when a ring fills).
 enum Stage {
   ST_ZERO, ST_PREPROCESS, ST_PACK, ST_BIN_COUNT, ST_SCAN, ST_BIN_FILL, ST_MLP_FWD, ST_COMPOSITE,
-  ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_GEO_FINAL, ST_COUNT
+  ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_HIT_GEO, ST_GEO_FINAL, ST_COUNT
 };
 static const char* kStageNames[ST_COUNT] = {
     "zero", "preprocess", "pack_weights", "bin_count", "scan", "bin_fill", "mlp_forward",
-    "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "geo_finalize"};
+    "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "hit_geometry", "geo_finalize"};
 constexpr int kRing = 64;
 struct StageTimer {
   hipEvent_t a[kRing], b[kRing];
@@ -113,6 +113,7 @@ uint64_t layout(const NetShape& n, int64_t R, int64_t hcap, uint8_t* base, Works
   ws.hit_gsa = (float*)take(H * 4);
   ws.hit_tb = (float*)take(H * 4);
   ws.hit_gtot = (float*)take(H * 4);
+  ws.hit_gv = (float*)take(H * 4 * 9);
   ws.phit = (int32_t*)take(H * 4);
   ws.num_rays = R;
   ws.hit_cap = hcap;
@@ -408,6 +409,7 @@ int msplat_render_backward(msplat_ctx* ctx, const msplat_model* m, const msplat_
   STAGE(ctx, ST_MLP_BWD, s,
         launch_mlp_backward(n, ws, *o, (int)items, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr,
                             g_mlp, s));
+  STAGE(ctx, ST_HIT_GEO, s, launch_hit_geometry(ws, ray_d, nh, s));
   STAGE(ctx, ST_GEO_FINAL, s, launch_geo_finalize(ws, n.P, g_center, g_scale, g_quat, s));
   return MSPLAT_OK;
 }

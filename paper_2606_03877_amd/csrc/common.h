@@ -80,6 +80,9 @@ struct Workspace {
   float* hit_gsa;        // backward: g . (colour composited after the hit)
   float* hit_tb;         // backward: transmittance before the hit
   float* hit_gtot;       // backward: g . (the hit's own composited colour)
+  float* hit_gv;         // [9][H] backward: the hit's sums of the sample-position
+                         // adjoints (dL/dp, s dL/dp, dL/ds_k, omega_k dL/ds_k, dL/dDelta
+                         // terms), indexed by the hit's entry in phit
   int32_t* phit;         // [H] hits grouped by primitive
   int64_t num_rays;
   int64_t hit_cap;
@@ -234,6 +237,7 @@ hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat
                                     const float* grad_rgb, const float* grad_trans,
                                     const float* grad_feat, int cf, const float* trans,
                                     hipStream_t s);
+hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, hipStream_t s);
 hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
                                float* g_quat, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);

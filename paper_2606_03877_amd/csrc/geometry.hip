@@ -725,6 +725,103 @@ __global__ __launch_bounds__(256) void composite_adjoint_kernel(
 }
 
 // dL/dM and dL/dv accumulated per primitive -> dL/d(center, scale, quat)
+// Per-hit geometry adjoint over the primitive-grouped hit list: each wave
+// takes kGeoHitsPerLane x 64 consecutive entries.  A hit's samples sit at
+// p_c + s_k e with s_k = (t_a - t_c) + (k + u_k) Delta; the backward kernel
+// leaves per hit the sums over its samples of dL/dp, s_k dL/dp, dL/ds_k,
+// omega_k dL/ds_k (omega_k = (k + u_k)/K) and of the dL/dDelta terms.  Here
+// they are carried through t_a, Delta (chord ends t_c -+ eta, eta =
+// sqrt(g/a)), p_c = o_l + t_c d_l and e = M d to dL/dM and dL/dv (v: the
+// frame's origin offset), which the finalize kernel maps to (mu, s, q).  A
+// wave keeps a running sum while its hits belong to one primitive and adds
+// it to the primitive's totals when the primitive changes (few atomics per
+// wave: the list is grouped by primitive).
+constexpr int kGeoHitsPerLane = 8;
+
+__device__ __forceinline__ void hit_geometry_terms(const Workspace& ws, const float* __restrict__ ray_d, int hit,
+                                                   int64_t pos, int p, float (&acc)[12]) {
+  const int64_t H = ws.hit_cap;
+  const float* gp = ws.geo + (int64_t)p * kGeoStride;
+  float gv[9], pc[3], ee[3];
+  for (int k = 0; k < 9; ++k) gv[k] = ws.hit_gv[k * H + pos];
+  for (int a = 0; a < 3; ++a) {
+    pc[a] = ws.hit_pc[a * H + hit];
+    ee[a] = ws.hit_e[a * H + hit];
+  }
+  const int kraw = ws.hit_k[hit];
+  const bool clipped = (kraw & kClippedBit) != 0;
+  const float Kf = (float)(kraw & kKMask);
+  const float eta = ws.hit_eta[hit];
+  const int ray = ws.hit_ray[hit];
+  float dtb = gv[7] + gv[8] / Kf;
+  float dta = gv[6] - gv[7] - gv[8] / Kf;
+  float lam = clipped ? dtb : dtb + dta;
+  float zet = clipped ? dtb : dtb - dta;
+  float a2 = ee[0] * ee[0] + ee[1] * ee[1] + ee[2] * ee[2];
+  float kap = eta > 0.f ? zet / (eta * a2) : 0.f;
+  float dd[3] = {ray_d[3 * ray], ray_d[3 * ray + 1], ray_d[3 * ray + 2]};
+  // delta_c = mu - o - t_c d = -R diag(s) p_c
+  float dc[3];
+  for (int r = 0; r < 3; ++r) {
+    dc[r] = 0.f;
+    for (int c = 0; c < 3; ++c) dc[r] -= gp[G_R + 3 * r + c] * gp[G_S + c] * pc[c];
+  }
+  for (int r = 0; r < 3; ++r) {
+    float gm = lam * ee[r] / a2 + kap * pc[r];
+    float c1 = gm - gv[r];
+    float c2 = gv[3 + r] - (lam * pc[r] + zet * eta * ee[r]) / a2;
+    for (int c = 0; c < 3; ++c) acc[3 * r + c] = c1 * dc[c] + c2 * dd[c];
+    acc[9 + r] = c1;
+  }
+}
+
+// add a wave's running sum (one primitive, uniform over the wave) and clear it
+__device__ __forceinline__ void flush_geo(float* __restrict__ geo_grad, int p, float (&run)[12]) {
+  if (p < 0) return;
+  for (int k = 0; k < 12; ++k) {
+    float v = wave_sum(run[k]);
+    if (threadIdx.x % 64 == 0 && v != 0.f) atomicAdd(geo_grad + (int64_t)p * 12 + k, v);
+    run[k] = 0.f;
+  }
+}
+
+__global__ __launch_bounds__(256) void hit_geometry_kernel(Workspace ws, const float* __restrict__ ray_d,
+                                                           int64_t num_hits) {
+  const int lane = threadIdx.x % 64;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  const int64_t base = wave * 64 * kGeoHitsPerLane;
+  float run[12];
+  for (int k = 0; k < 12; ++k) run[k] = 0.f;
+  int prun = -1;   // primitive of the running sum (wave-uniform)
+  for (int m = 0; m < kGeoHitsPerLane; ++m) {
+    const int64_t i = base + (int64_t)m * 64 + lane;
+    if (__builtin_amdgcn_readfirstlane((int)(i >= num_hits))) break;   // (lane 0 past the end: all are)
+    float c[12];
+    for (int k = 0; k < 12; ++k) c[k] = 0.f;
+    int p = -1;
+    if (i < num_hits) {
+      const int hit = ws.phit[i];
+      p = ws.hit_prim[hit];
+      if (ws.hit_nused[hit] > 0) hit_geometry_terms(ws, ray_d, hit, i, p, c);   // (else no samples ran)
+    }
+    const int p0 = __builtin_amdgcn_readfirstlane(p);
+    if (__all(p == p0 || p < 0)) {
+      if (p0 != prun) {
+        flush_geo(ws.geo_grad, prun, run);
+        prun = p0;
+      }
+      for (int k = 0; k < 12; ++k) run[k] += c[k];
+    } else {
+      // a primitive boundary inside this group of 64: its terms go directly
+      flush_geo(ws.geo_grad, prun, run);
+      prun = -1;
+      for (int k = 0; k < 12; ++k)
+        if (c[k] != 0.f) atomicAdd(ws.geo_grad + (int64_t)p * 12 + k, c[k]);
+    }
+  }
+  flush_geo(ws.geo_grad, prun, run);
+}
+
 __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* __restrict__ acc,
                                     int P, float* __restrict__ g_center, float* __restrict__ g_scale,
                                     float* __restrict__ g_quat) {
@@ -850,6 +947,14 @@ hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(composite_adjoint_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, ws,
                      R, o, grad_rgb, grad_trans, grad_feat, cf, trans);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, hipStream_t s) {
+  if (num_hits <= 0) return hipSuccess;
+  const int64_t waves = (num_hits + 64 * kGeoHitsPerLane - 1) / (64 * kGeoHitsPerLane);
+  hipLaunchKernelGGL(hit_geometry_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ws, ray_d,
+                     num_hits);
   return hipGetLastError();
 }
 

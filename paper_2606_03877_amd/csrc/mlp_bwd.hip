@@ -474,7 +474,6 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   using B = Bwd<N>;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ int rounds_s[B::NW];
-  __shared__ float gsum_s[12];   // this work item's geometry sums (dL/dM, dL/dv)
   const Workspace& ws = args.ws;
   const int lane = threadIdx.x % 64;
   const int q = threadIdx.x / 64;
@@ -511,7 +510,6 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   const int ns = __builtin_amdgcn_readlane(incl, 63);
   const int nblk = (ns + 31) / 32;
   if (lane == 0) rounds_s[q] = nblk;
-  if (threadIdx.x < 12) gsum_s[threadIdx.x] = 0.f;
   __syncthreads();
   int rounds = 0;
   for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
@@ -529,13 +527,14 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     const bool valid = x < ns;
     // the hit of this column: the last of the wave's hits whose samples
     // start at or before it (hit records read from lanes into scalar registers)
-    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
+    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0, slot = 0;
     for (int l = 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
       if (ol <= x) {
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);
         hoff = ol;
+        slot = l;
       }
     }
     const int k = valid ? x - hoff : 0;
@@ -632,12 +631,9 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
 
     // ---- per-hit geometry sums ----
-    float pc[3], ee[3];
+    float ee[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      pc[a] = ws.hit_pc[a * H + hit];
-      ee[a] = ws.hit_e[a * H + hit];
-    }
+    for (int a = 0; a < 3; ++a) ee[a] = ws.hit_e[a * H + hit];
     const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
     float gv[9] = {dp[0], dp[1], dp[2], sk * dp[0], sk * dp[1], sk * dp[2], dtk, om * dtk, dts};
 #pragma unroll
@@ -645,40 +641,12 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
       gv[i] = sc.incl(gv[i]);
       if (!sc.seen_head) gv[i] += cr_geo[i];
     }
+    // the lane of the hit's last sample leaves the hit's sums; the chain to
+    // the primitive's frame runs per hit in a kernel of its own
     if (last && g == 0) {
-      const float* gp = ws.geo + (int64_t)p * kGeoStride;
-      const int kraw = ws.hit_k[hit];
-      const bool clipped = (kraw & kClippedBit) != 0;
-      const float eta = ws.hit_eta[hit];
-      const float Kf = (float)K;
-      float dtb = gv[7] + gv[8] / Kf;
-      float dta = gv[6] - gv[7] - gv[8] / Kf;
-      float lam = clipped ? dtb : dtb + dta;
-      float zet = clipped ? dtb : dtb - dta;
-      float a2 = ee[0] * ee[0] + ee[1] * ee[1] + ee[2] * ee[2];
-      float kap = eta > 0.f ? zet / (eta * a2) : 0.f;
-      float dd[3] = {args.ray_d[3 * ray], args.ray_d[3 * ray + 1], args.ray_d[3 * ray + 2]};
-      // delta_c = mu - o - t_c d = -R diag(s) p_c
-      float dc[3];
+      const int pos = first + q + slot * B::NW;   // the hit's entry in the grouped list
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        dc[r] = 0.f;
-#pragma unroll
-        for (int cidx = 0; cidx < 3; ++cidx) dc[r] -= gp[G_R + 3 * r + cidx] * gp[G_S + cidx] * pc[cidx];
-      }
-      float c1[3], c2[3];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        float gm = lam * ee[r] / a2 + kap * pc[r];
-        c1[r] = gm - gv[r];
-        c2[r] = gv[3 + r] - (lam * pc[r] + zet * eta * ee[r]) / a2;
-      }
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int cidx = 0; cidx < 3; ++cidx) atomicAdd(&gsum_s[3 * r + cidx], c1[r] * dc[cidx] + c2[r] * dd[cidx]);
-        atomicAdd(&gsum_s[9 + r], c1[r]);
-      }
+      for (int i = 0; i < 9; ++i) ws.hit_gv[i * H + pos] = gv[i];
     }
     // carries of the geometry scans
 #pragma unroll
@@ -687,10 +655,6 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
 
   // ---- flush the weight-gradient strips ----
   flush_range<N, LO, LO, HI>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
-  // ---- flush the geometry sums ----
-  __syncthreads();
-  if (threadIdx.x < 12 && gsum_s[threadIdx.x] != 0.f)
-    atomicAdd(ws.geo_grad + (int64_t)p * 12 + threadIdx.x, gsum_s[threadIdx.x]);
 }
 
 }  // namespace
