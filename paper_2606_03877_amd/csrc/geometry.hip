@@ -277,7 +277,9 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
   int64_t packet = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = lane_id();
   int64_t ray = packet * kWave + lane;
-  if (packet * kWave >= R) return;   // whole wave out of range (wave-uniform)
+  // a wave past the last ray skips the work but still meets the workgroup
+  // barrier below (wave-uniform)
+  const bool live = packet * kWave < R;
   bool valid = ray < R;
   float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
   float3 d = valid ? ld3(ray_d, ray) : make_float3(0.f, 0.f, 1.f);
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
   int64_t nsamp = 0;
   int nfall = 0;
   float min_g = 3.0e38f;
-  for (int base = 0; base < P; base += kWave) {
+  for (int base = 0; live && base < P; base += kWave) {
     int pl = base + lane;
     bool cand = false;
     if (pl < P) {
@@ -324,10 +326,27 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
   int64_t ws = wave_sum(nsamp);
   int wf = wave_sum(nfall);
   float wm = wave_min(min_g);
+  // the workgroup's waves combine their counters in LDS first: one set of
+  // atomics per workgroup (same-address atomics from every wave serialise)
+  __shared__ unsigned long long bs_samp;
+  __shared__ int bs_fall;
+  __shared__ uint32_t bs_ming;
+  if (threadIdx.x == 0) {
+    bs_samp = 0ull;
+    bs_fall = 0;
+    bs_ming = 0x7f7fffffu;
+  }
+  __syncthreads();
   if (lane == 0) {
-    atomicAdd((unsigned long long*)&ctr->num_samples, (unsigned long long)ws);
-    if (wf) atomicAdd(&ctr->num_fallbacks, wf);
-    atomicMin(&ctr->min_abs_g_bits, __float_as_uint(wm));
+    atomicAdd(&bs_samp, (unsigned long long)ws);
+    atomicAdd(&bs_fall, wf);
+    atomicMin(&bs_ming, __float_as_uint(wm));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd((unsigned long long*)&ctr->num_samples, bs_samp);
+    if (bs_fall) atomicAdd(&ctr->num_fallbacks, bs_fall);
+    atomicMin(&ctr->min_abs_g_bits, bs_ming);
   }
 }
 
