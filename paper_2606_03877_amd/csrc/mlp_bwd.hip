@@ -3,22 +3,25 @@
 // derivative of the forward in mlp.hip with the discrete decisions fixed).
 //
 // Work decomposition is the forward's: one workgroup per group of up to
-// kHitsPerItem hits of one primitive, weights (forward and transposed) staged
-// in LDS, each wave walking its share of the samples in 32-column blocks.
+// kHitsPerItem hits of one primitive, its operands (forward and transposed)
+// staged in LDS, each wave walking its hits' samples in 32-column blocks.
 // Per block the wave
-//   1. recomputes the network, keeping every layer's input activations in
+//   1. recomputes the network, keeping the hi parts of the layer inputs in
 //      registers (nothing is stored to memory between forward and backward);
 //   2. forms dL/d(raw outputs) from the compositing adjoint: with per-hit
 //      transmittance T_b, suffix g.S_after and total g.(hit colour) from the
 //      per-ray adjoint, dtau_k = T_{k+1} g.c_k - sum_{j>k} w_j g.c_j - g.S_after;
 //   3. runs the transposed chain delta_{j-1} = W_j^T delta_j * relu' on the
 //      matrix cores, registers to registers;
-//   4. reduces dL/dp of its samples into per-hit sums and chains them through
-//      the contact point, the chord and the frame M = diag(s)^-1 R^T.
+//   4. reduces the sample-position adjoints of its samples into per-hit sums
+//      (segmented scans), which the hit's last sample stores; a kernel of its
+//      own (geometry.hip) chains them through the contact point, the chord
+//      and the frame M = diag(s)^-1 R^T.
 // Weight gradients are contractions over samples: the waves of a workgroup
-// publish delta_j and the layer inputs of their block to LDS, then each wave
-// accumulates its own 16-row strips of dW_j over all the workgroup's samples
-// in registers.  Those sums are added to global memory once per work item.
+// publish delta_j and the layer inputs of their blocks to LDS, then each wave
+// accumulates its units of dW_j (a 16-row strip by a few 16-column tiles)
+// over all the workgroup's samples in registers.  Those sums are added to
+// global memory once per work item.
 #include "mlp_kernels.h"
 
 namespace msplat {
@@ -91,8 +94,6 @@ struct Bwd {
   static constexpr int toff(int lo, int j) { return TOFF(j) - TOFF(lo); }
 };
 
-template <class N>
-using BT = typename Operands<N>::BT;
 
 // D registers -> B operand (no activation), first NSLOT slots
 template <class N, int NSLOT, int RB>
@@ -123,11 +124,6 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int la
     acc[rb] = c;
     __builtin_amdgcn_sched_barrier(0);
   }
-}
-
-template <class N>
-__device__ __forceinline__ float bval(const BT<N>& v, int e) {
-  if constexpr (N::BF16) return (float)v[e]; else return v;
 }
 
 // publish this wave's 32 columns of a layer input (slots -> canonical rows)
