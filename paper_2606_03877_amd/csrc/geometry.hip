@@ -744,19 +744,13 @@ __global__ __launch_bounds__(256) void composite_adjoint_kernel(
 }
 
 // dL/dM and dL/dv accumulated per primitive -> dL/d(center, scale, quat)
-// Per-hit geometry adjoint over the primitive-grouped hit list: each wave
-// takes kGeoHitsPerLane x 64 consecutive entries.  A hit's samples sit at
+// Per-hit geometry adjoint over the primitive-grouped hit list.  A hit's samples sit at
 // p_c + s_k e with s_k = (t_a - t_c) + (k + u_k) Delta; the backward kernel
 // leaves per hit the sums over its samples of dL/dp, s_k dL/dp, dL/ds_k,
 // omega_k dL/ds_k (omega_k = (k + u_k)/K) and of the dL/dDelta terms.  Here
 // they are carried through t_a, Delta (chord ends t_c -+ eta, eta =
 // sqrt(g/a)), p_c = o_l + t_c d_l and e = M d to dL/dM and dL/dv (v: the
-// frame's origin offset), which the finalize kernel maps to (mu, s, q).  A
-// wave keeps a running sum while its hits belong to one primitive and adds
-// it to the primitive's totals when the primitive changes (few atomics per
-// wave: the list is grouped by primitive).
-constexpr int kGeoHitsPerLane = 8;
-
+// frame's origin offset), which the finalize kernel maps to (mu, s, q).
 __device__ __forceinline__ void hit_geometry_terms(const Workspace& ws, const float* __restrict__ ray_d, int hit,
                                                    int64_t pos, int p, float (&acc)[12]) {
   const int64_t H = ws.hit_cap;
@@ -794,51 +788,58 @@ __device__ __forceinline__ void hit_geometry_terms(const Workspace& ws, const fl
   }
 }
 
-// add a wave's running sum (one primitive, uniform over the wave) and clear it
-__device__ __forceinline__ void flush_geo(float* __restrict__ geo_grad, int p, float (&run)[12]) {
-  if (p < 0) return;
-  for (int k = 0; k < 12; ++k) {
-    float v = wave_sum(run[k]);
-    if (threadIdx.x % 64 == 0 && v != 0.f) atomicAdd(geo_grad + (int64_t)p * 12 + k, v);
-    run[k] = 0.f;
-  }
-}
-
+// One thread per entry of the primitive-grouped hit list (all loads of a hit
+// are issued at once; no thread walks a chain of hits).  A workgroup whose
+// hits share one primitive adds its sum with one set of atomics; otherwise
+// each wave whose hits share one does; otherwise each thread.
 __global__ __launch_bounds__(256) void hit_geometry_kernel(Workspace ws, const float* __restrict__ ray_d,
                                                            int64_t num_hits) {
-  const int lane = threadIdx.x % 64;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
-  const int64_t base = wave * 64 * kGeoHitsPerLane;
-  float run[12];
-  for (int k = 0; k < 12; ++k) run[k] = 0.f;
-  int prun = -1;   // primitive of the running sum (wave-uniform)
-  for (int m = 0; m < kGeoHitsPerLane; ++m) {
-    const int64_t i = base + (int64_t)m * 64 + lane;
-    if (__builtin_amdgcn_readfirstlane((int)(i >= num_hits))) break;   // (lane 0 past the end: all are)
-    float c[12];
-    for (int k = 0; k < 12; ++k) c[k] = 0.f;
-    int p = -1;
-    if (i < num_hits) {
-      const int hit = ws.phit[i];
-      p = ws.hit_prim[hit];
-      if (ws.hit_nused[hit] > 0) hit_geometry_terms(ws, ray_d, hit, i, p, c);   // (else no samples ran)
-    }
-    const int p0 = __builtin_amdgcn_readfirstlane(p);
-    if (__all(p == p0 || p < 0)) {
-      if (p0 != prun) {
-        flush_geo(ws.geo_grad, prun, run);
-        prun = p0;
+  __shared__ float part[4][12];
+  __shared__ int wp[4];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float c[12];
+  for (int k = 0; k < 12; ++k) c[k] = 0.f;
+  int p = -1;
+  if (i < num_hits) {
+    const int hit = ws.phit[i];
+    p = ws.hit_prim[hit];
+    if (ws.hit_nused[hit] > 0) hit_geometry_terms(ws, ray_d, hit, i, p, c);   // (else no samples ran)
+  }
+  // the wave's primitive, or -2 if its hits belong to several (-1: no hits)
+  const int pw0 = __builtin_amdgcn_readfirstlane(p);
+  const int pw = __all(p == pw0 || p < 0) ? pw0 : -2;
+  if (lane == 0) wp[wv] = pw;
+  __syncthreads();
+  int pb = wp[0];
+  for (int w = 1; w < 4; ++w) {
+    const int o = wp[w];
+    if (o == -1) continue;
+    pb = (pb == -1) ? o : (pb == o ? pb : -2);
+  }
+  if (pb == -2 || pw == -2) {
+    // several primitives in this workgroup: per wave, or per thread
+    if (pw >= 0) {
+      for (int k = 0; k < 12; ++k) {
+        float v = wave_sum(c[k]);
+        if (lane == 0 && v != 0.f) atomicAdd(ws.geo_grad + (int64_t)pw * 12 + k, v);
       }
-      for (int k = 0; k < 12; ++k) run[k] += c[k];
-    } else {
-      // a primitive boundary inside this group of 64: its terms go directly
-      flush_geo(ws.geo_grad, prun, run);
-      prun = -1;
+    } else if (pw == -2 && p >= 0) {
       for (int k = 0; k < 12; ++k)
         if (c[k] != 0.f) atomicAdd(ws.geo_grad + (int64_t)p * 12 + k, c[k]);
     }
+    return;
   }
-  flush_geo(ws.geo_grad, prun, run);
+  if (pb < 0) return;   // no hits in this workgroup
+  for (int k = 0; k < 12; ++k) {
+    float v = wave_sum(c[k]);
+    if (lane == 0) part[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 12) {
+    const float v = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
+    if (v != 0.f) atomicAdd(ws.geo_grad + (int64_t)pb * 12 + threadIdx.x, v);
+  }
 }
 
 __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* __restrict__ acc,
@@ -971,8 +972,7 @@ hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat
 
 hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, hipStream_t s) {
   if (num_hits <= 0) return hipSuccess;
-  const int64_t waves = (num_hits + 64 * kGeoHitsPerLane - 1) / (64 * kGeoHitsPerLane);
-  hipLaunchKernelGGL(hit_geometry_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ws, ray_d,
+  hipLaunchKernelGGL(hit_geometry_kernel, dim3((unsigned)((num_hits + 255) / 256)), dim3(256), 0, s, ws, ray_d,
                      num_hits);
   return hipGetLastError();
 }
