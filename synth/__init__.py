@@ -76,6 +76,10 @@ CONFIGS: List[Config] = [
     Config(4, "multiview", 512, 6, 64, 3, 4, "uniform", ("loguniform", 0.02, 0.5),
            tuple([(256, 256)] * 4 + [(512, 512)] * 4 + [(800, 800)] * 4 + [(1024, 768)] * 4),
            3.0, 0, t_stop=1e-4),
+    # the 64-wide network with 16 identity feature channels (39-64x3-20, a
+    # compiled shape no workload above uses): a parity-test case
+    Config(5, "features-64", 64, 6, 64, 3, 20, "uniform", ("loguniform", 0.05, 0.3),
+           ((800, 800),), 3.0, 64, t_stop=1e-4),
 ]
 
 

@@ -11,7 +11,7 @@ from gpu_cases import (RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(0, 40, 36), (1, 64, 50), (4, 44, 40), (3, 40, 30)]
+CASES = [(0, 40, 36), (1, 64, 50), (4, 44, 40), (3, 40, 30), (5, 48, 40)]
 KEYS = ("center", "scale", "quat", "mlp")
 
 

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 # (config, width, height): small frames that span several 8x8 tiles and a
 # ragged tail of rays (counts not a multiple of 64)
-CASES = [(0, 64, 64), (1, 100, 75), (4, 90, 70), (3, 72, 41)]
+CASES = [(0, 64, 64), (1, 100, 75), (4, 90, 70), (3, 72, 41), (5, 72, 41)]
 
 
 def _case(ci, w, h, t_stop=None):
