@@ -58,7 +58,7 @@ typedef enum msplat_precision {
  * Compiled shapes (pe_freqs, hidden_width, hidden_layers, out_dim):
  *   (4, 32, 2, 4), (6, 64, 3, 4), (6, 64, 3, 20), (6, 128, 4, 20).  Others:
  *   MSPLAT_E_UNSUPPORTED.  Networks wider than 64 read their weights from global
- *   memory and run the backward as one pass per layer.
+ *   memory and run the backward in two passes over ranges of layers.
  */
 typedef struct msplat_model {
   int32_t num_prims;     /* P >= 1 */
