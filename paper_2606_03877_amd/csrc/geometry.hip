@@ -637,22 +637,28 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
       ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
       ws.hit_ray[j] = (int32_t)ray;
     }
-    // slots in the per-primitive lists: one atomic per distinct primitive of
-    // the wave (coherent packets share few), ranks within it by lane
+    // slots in the per-primitive lists: the lanes are grouped by primitive
+    // (ballots only), then every group's first lane reserves the group's
+    // slots with one atomic, all groups at once (a reservation per group in
+    // turn would wait for each atomic's return); ranks within a group by lane
     uint64_t pending = __ballot(act);
-    int slot = 0;
+    int leader_of = lane, rank = 0, cnt = 0;
     while (pending) {
       const int leader = __builtin_ctzll(pending);
       const int lp = __shfl(p, leader, 64);
       const bool mine = act && p == lp;
       const uint64_t same = __ballot(mine);
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&ws.prim_cursor[lp], __popcll(same));
-      base = __shfl(base, leader, 64);
-      if (mine) slot = base + __popcll(same & ((1ull << lane) - 1ull));
+      if (mine) {
+        leader_of = leader;
+        rank = __popcll(same & ((1ull << lane) - 1ull));
+      }
+      if (lane == leader) cnt = __popcll(same);
       pending &= ~same;
     }
-    if (act) ws.phit[slot] = (int32_t)j;
+    int base = 0;
+    if (act && lane == leader_of) base = atomicAdd(&ws.prim_cursor[p], cnt);
+    base = __shfl(base, leader_of, 64);
+    if (act) ws.phit[base + rank] = (int32_t)j;
   }
 }
 
