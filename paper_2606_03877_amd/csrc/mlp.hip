@@ -175,16 +175,17 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
   }
   // this wave's hits
   constexpr int NWF = fwd_waves<N>();
-  // hits dealt round-robin over the waves (neighbouring hits of a primitive
-  // come from neighbouring rays and have similar sample counts): wave wv
-  // takes hits wv, wv + NW, ...
-  const int c = wv < nh ? (nh - wv + NWF - 1) / NWF : 0;
-  int my_hit = 0, my_k = 0;
-  if (lane < c) {
-    my_hit = ws.phit[first + wv + lane * NWF];
-    int kk = ws.hit_k[my_hit] & kKMask;
-    my_k = (args.mode == 0 || ws.hit_nused[my_hit] == -1) ? kk : 0;
+  static_assert(kHitsPerItem <= 64, "one item's hits fit the lanes of a wave");
+  int item_hit = 0, item_k = 0;
+  if (lane < nh) {
+    item_hit = ws.phit[first + lane];
+    int kk = ws.hit_k[item_hit] & kKMask;
+    item_k = (args.mode == 0 || ws.hit_nused[item_hit] == -1) ? kk : 0;
   }
+  int my_k;
+  const int li = deal_hits<NWF>(lane < nh ? (item_k << 7) | (127 - lane) : -1, wv, lane, nh, my_k);
+  const int my_hit = __shfl(item_hit, li < 0 ? 0 : li, 64);
+  const int c = __popcll(__ballot(li >= 0));   // (the wave's slots in use form a prefix)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
   const int ns = __builtin_amdgcn_readlane(incl, 63);

@@ -492,15 +492,16 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     wts = lds + B::W_OFF - B::SKIP;   // read after the barrier below
   }
   const uint8_t* wts0 = B::G0 ? wglb : wts;
-  // hits dealt round-robin over the waves (neighbouring hits of a primitive
-  // come from neighbouring rays and have similar sample counts): wave q
-  // takes hits q, q + NW, ...
-  const int c = q < nh ? (nh - q + B::NW - 1) / B::NW : 0;
-  int my_hit = 0, my_k = 0;
-  if (lane < c) {
-    my_hit = ws.phit[first + q + lane * B::NW];
-    my_k = ws.hit_nused[my_hit] > 0 ? (ws.hit_k[my_hit] & kKMask) : 0;
+  static_assert(kHitsPerItem <= 64, "one item's hits fit the lanes of a wave");
+  int item_hit = 0, item_k = 0;
+  if (lane < nh) {
+    item_hit = ws.phit[first + lane];
+    item_k = ws.hit_nused[item_hit] > 0 ? (ws.hit_k[item_hit] & kKMask) : 0;
   }
+  int my_k;
+  const int my_li = deal_hits<B::NW>(lane < nh ? (item_k << 7) | (127 - lane) : -1, q, lane, nh, my_k);
+  const int my_hit = __shfl(item_hit, my_li < 0 ? 0 : my_li, 64);
+  const int c = __popcll(__ballot(my_li >= 0));   // (the wave's slots in use form a prefix)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
   const int ns = __builtin_amdgcn_readlane(incl, 63);
@@ -523,14 +524,15 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     const bool valid = x < ns;
     // the hit of this column: the last of the wave's hits whose samples
     // start at or before it (hit records read from lanes into scalar registers)
-    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0, slot = 0;
+    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
+    int hli = __builtin_amdgcn_readlane(my_li, 0);
     for (int l = 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
       if (ol <= x) {
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);
         hoff = ol;
-        slot = l;
+        hli = __builtin_amdgcn_readlane(my_li, l);
       }
     }
     const int k = valid ? x - hoff : 0;
@@ -640,7 +642,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     // the lane of the hit's last sample leaves the hit's sums; the chain to
     // the primitive's frame runs per hit in a kernel of its own
     if (last && g == 0) {
-      const int pos = first + q + slot * B::NW;   // the hit's entry in the grouped list
+      const int pos = first + hli;   // the hit's entry in the grouped list
 #pragma unroll
       for (int i = 0; i < 9; ++i) ws.hit_gv[i * H + pos] = gv[i];
     }

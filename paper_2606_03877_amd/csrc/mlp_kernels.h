@@ -360,6 +360,36 @@ __device__ __forceinline__ float col_below(float v, int col) {
   return (col & 15) ? a : (col ? b : 0.f);
 }
 
+// The hits of a work item dealt to its NW waves so that the waves' sample
+// counts balance (a workgroup lasts as long as its busiest wave).  Lane
+// l < nh brings key (k_l << 7) | (127 - l), k_l its hit's sample count, other
+// lanes -1; the keys are sorted in descending order across the wave
+// (bitonic network: distinct keys, item-local index in the low bits), and
+// sorted position r goes to wave w, slot s with r = NW s + w for even s and
+// NW s + NW - 1 - w for odd s (snake order).  Returns the item-local index
+// of the hit in slot `lane` of wave `w` (-1: no hit) and its count in k.
+template <int NW>
+__device__ __forceinline__ int deal_hits(int key, int w, int lane, int nh, int& k) {
+  int v = key;
+#pragma unroll
+  for (int kk = 2; kk <= 64; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      const int o = __shfl_xor(v, j, 64);
+      const bool keep_max = ((lane & kk) == 0) == ((lane & j) == 0);
+      v = keep_max ? max(v, o) : min(v, o);
+    }
+  }
+  const int r = NW * lane + ((lane & 1) ? NW - 1 - w : w);
+  const int got = __shfl(v, r < 64 ? r : 63, 64);
+  if (r >= nh) {
+    k = 0;
+    return -1;
+  }
+  k = got >> 7;
+  return 127 - (got & 127);
+}
+
 __device__ __forceinline__ int find_prim(const int32_t* __restrict__ wi_off, int P, int wi) {
   int lo = 0, hi = P;   // wi_off[lo] <= wi < wi_off[hi]
   while (hi - lo > 1) {
