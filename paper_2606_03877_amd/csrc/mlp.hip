@@ -3,7 +3,7 @@
 // Hits are grouped by primitive; one workgroup takes up to kHitsPerItem hits
 // of one primitive, stages that primitive's packed weights in LDS once (wide
 // networks read them from L2), and its waves (eight; four for wide networks)
-// each walk the samples of their hits (dealt round-robin) in blocks of 32
+// each walk the samples of their hits (dealt by sample count) in blocks of 32
 // samples (matrix columns).  Per block: positional encoding straight
 // into the B operand, the layer chain on the matrix cores with activations
 // kept in registers, then the output activations and the hit-local front-to-
