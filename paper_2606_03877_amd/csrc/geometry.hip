@@ -268,17 +268,26 @@ __device__ __forceinline__ bool cone_may_hit(const Cone& c, float cx, float cy, 
 
 // ---------------------------------------------------------- count kernel --
 
+constexpr int kBinHistMax = 8192;   // primitives counted in LDS per workgroup (32 KiB)
+
 __global__ __launch_bounds__(256) void bin_count_kernel(
     const float* __restrict__ ray_o, const float* __restrict__ ray_d,
     const float* __restrict__ center, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ geo, int64_t R, int P,
     msplat_opts opt, int32_t* __restrict__ ray_cnt, int32_t* __restrict__ prim_nhit,
     DevCounters* __restrict__ ctr) {
+  // per-primitive hit counts of the workgroup's packets, added to the global
+  // counts once at the end (same-address atomics from every packet serialise)
+  extern __shared__ int hist[];
+  if (P <= kBinHistMax) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x) hist[i] = 0;
+  }
+  __syncthreads();
   int64_t packet = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = lane_id();
   int64_t ray = packet * kWave + lane;
   // a wave past the last ray skips the work but still meets the workgroup
-  // barrier below (wave-uniform)
+  // barriers below (wave-uniform)
   const bool live = packet * kWave < R;
   bool valid = ray < R;
   float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
@@ -319,7 +328,10 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
         nsamp += K;
       }
       int cnt = __popcll(__ballot(hit));
-      if (lane == 0 && cnt) atomicAdd(&prim_nhit[p], cnt);
+      if (lane == 0 && cnt) {
+        if (P <= kBinHistMax) atomicAdd(&hist[p], cnt);
+        else atomicAdd(&prim_nhit[p], cnt);
+      }
     }
   }
   if (valid) ray_cnt[ray + 1] = nhit;
@@ -347,6 +359,10 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
     atomicAdd((unsigned long long*)&ctr->num_samples, bs_samp);
     if (bs_fall) atomicAdd(&ctr->num_fallbacks, bs_fall);
     atomicMin(&ctr->min_abs_g_bits, bs_ming);
+  }
+  if (P <= kBinHistMax) {
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+      if (hist[i]) atomicAdd(&prim_nhit[i], hist[i]);
   }
 }
 
@@ -925,7 +941,8 @@ hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float
                              const float* center, const float* scale, const float* quat, int64_t R,
                              int P, const msplat_opts& o, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_count_kernel, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
+  const size_t hist_bytes = P <= kBinHistMax ? (size_t)P * 4 : 0;
+  hipLaunchKernelGGL(bin_count_kernel, dim3(packet_blocks(R)), dim3(256), hist_bytes, s, ray_o, ray_d, center,
                      scale, quat, (const float*)ws.geo, R, P, o, ws.ray_off, ws.prim_nhit,
                      ws.counters);
   return hipGetLastError();
