@@ -95,32 +95,47 @@ __global__ void pack_weights_kernel(const float* __restrict__ mlp, uint8_t* __re
 }
 
 // full network of one 32-sample block; returns the output layer's D registers
-template <class N, int J>
-__device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ wb, int lane,
-                                               f32x16 (&acc)[N::RBH]) {
+template <class N, int J, int LAYOUT>
+__device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
+                                               int lane, f32x16 (&acc)[N::RBH]) {
   Act<N, rup(N::HID_KS, N::KGRP)> Bh;
   relu_to_B<N>(acc, Bh);
   if constexpr (J < N::NL - 1) {
-    layer_fwd<N, J, N::HID_KS>(wb, lane, Bh, acc);
-    return hidden_chain<N, J + 1>(wb, lane, acc);
+    layer_fwd<N, J, N::HID_KS, LAYOUT>(wb, wlo, lane, Bh, acc);
+    return hidden_chain<N, J + 1, LAYOUT>(wb, wlo, lane, acc);
   } else {
     f32x16 out[1];
-    layer_fwd<N, J, N::HID_KS>(wb, lane, Bh, out);
+    layer_fwd<N, J, N::HID_KS, LAYOUT>(wb, wlo, lane, Bh, out);
     return out[0];
   }
 }
 
-template <class N>
-__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, int lane, const float ph[3],
-                                                const float pl[3]) {
+template <class N, int LAYOUT>
+__device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
+                                                int lane, const float ph[3], const float pl[3]) {
   int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
   encode_slots<N>(ph, pl, g, ev);
   Act<N, rup(N::ENC_KS, N::KGRP)> B0;
   enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
-  layer_fwd<N, 0, N::ENC_KS>(wb, lane, B0, acc);
-  return hidden_chain<N, 1>(wb, lane, acc);
+  layer_fwd<N, 0, N::ENC_KS, LAYOUT>(wb, wlo, lane, B0, acc);
+  return hidden_chain<N, 1, LAYOUT>(wb, wlo, lane, acc);
+}
+
+// How the forward kernel reads a primitive's operands: 1, all staged in LDS
+// (networks up to 64 wide, and wider plain-BF16 ones, whose operands fit);
+// 2, the split form's hi sections and biases staged in LDS and the lo
+// sections read from L2 (wide split networks: both halves do not fit);
+// 0, everything from L2 (wide FP32).
+constexpr int kFwdLdsMax = 160 * 1024;
+template <class N>
+constexpr int fwd_stage() {
+  return N::fwd_bytes() <= kFwdLdsMax ? 1 : ((N::SPLIT && N::fwd_hi_bytes() <= kFwdLdsMax) ? 2 : 0);
+}
+template <class N>
+constexpr int fwd_lds_bytes() {
+  return fwd_stage<N>() == 1 ? N::fwd_bytes() : (fwd_stage<N>() == 2 ? N::fwd_hi_bytes() : 0);
 }
 
 // ------------------------------------------------------------- forward --
@@ -163,13 +178,26 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     if ((int)threadIdx.x < nh) flag = ws.hit_nused[ws.phit[first + threadIdx.x]] == -1;
     if (!__syncthreads_or(flag)) return;
   }
-  // the primitive's packed forward operands: staged in LDS, or read where
-  // they are (global memory, L2-resident) for wide networks
-  const uint8_t* wts = ws.wpack + (int64_t)p * ws.wpack_bytes;
-  if constexpr (!N::WIDE) {
-    const uint4* src = reinterpret_cast<const uint4*>(wts);
+  // the primitive's packed forward operands, staged in LDS as fwd_stage says
+  const uint8_t* wglb = ws.wpack + (int64_t)p * ws.wpack_bytes;
+  const uint8_t* wts = wglb;
+  if constexpr (fwd_stage<N>() == 1) {
+    const uint4* src = reinterpret_cast<const uint4*>(wglb);
     uint4* dst = reinterpret_cast<uint4*>(lds);
     for (int i = threadIdx.x; i < N::fwd_bytes() / 16; i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    wts = lds;
+  } else if constexpr (fwd_stage<N>() == 2) {
+    // each layer's hi section, then the biases
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+#pragma unroll
+    for (int j = 0; j < N::NL; ++j) {
+      const uint4* src = reinterpret_cast<const uint4*>(wglb + N::fwdA_off(j));
+      for (int i = threadIdx.x; i < N::fwdA_single(j) / 16; i += blockDim.x) dst[N::fwd_hi_off(j) / 16 + i] = src[i];
+    }
+    const uint4* srcb = reinterpret_cast<const uint4*>(wglb + N::bias_off(0));
+    for (int i = threadIdx.x; i < (N::fwd_bytes() - N::bias_off(0)) / 16; i += blockDim.x)
+      dst[N::fwd_hi_off(N::NL) / 16 + i] = srcb[i];
     __syncthreads();
     wts = lds;
   }
@@ -220,7 +248,7 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     const float dlt = ws.hit_dlt[hit];
     float ph[3], pl[3];
     sample_position(ws, hit, k, u, ph, pl);
-    f32x16 o = forward_block<N>(wts, lane, ph, pl);
+    f32x16 o = forward_block<N, fwd_stage<N>() == 2 ? kHiStaged : kPacked>(wts, wglb, lane, ph, pl);
     // density of the column (held by half 0), shared with half 1
     float tau0 = valid ? softplusf_(o[3]) * dlt : 0.f;
     const float tau = from_lower_half(tau0);
@@ -335,7 +363,16 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
                            float* rgb, float* trans, float* feat, hipStream_t s) {
   if (items <= 0) return hipSuccess;
   FwdArgs a{ws, o, mode, P, rgb, trans, feat};
-  size_t lds = N::WIDE ? 0 : N::fwd_bytes();
+  size_t lds = fwd_lds_bytes<N>();
+  if (lds > 64 * 1024) {
+    static bool attr = false;   // (per network type)
+    if (!attr) {
+      hipError_t e = hipFuncSetAttribute((const void*)mlp_forward_kernel<N>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+  }
   hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3(items), dim3(64 * fwd_waves<N>()), lds, s, a);
   return hipGetLastError();
 }

@@ -113,10 +113,10 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int la
   constexpr int NG = N::groups(N::bks(J));
   const uint8_t* A = wb + N::bwdA_off(J);
   RowOps<N, NG, false> ops[2];
-  load_row<N, NG, false>(A, N::bwdA_single(J), nullptr, 0, lane, ops[0]);
+  load_row<N, NG, false>(A, A + N::bwdA_single(J), nullptr, 0, lane, ops[0]);
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    if (rb + 1 < RB) load_row<N, NG, false>(A, N::bwdA_single(J), nullptr, rb + 1, lane, ops[(rb + 1) & 1]);
+    if (rb + 1 < RB) load_row<N, NG, false>(A, A + N::bwdA_single(J), nullptr, rb + 1, lane, ops[(rb + 1) & 1]);
     f32x16 c;
 #pragma unroll
     for (int e = 0; e < 16; ++e) c[e] = 0.f;
@@ -379,12 +379,12 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, c
   f32x16 acc[N::RBH];
   {
     FwdOps<N, 0, N::ENC_KS> first;
-    fwd_row_load<N, 0, N::ENC_KS>(wb0, lane, 0, first);
+    fwd_row_load<N, 0, N::ENC_KS>(wb0, wb0, lane, 0, first);
     float ev[N::ENC_KS * N::KSTEP];
     encode_slots<N>(ph, pl, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
-    layer_fwd_from<N, 0, N::ENC_KS>(wb0, lane, a0, acc, first);
+    layer_fwd_from<N, 0, N::ENC_KS>(wb0, wb0, lane, a0, acc, first);
   }
   f32x16 out;
   chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);

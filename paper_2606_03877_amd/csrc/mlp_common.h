@@ -110,6 +110,13 @@ struct Net {
     return j == 0 ? fwdA_off(NL - 1) + fwdA_bytes(NL - 1) : bias_off(j - 1) + bias_bytes(j - 1);
   }
   __host__ __device__ static constexpr int fwd_bytes() { return bias_off(NL - 1) + bias_bytes(NL - 1); }
+  // a forward staging of the hi parts only (split form): the layers' hi
+  // sections back to back, then the biases
+  __host__ __device__ static constexpr int fwd_hi_off(int j) {
+    return j == 0 ? 0 : fwd_hi_off(j - 1) + fwdA_single(j - 1);
+  }
+  __host__ __device__ static constexpr int fwd_hi_bias(int j) { return fwd_hi_off(NL) + bias_off(j) - bias_off(0); }
+  __host__ __device__ static constexpr int fwd_hi_bytes() { return fwd_hi_off(NL) + fwd_bytes() - bias_off(0); }
   __host__ __device__ static constexpr int bwdA_off(int j) {
     return j == 0 ? fwd_bytes() : bwdA_off(j - 1) + bwdA_bytes(j - 1);
   }

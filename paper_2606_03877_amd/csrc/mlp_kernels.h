@@ -101,13 +101,13 @@ struct RowOps {
 };
 
 template <class N, int NG, bool BIAS>
-__device__ __forceinline__ void load_row(const uint8_t* __restrict__ A, int single, const uint8_t* __restrict__ bp,
-                                         int rb, int lane, RowOps<N, NG, BIAS>& o) {
+__device__ __forceinline__ void load_row(const uint8_t* __restrict__ A, const uint8_t* __restrict__ Alo,
+                                         const uint8_t* __restrict__ bp, int rb, int lane, RowOps<N, NG, BIAS>& o) {
 #pragma unroll
   for (int gi = 0; gi < NG; ++gi) {
     const int idx = ((rb * NG + gi) * 64 + lane) * 16;
     o.a[gi] = lds16(A + idx);
-    if constexpr (N::SPLIT) o.al[gi] = lds16(A + single + idx);
+    if constexpr (N::SPLIT) o.al[gi] = lds16(Alo + idx);
   }
   if constexpr (BIAS) {
 #pragma unroll
@@ -138,11 +138,22 @@ __device__ __forceinline__ void row_mfma(const RowOps<N, NG, BIAS>& o, const Act
 template <class N, int J, int KS>
 using FwdOps = RowOps<N, N::groups(KS), (J > 0)>;
 
-template <class N, int J, int KS>
-__device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, int lane, int rb,
-                                             FwdOps<N, J, KS>& o) {
-  const uint8_t* bp = wb + N::bias_off(J) + ((lane / 32) * 16) * 4 + rb * 128;
-  load_row<N, N::groups(KS), (J > 0)>(wb + N::fwdA_off(J), N::fwdA_single(J), bp, rb, lane, o);
+// Where the forward operands are read: kPacked, the packed layout at wb
+// (LDS or global); kHiStaged, the hi sections and biases staged at wb in the
+// fwd_hi_* layout, the lo sections read from the packed copy at wlo.
+enum FwdLayout { kPacked = 0, kHiStaged = 1 };
+
+template <class N, int J, int KS, int LAYOUT = kPacked>
+__device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
+                                             int lane, int rb, FwdOps<N, J, KS>& o) {
+  const int bo = ((lane / 32) * 16) * 4 + rb * 128;
+  if constexpr (LAYOUT == kHiStaged) {
+    load_row<N, N::groups(KS), (J > 0)>(wb + N::fwd_hi_off(J), wlo + N::fwdA_off(J) + N::fwdA_single(J),
+                                        wb + N::fwd_hi_bias(J) + bo, rb, lane, o);
+  } else {
+    const uint8_t* A = wb + N::fwdA_off(J);
+    load_row<N, N::groups(KS), (J > 0)>(A, A + N::fwdA_single(J), wb + N::bias_off(J) + bo, rb, lane, o);
+  }
 }
 
 // one dense layer on the matrix cores: acc[rb] = bias + W_j x, given the
@@ -151,9 +162,9 @@ __device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, int
 // rb+1 are requested before the products of row block rb, so their latency
 // overlaps the matrix cores' work; at most two row blocks' operands are in
 // flight (bounds register pressure).
-template <class N, int J, int KS>
-__device__ __forceinline__ void layer_fwd_from(const uint8_t* __restrict__ wb, int lane,
-                                               const Act<N, rup(KS, N::KGRP)>& B,
+template <class N, int J, int KS, int LAYOUT = kPacked>
+__device__ __forceinline__ void layer_fwd_from(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
+                                               int lane, const Act<N, rup(KS, N::KGRP)>& B,
                                                f32x16 (&acc)[N::frb(J)], const FwdOps<N, J, KS>& first) {
   constexpr int RB = N::frb(J);
   constexpr int NG = N::groups(KS);
@@ -162,7 +173,7 @@ __device__ __forceinline__ void layer_fwd_from(const uint8_t* __restrict__ wb, i
   ops[0] = first;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    if (rb + 1 < RB) fwd_row_load<N, J, KS>(wb, lane, rb + 1, ops[(rb + 1) & 1]);
+    if (rb + 1 < RB) fwd_row_load<N, J, KS, LAYOUT>(wb, wlo, lane, rb + 1, ops[(rb + 1) & 1]);
     const FwdOps<N, J, KS>& o = ops[rb & 1];
     f32x16 c;
     if constexpr (BIAS) {
@@ -182,13 +193,18 @@ __device__ __forceinline__ void layer_fwd_from(const uint8_t* __restrict__ wb, i
   }
 }
 
-template <class N, int J, int KS>
-__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
-                                          const Act<N, rup(KS, N::KGRP)>& B,
+template <class N, int J, int KS, int LAYOUT = kPacked>
+__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
+                                          int lane, const Act<N, rup(KS, N::KGRP)>& B,
                                           f32x16 (&acc)[N::frb(J)]) {
   FwdOps<N, J, KS> first;
-  fwd_row_load<N, J, KS>(wb, lane, 0, first);
-  layer_fwd_from<N, J, KS>(wb, lane, B, acc, first);
+  fwd_row_load<N, J, KS, LAYOUT>(wb, wlo, lane, 0, first);
+  layer_fwd_from<N, J, KS, LAYOUT>(wb, wlo, lane, B, acc, first);
+}
+template <class N, int J, int KS>
+__device__ __forceinline__ void layer_fwd(const uint8_t* __restrict__ wb, int lane,
+                                          const Act<N, rup(KS, N::KGRP)>& B, f32x16 (&acc)[N::frb(J)]) {
+  layer_fwd<N, J, KS, kPacked>(wb, wb, lane, B, acc);
 }
 
 // k-step s of a bfloat16 B operand from its 8 slot values, converted in pairs
