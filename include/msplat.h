@@ -57,8 +57,10 @@ typedef enum msplat_precision {
  * out_dim-4 feature channels (identity), composited like RGB.
  * Compiled shapes (pe_freqs, hidden_width, hidden_layers, out_dim):
  *   (4, 32, 2, 4), (6, 64, 3, 4), (6, 64, 3, 20), (6, 128, 4, 20).  Others:
- *   MSPLAT_E_UNSUPPORTED.  Networks wider than 64 read their weights from global
- *   memory and run the backward in two passes over ranges of layers.
+ *   MSPLAT_E_UNSUPPORTED.  For networks wider than 64 the forward keeps in LDS
+ *   what fits of the weights (all of them in BF16, the hi halves of the split
+ *   form), the backward reads them from global memory and runs in two passes
+ *   over ranges of layers.
  */
 typedef struct msplat_model {
   int32_t num_prims;     /* P >= 1 */
