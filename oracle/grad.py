@@ -29,13 +29,15 @@ def to_tensors(scene: dict, dtype=torch.float64, requires_grad=False) -> dict:
 
 def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
                    grad_rgb=None, grad_feat=None, target_rgb=None, chunk: int = 4096,
-                   grad_trans=None, ray_ids=None):
+                   grad_trans=None, ray_ids=None, centre=None):
     """Vector-Jacobian product of the render with upstream gradients.
 
     Either ``grad_rgb`` ([R,3], optionally ``grad_feat``) is given, giving
     L = sum(grad_rgb * rgb) + sum(grad_feat * feat), or ``target_rgb`` is
     given, giving the mean-squared error L = mean((rgb - target)^2) over all
     R x 3 values.  Rays are processed in chunks and gradients accumulated.
+    ``centre`` (per-ray virtual rays for tile order, as in ``render``) is
+    sliced with the rays; by default chunks start on packet boundaries.
     Returns (rgb, trans, feat, grads) with grads keyed like the scene.
     """
     prm = to_tensors(scene, requires_grad=True)
@@ -48,7 +50,8 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
         e = min(nr, s + chunk)
         out = render(prm["center"], prm["scale"], prm["quat"], prm["mlp"], o[s:e], d[s:e],
                      model, opts, ray_index_base=s,
-                     ray_ids=None if ray_ids is None else ray_ids[s:e])
+                     ray_ids=None if ray_ids is None else ray_ids[s:e],
+                     centre=None if centre is None else (centre[0][s:e], centre[1][s:e]))
         if target_rgb is not None:
             tgt = torch.from_numpy(np.asarray(target_rgb[s:e], np.float64))
             loss = ((out["rgb"] - tgt) ** 2).sum() / (3.0 * nr)

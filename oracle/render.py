@@ -21,6 +21,11 @@ DESIGN.md):
     thickness in alpha = 1 - exp(-sigma * Delta);
   * hits are composited one after the other (hit-major), sorted by the
     unclamped contact depth, ties broken by primitive index;
+  * tile order (option): every ray of a packet of 64 consecutive rays takes
+    the order of the contact depths along one virtual ray of the packet,
+    whose origin is the mean of the packet's origins and whose direction is
+    the normalised sum of its directions (for an 8x8 pixel tile of a pinhole
+    camera, the ray through the tile centre up to a second-order term);
   * early termination stops after the first sample whose transmittance falls
     below the threshold.
 """
@@ -36,7 +41,9 @@ import torch
 from .pcg import sample_offsets
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
-           "encode", "mlp_apply", "relu_noise", "relu_margin", "render"]
+           "encode", "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render"]
+
+PACKET = 64   # rays per packet (an 8x8 pixel tile)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -69,6 +76,7 @@ class Opts:
     jitter: int = 1                  # 1 = hashed stratified offsets, 0 = midpoints
     jitter_seed: int = 0
     background: Sequence[float] = (0.0, 0.0, 0.0)
+    order: int = 0                   # 0 = each ray's own contact depth; 1 = tile order
 
 
 def _where(cond, a, b):
@@ -206,26 +214,58 @@ def _softplus(o):
     return _where(pos, o + torch.log1p(torch.exp(-o)), torch.log1p(torch.exp(o)))
 
 
+def packet_centres(ray_o, ray_d, packet: int = PACKET):
+    """Virtual ray of every packet of ``packet`` consecutive rays (the last one
+    may be shorter), repeated for each of its rays: origin = mean of the
+    packet's origins, direction = normalised sum of its directions, (0, 0, 1)
+    if that sum vanishes.  The tile-order variant of the depth sort (Sec. 3.3,
+    after Eq. 2; App. on tile-based rendering) solves Eq. 1 along this ray.
+    Returns float64 numpy arrays ([R,3], [R,3])."""
+    o = np.asarray(ray_o, np.float64)
+    d = np.asarray(ray_d, np.float64)
+    oc = np.empty_like(o)
+    dc = np.empty_like(d)
+    for s in range(0, len(o), packet):
+        e = min(len(o), s + packet)
+        oc[s:e] = o[s:e].mean(0)
+        v = d[s:e].sum(0)
+        n = np.linalg.norm(v)
+        dc[s:e] = v / n if n > 0 else np.array([0.0, 0.0, 1.0])
+    return oc, dc
+
+
 def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
-           ray_index_base: int = 0, keep_samples: bool = False, ray_ids=None) -> dict:
+           ray_index_base: int = 0, keep_samples: bool = False, ray_ids=None,
+           centre=None) -> dict:
     """Render every ray (Sec. 3.3 front-to-back compositing over the depth-
     sorted hits, each hit sampled at K stratified points of its chord).
 
     Parameters are float64 (or complex128) tensors; rays are float64.
     ``ray_index_base`` offsets the ray index fed to the sample-offset hash, so a
     subset of a batch can be rendered with the batch's own offsets; ``ray_ids``
-    (one index per ray) overrides it for scattered subsets.
+    (one index per ray) overrides it for scattered subsets.  With
+    ``opts.order == 1`` hits are ordered along each ray's packet virtual ray:
+    ``centre`` = (origins, directions) per ray, by default
+    ``packet_centres(ray_o, ray_d)`` (rays given from a packet boundary).
     """
     dt = center.dtype
     nr = ray_o.shape[0]
     npr = center.shape[0]
     isx = intersect(ray_o, ray_d, center, scale, quat)
     hit = isx["hit"]
-    # --- depth order: ascending (t_c, primitive index) per ray ---
+    # --- depth order: ascending (key, primitive index) per ray, the key being
+    # the contact depth along the ray itself or along its packet's virtual ray
     rr, pp = torch.nonzero(hit, as_tuple=True)
     rr = rr.numpy()
     pp = pp.numpy()
-    tcr = isx["tc"].real.detach()[rr, pp].numpy() if len(rr) else np.zeros(0)
+    if opts.order == 1:
+        oc, dc = packet_centres(ray_o.real, ray_d.real) if centre is None else centre
+        key_all = intersect(torch.from_numpy(np.asarray(oc, np.float64)),
+                            torch.from_numpy(np.asarray(dc, np.float64)),
+                            center.real.detach(), scale.real.detach(), quat.real.detach())["tc"]
+    else:
+        key_all = isx["tc"]
+    tcr = key_all.real.detach()[rr, pp].numpy() if len(rr) else np.zeros(0)
     order = np.lexsort((pp, tcr, rr))
     rr, pp = rr[order], pp[order]
     nh = len(rr)

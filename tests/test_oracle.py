@@ -581,3 +581,118 @@ def test_relu_margin_zero_for_a_unit_exactly_at_its_switching_point():
     m = oracle.relu_margin(theta, x, model)
     assert m[9] == 0.0
     assert (np.delete(m, 9) > 0).all()
+
+
+# -------------------------------------------------------------- tile order --
+
+def _tilted(tan_t):
+    c = 1.0 / math.sqrt(1.0 + tan_t * tan_t)
+    return np.array([-tan_t * c, 0.0, c])
+
+
+def _two_sphere_tile_case():
+    """Spheres A at (0,0,5) and B at (0.1,0,5.02), radius 2, constant colours.
+    Along +z A's contact depth is smaller (5 < 5.02); along the ray e tilted
+    by atan 0.3 towards -x it is B's (t_B - t_A = -0.1 sin + 0.02 cos < 0).
+    Packet 0: 64 copies of e; packet 1: 63 rays along +z and e at lane 5;
+    packet 2 (ragged, 11 rays): e first, then +z rays."""
+    m = SMALL
+    ca, cb = np.array([0.9, 0.2, 0.1]), np.array([0.1, 0.3, 0.8])
+    sa, sb = 0.7, 1.3
+    sc = {"center": np.array([[0.0, 0.0, 5.0], [0.1, 0.0, 5.02]]),
+          "scale": np.full((2, 3), 2.0), "quat": np.array([[1.0, 0, 0, 0], [1.0, 0, 0, 0]]),
+          "mlp": np.stack([const_params(m, ca, sa), const_params(m, cb, sb)])}
+    e, z = _tilted(0.3), np.array([0.0, 0.0, 1.0])
+    d = np.concatenate([np.tile(e, (64, 1)), np.tile(z, (64, 1)), np.tile(z, (11, 1))])
+    d[64 + 5] = e
+    d[128] = e
+    o = np.zeros_like(d)
+    return sc, o, d, (ca, sa), (cb, sb)
+
+
+def test_packet_centres_are_mean_origin_and_normalised_direction_sum():
+    sc, o, d, _, _ = _two_sphere_tile_case()
+    o = o + np.arange(len(o))[:, None] * np.array([0.01, -0.02, 0.03])
+    oc, dc = oracle.packet_centres(o, d)
+    for s, e in [(0, 64), (64, 128), (128, len(o))]:
+        v = d[s:e].sum(0)
+        np.testing.assert_allclose(dc[s:e], np.broadcast_to(v / np.linalg.norm(v), (e - s, 3)), rtol=1e-15)
+        np.testing.assert_allclose(oc[s:e], np.broadcast_to(o[s:e].mean(0), (e - s, 3)), rtol=1e-15)
+    np.testing.assert_allclose(dc[0], _tilted(0.3), rtol=1e-15)
+
+
+def test_tile_order_composites_in_the_virtual_rays_depth_order():
+    """Closed form: a ray meeting constant primitives X then Y gives
+    alpha_X c_X + (1 - alpha_X) alpha_Y c_Y with alpha = 1 - exp(-sigma L)."""
+    sc, o, d, (ca, sa), (cb, sb) = _two_sphere_tile_case()
+    exact = render_np(sc, o, d, SMALL, oracle.Opts(samples_fixed=6, jitter=1, order=0))
+    tile = render_np(sc, o, d, SMALL, oracle.Opts(samples_fixed=6, jitter=1, order=1))
+
+    def alpha(i, r, sigma):
+        roots = chord(o[r], d[r], sc["center"][i], sc["scale"][i], sc["quat"][i])
+        return 1 - math.exp(-sigma * (roots[1] - max(roots[0], 0.0)))
+
+    def prims(out, r):
+        return list(out["prim"][out["ray_off"][r]:out["ray_off"][r + 1]])
+
+    for r in range(len(d)):
+        tilted = np.allclose(d[r], _tilted(0.3))
+        aa, ab = alpha(0, r, sa), alpha(1, r, sb)
+        a_first = aa * ca + (1 - aa) * ab * cb
+        b_first = ab * cb + (1 - ab) * aa * ca
+        # exact order follows the ray itself
+        assert prims(exact, r) == ([1, 0] if tilted else [0, 1])
+        np.testing.assert_allclose(exact["rgb"][r].numpy(), b_first if tilted else a_first, rtol=1e-12)
+        # tile order: packet 0's virtual ray is the tilted one, the others' are near +z
+        b_in_front = r < 64
+        assert prims(tile, r) == ([1, 0] if b_in_front else [0, 1])
+        np.testing.assert_allclose(tile["rgb"][r].numpy(), b_first if b_in_front else a_first, rtol=1e-12)
+        # hit sets, chords and transmittance do not depend on the order
+        np.testing.assert_allclose(float(tile["trans"][r]), float(exact["trans"][r]), rtol=1e-12)
+
+
+def test_tile_order_equals_exact_order_when_a_packets_rays_coincide():
+    cfg = synth.CONFIGS[0]
+    sc = synth.make_scene(cfg)
+    rng = np.random.default_rng(3)
+    cam = synth.make_camera(rng, 64, 64, cfg.camera_radius, cfg.fov_deg)
+    o, d, _ = synth.camera_rays(cam)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    opts = dict(samples_fixed=cfg.samples_fixed, jitter=1, jitter_seed=9)
+    full = render_np(sc, o, d, m, oracle.Opts(order=0, **opts))
+    multi = np.nonzero(np.diff(full["ray_off"]) >= 2)[0]
+    assert len(multi) >= 8
+    n = 64 * 7 + 13                       # ragged last packet
+    pick = np.repeat(multi[:: max(1, len(multi) // 8)][:8], 64)[:n]
+    o, d = o[pick], d[pick]
+    a = render_np(sc, o, d, m, oracle.Opts(order=0, **opts))
+    b = render_np(sc, o, d, m, oracle.Opts(order=1, **opts))
+    assert int(a["ray_off"][-1]) > n // 4
+    assert np.array_equal(a["prim"], b["prim"]) and np.array_equal(a["ray_off"], b["ray_off"])
+    np.testing.assert_array_equal(a["rgb"].numpy(), b["rgb"].numpy())
+
+
+def test_tile_order_keeps_every_rays_hit_set_and_sample_positions():
+    cfg = synth.CONFIGS[0]
+    sc = synth.make_scene(cfg)
+    cam = synth.make_camera(np.random.default_rng(4), 64, 64, cfg.camera_radius, cfg.fov_deg)
+    o, d, _ = synth.camera_rays(cam)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    opts = dict(samples_fixed=cfg.samples_fixed, jitter=0)
+    a = render_np(sc, o, d, m, oracle.Opts(order=0, **opts))
+    b = render_np(sc, o, d, m, oracle.Opts(order=1, **opts))
+    assert np.array_equal(a["ray_off"], b["ray_off"])
+    moved = 0
+    for r in range(len(o)):
+        s, e = a["ray_off"][r], a["ray_off"][r + 1]
+        pa, pb = a["prim"][s:e], b["prim"][s:e]
+        assert sorted(pa) == sorted(pb)
+        # same chord per (ray, primitive) whatever its rank
+        ta = dict(zip(pa, a["t_a"][s:e].numpy()))
+        tb = dict(zip(pb, b["t_a"][s:e].numpy()))
+        assert all(ta[p] == tb[p] for p in pa)
+        if e - s <= 1:
+            np.testing.assert_array_equal(a["rgb"][r].numpy(), b["rgb"][r].numpy())
+        moved += int(not np.array_equal(pa, pb))
+    # the packets are camera tiles: the orders differ on few rays only
+    assert moved <= 0.05 * len(o)
