@@ -83,6 +83,16 @@ typedef struct msplat_opts {
   int32_t jitter;           /* 0: bin midpoints; 1: hashed stratified offsets */
   uint32_t jitter_seed;
   float background[3];      /* added as T_final * background */
+  int32_t order;            /* depth order of a ray's hits (Sec. 3.3, after Eq. 2):
+                               0: contact depth along the ray itself (exact);
+                               1: tile order -- every ray of a packet of 64
+                               consecutive rays takes the order of the contact
+                               depths along one virtual ray of the packet (origin:
+                               mean of the packet's origins; direction: normalised
+                               sum of its directions, (0,0,1) if that sum is 0),
+                               ties broken by primitive index.  Meant for rays given
+                               as 8x8 pixel tiles; hit sets and sample positions are
+                               those of order 0, only the compositing order changes */
 } msplat_opts;
 
 /* Counters filled by the forward pass (read with msplat_get_stats). */
@@ -191,7 +201,8 @@ int msplat_debug_hits(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, int64_
  * only; not a product path).  Same arguments as msplat_render_forward with
  * float64 inputs and outputs; the workspace needs 256 bytes (*need_bytes).
  * The network is evaluated in float64 on the vector units; at most 48 hits
- * per ray are kept (MSPLAT_E_CAPACITY beyond that).
+ * per ray are kept (MSPLAT_E_CAPACITY beyond that).  Exact order only
+ * (opts->order == 1: MSPLAT_E_UNSUPPORTED).
  * decisions [R] (uint32, may be NULL) receives a hash of each ray's discrete
  * decisions: the depth-ordered primitives, the samples evaluated, every open
  * ReLU gate and the termination cut.  Two calls whose hashes agree for a ray

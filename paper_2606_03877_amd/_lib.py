@@ -36,7 +36,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("samples_fixed", ctypes.c_int32), ("samples_min", ctypes.c_int32),
                 ("samples_max", ctypes.c_int32), ("samples_per_unit", ctypes.c_float),
                 ("t_stop", ctypes.c_float), ("jitter", ctypes.c_int32),
-                ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3)]
+                ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3),
+                ("order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

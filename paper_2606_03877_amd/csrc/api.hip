@@ -201,6 +201,7 @@ bool opts_ok(const msplat_opts* o) {
     if (!(o->samples_per_unit > 0.f)) return false;
   }
   if (!(o->t_stop >= 0.f && o->t_stop < 1.f)) return false;
+  if (o->order != 0 && o->order != 1) return false;
   return true;
 }
 
@@ -480,7 +481,7 @@ int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const mspl
   if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
   if (R > 0 && (!ray_o || !ray_d || !rgb || !trans)) return MSPLAT_E_INVALID;
   if (n.NOUT > 4 && R > 0 && !feat) return MSPLAT_E_INVALID;
-  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  if (!mlp_supported(n) || o->order != 0) return MSPLAT_E_UNSUPPORTED;
   if (need_bytes) *need_bytes = 256;
   if (ws_bytes < 256) return MSPLAT_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;

@@ -221,6 +221,7 @@ __device__ HitDF hit_test_df(const float* __restrict__ center, const float* __re
 struct Cone {
   float ox, oy, oz, dx, dy, dz, cos_t, sin_t, rho;
   bool all;
+  float3 vo, vd;   // the packet's virtual ray: mean origin, normalised direction sum
 };
 
 __device__ __forceinline__ Cone packet_cone(bool valid, float3 o, float3 d) {
@@ -235,6 +236,8 @@ __device__ __forceinline__ Cone packet_cone(bool valid, float3 o, float3 d) {
   float ax = wave_sum(valid ? d.x : 0.f), ay = wave_sum(valid ? d.y : 0.f),
         az = wave_sum(valid ? d.z : 0.f);
   float an = sqrtf(ax * ax + ay * ay + az * az);
+  c.vo = make_float3(c.ox, c.oy, c.oz);
+  c.vd = an > 0.f ? make_float3(ax / an, ay / an, az / an) : make_float3(0.f, 0.f, 1.f);
   c.all = true;
   c.cos_t = -1.f;
   c.sin_t = 0.f;
@@ -481,6 +484,138 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
   }
 }
 
+// ----------------------------------------------------------- tile order --
+
+// contact depth of a primitive along the packet's virtual ray (vo, vd): the
+// unclamped minimiser of Eq. 1, t = (M vd).(M (mu - vo)) / |M vd|^2, in
+// float32.  The sort key of tile order (Sec. 3.3, after Eq. 2), shared by the
+// packet's rays.
+__device__ __forceinline__ float virtual_depth(const float* __restrict__ g, float3 vo, float3 vd) {
+  const float* M = g + G_M_HI;
+  const float v[3] = {g[G_MU] - vo.x, g[G_MU + 1] - vo.y, g[G_MU + 2] - vo.z};
+  const float dd[3] = {vd.x, vd.y, vd.z};
+  float em = 0.f, ee = 0.f;
+  for (int r = 0; r < 3; ++r) {
+    const float m = M[3 * r] * v[0] + M[3 * r + 1] * v[1] + M[3 * r + 2] * v[2];
+    const float e = M[3 * r] * dd[0] + M[3 * r + 1] * dd[1] + M[3 * r + 2] * dd[2];
+    em += e * m;
+    ee += e * e;
+  }
+  return em / ee;
+}
+
+// (key, primitive) as one unsigned integer whose order is the lexicographic
+// order of (key, primitive) for non-NaN keys (-0 is taken as +0)
+__device__ __forceinline__ uint64_t kp_pack(float key, int p) {
+  uint32_t u = __float_as_uint(key + 0.f);
+  u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)u << 32) | (uint32_t)p;
+}
+
+constexpr int kTileNE = 8;                  // candidates held per lane
+constexpr int kTileMax = kTileNE * kWave;   // candidates a packet sorts in registers
+
+// a packet's candidates as packed (key, primitive), element e in lane e % 64
+// of register e / 64; unused elements hold the largest value
+struct TileList {
+  uint64_t v[kTileNE];
+};
+
+// bit position of the i-th (from 0) set bit of m; i < popcount(m)
+__device__ __forceinline__ int nth_bit(uint64_t m, int i) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const int c = __popcll(m & ((1ull << w) - 1ull));
+    if (i >= c) {
+      i -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// gather the packet's candidates with their keys, in primitive order (the
+// culling test of the hit passes); false if there are more than kTileMax
+__device__ bool tile_collect(const Cone& cone, const float* __restrict__ geo, int P, int lane, TileList& t,
+                             int& nc) {
+#pragma unroll
+  for (int r = 0; r < kTileNE; ++r) t.v[r] = ~0ull;
+  nc = 0;
+  for (int base = 0; base < P; base += kWave) {
+    const int pl = base + lane;
+    bool cand = false;
+    uint64_t kv = 0;
+    if (pl < P) {
+      const float* gp = geo + (int64_t)pl * kGeoStride;
+      cand = cone_may_hit(cone, gp[G_MU], gp[G_MU + 1], gp[G_MU + 2], gp[G_RAD]);
+      if (cand) kv = kp_pack(virtual_depth(gp, cone.vo, cone.vd), pl);
+    }
+    const uint64_t mask = __ballot(cand);
+    const int cnt = __popcll(mask);
+    if (cnt == 0) continue;
+    if (nc + cnt > kTileMax) return false;
+    // element nc + i of the list takes the chunk's i-th candidate lane
+#pragma unroll
+    for (int r = 0; r < kTileNE; ++r) {
+      if ((r + 1) * kWave <= nc || r * kWave >= nc + cnt) continue;   // (wave-uniform)
+      const int i = r * kWave + lane - nc;
+      const bool mine = i >= 0 && i < cnt;
+      const uint64_t x = __shfl(kv, nth_bit(mask, mine ? i : 0), kWave);
+      if (mine) t.v[r] = x;
+    }
+    nc += cnt;
+  }
+  return true;
+}
+
+// ascending bitonic sort of the first 64 NR elements
+template <int NR>
+__device__ __forceinline__ void tile_sort(TileList& t, int lane) {
+  for (int kk = 2; kk <= NR * kWave; kk <<= 1) {
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= kWave) {
+        // partner in the same lane, register r ^ (j / 64)
+        const int D = j / kWave;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+#pragma unroll
+          for (int q = r + 1; q < NR; ++q) {
+            if ((r ^ q) != D) continue;
+            const bool asc = ((r * kWave + lane) & kk) == 0;
+            const uint64_t a = t.v[r], b = t.v[q];
+            const bool sw = asc ? (b < a) : (a < b);
+            t.v[r] = sw ? b : a;
+            t.v[q] = sw ? a : b;
+          }
+        }
+      } else {
+        // partner in lane ^ j: the lower lane keeps the smaller element of an
+        // ascending run, the larger of a descending one
+        const bool lower = (lane & j) == 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const uint64_t x = __shfl_xor(t.v[r], j, kWave);
+          const bool asc = ((r * kWave + lane) & kk) == 0;
+          const bool take = (lower == asc) ? (x < t.v[r]) : (t.v[r] < x);
+          if (take) t.v[r] = x;
+        }
+      }
+    }
+  }
+}
+
+// primitive of list element i (wave-uniform i)
+__device__ __forceinline__ int tile_prim(const TileList& t, int i) {
+  const int r = i / kWave;
+  uint32_t v = (uint32_t)t.v[0];
+#pragma unroll
+  for (int q = 1; q < kTileNE; ++q)
+    if (r == q) v = (uint32_t)t.v[q];
+  return (int)__builtin_amdgcn_readlane(v, i % kWave);
+}
+
 // ----------------------------------------------------------- fill kernel --
 
 // strict weak order on (t_c, prim) with double-float recomputation of close keys
@@ -496,6 +631,7 @@ __device__ __forceinline__ bool key_less(float ahi, float alo, int ap, float bhi
   return ap < bp;
 }
 
+template <bool TILE>
 __global__ __launch_bounds__(256) void bin_fill_kernel(
     const float* __restrict__ ray_o, const float* __restrict__ ray_d,
     const float* __restrict__ center, const float* __restrict__ scale,
@@ -511,8 +647,52 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
   Cone cone = packet_cone(valid, o, d);
   int64_t off = valid ? ws.ray_off[ray] : 0;
   int n = 0;
-  // pass 1: unsorted hits (primitive order) with their decided K, clip flag, eta
-  for (int base = 0; base < P; base += kWave) {
+  // hit test of this lane's ray against primitive p (wave-uniform); a hit is
+  // appended to the ray's segment with its decided K, clip flag and eta
+  auto test_append = [&](int p) __attribute__((always_inline)) {
+    if (!valid) return;
+    const float* gp = geo + (int64_t)p * kGeoStride;
+    int K = 0;
+    HitF h = hit_test_f32(gp, o, d, opt, &K);
+    bool hit = h.hit;
+    bool clipped = h.clipped;
+    float eta = h.eta;
+    if (h.uncertain) {
+      HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
+      hit = hd.hit;
+      K = hd.K;
+      clipped = hd.clipped;
+      eta = hd.eta.hi;
+    }
+    if (hit) {
+      int64_t j = off + n;
+      ws.hit_prim[j] = p;
+      ws.hit_tc_hi[j] = h.tc_hi;
+      ws.hit_tc_lo[j] = h.tc_lo;
+      ws.hit_k[j] = clipped ? -K : K;
+      ws.hit_eta[j] = eta;
+      ++n;
+    }
+  };
+  // tile order: one sort of the packet's candidates by their depth along the
+  // virtual ray, then every ray tests them in that order, so its hits come
+  // out sorted (a packet with more candidates than the registers hold falls
+  // back to the per-ray sort below, on the same keys)
+  bool in_order = false;
+  if constexpr (TILE) {
+    TileList tl;
+    int nc = 0;
+    if (tile_collect(cone, geo, P, lane, tl, nc)) {
+      if (nc <= kWave) tile_sort<1>(tl, lane);
+      else if (nc <= 2 * kWave) tile_sort<2>(tl, lane);
+      else if (nc <= 4 * kWave) tile_sort<4>(tl, lane);
+      else tile_sort<8>(tl, lane);
+      for (int i = 0; i < nc; ++i) test_append(tile_prim(tl, i));
+      in_order = true;
+    }
+  }
+  // pass 1: unsorted hits (primitive order)
+  for (int base = 0; !in_order && base < P; base += kWave) {
     int pl = base + lane;
     bool cand = false;
     if (pl < P) {
@@ -523,45 +703,29 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
     while (mask) {
       int bit = __builtin_ctzll(mask);
       mask &= mask - 1;
-      int p = __builtin_amdgcn_readfirstlane(base + bit);
-      const float* gp = geo + (int64_t)p * kGeoStride;
-      if (!valid) continue;
-      int K = 0;
-      HitF h = hit_test_f32(gp, o, d, opt, &K);
-      bool hit = h.hit;
-      bool clipped = h.clipped;
-      float eta = h.eta;
-      if (h.uncertain) {
-        HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
-        hit = hd.hit;
-        K = hd.K;
-        clipped = hd.clipped;
-        eta = hd.eta.hi;
-      }
-      if (hit) {
-        int64_t j = off + n;
-        ws.hit_prim[j] = p;
-        ws.hit_tc_hi[j] = h.tc_hi;
-        ws.hit_tc_lo[j] = h.tc_lo;
-        ws.hit_k[j] = clipped ? -K : K;
-        ws.hit_eta[j] = eta;
-        ++n;
-      }
+      test_append(__builtin_amdgcn_readfirstlane(base + bit));
     }
   }
   // (lanes of rays past the end have n = 0 and stay for the wave-wide steps below)
-  // pass 2: insertion sort of this ray's segment by (t_c, prim)
-  for (int i = 1; i < n; ++i) {
+  // pass 2: insertion sort of this ray's segment by (t_c, prim), or in tile
+  // order by (virtual-ray depth, prim)
+  for (int i = 1; !in_order && i < n; ++i) {
     int64_t ji = off + i;
     int p = ws.hit_prim[ji];
     float th = ws.hit_tc_hi[ji], tl = ws.hit_tc_lo[ji], et = ws.hit_eta[ji];
+    uint64_t vk = 0;
+    if constexpr (TILE) vk = kp_pack(virtual_depth(geo + (int64_t)p * kGeoStride, cone.vo, cone.vd), p);
     int kk = ws.hit_k[ji];
     int j = i - 1;
     while (j >= 0) {
       int64_t jj = off + j;
       int pj = ws.hit_prim[jj];
-      if (!key_less(th, tl, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt))
-        break;
+      bool before;
+      if constexpr (TILE)
+        before = vk < kp_pack(virtual_depth(geo + (int64_t)pj * kGeoStride, cone.vo, cone.vd), pj);
+      else
+        before = key_less(th, tl, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt);
+      if (!before) break;
       ws.hit_prim[jj + 1] = pj;
       ws.hit_tc_hi[jj + 1] = ws.hit_tc_hi[jj];
       ws.hit_tc_lo[jj + 1] = ws.hit_tc_lo[jj];
@@ -970,8 +1134,12 @@ hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float*
                            const float* center, const float* scale, const float* quat, int64_t R,
                            int P, const msplat_opts& o, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bin_fill_kernel, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
-                     scale, quat, (const float*)ws.geo, R, P, o, ws);
+  if (o.order == 1)
+    hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
+                       scale, quat, (const float*)ws.geo, R, P, o, ws);
+  else
+    hipLaunchKernelGGL(bin_fill_kernel<false>, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
+                       scale, quat, (const float*)ws.geo, R, P, o, ws);
   return hipGetLastError();
 }
 

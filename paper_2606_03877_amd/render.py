@@ -50,12 +50,13 @@ class RenderOpts:
     jitter: int = 1
     jitter_seed: int = 0
     background: Sequence[float] = (0.0, 0.0, 0.0)
+    order: int = 0   # 0: each ray's own contact depth; 1: tile order (packet virtual ray)
 
     def c(self) -> _lib.Opts:
         bg = (ctypes.c_float * 3)(*[float(b) for b in self.background])
         return _lib.Opts(self.samples_fixed, self.samples_min, self.samples_max,
                          float(self.samples_per_unit), float(self.t_stop), self.jitter,
-                         self.jitter_seed & 0xFFFFFFFF, bg)
+                         self.jitter_seed & 0xFFFFFFFF, bg, self.order)
 
 
 def _p(t: Optional[torch.Tensor]):

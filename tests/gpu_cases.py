@@ -24,19 +24,19 @@ def spec_of(cfg, precision):
                    precision)
 
 
-def opts_of(cfg, t_stop=None, jitter_seed=1234):
+def opts_of(cfg, t_stop=None, jitter_seed=1234, order=0):
     from paper_2606_03877_amd import RenderOpts
     return RenderOpts(samples_fixed=cfg.samples_fixed, samples_min=cfg.samples_min,
                       samples_max=cfg.samples_max, samples_per_unit=cfg.samples_per_unit,
                       t_stop=cfg.t_stop if t_stop is None else t_stop, jitter=cfg.jitter,
-                      jitter_seed=jitter_seed)
+                      jitter_seed=jitter_seed, order=order)
 
 
 def oracle_opts(o):
     return oracle.Opts(samples_fixed=o.samples_fixed, samples_min=o.samples_min,
                        samples_max=o.samples_max, samples_per_unit=o.samples_per_unit,
                        t_stop=o.t_stop, jitter=o.jitter, jitter_seed=o.jitter_seed,
-                       background=tuple(o.background))
+                       background=tuple(o.background), order=o.order)
 
 
 def oracle_model(cfg):
@@ -71,10 +71,11 @@ def to_dev(sc, o, d):
 RELU_AMBIGUOUS = {"fp32": 1e-6, "bf16x3": 5e-5, "bf16": 1e-2}
 
 
-def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096, margins=False):
-    """Oracle forward in chunks; with ``margins`` also the smallest ReLU
-    margin over each ray's samples (``relu_margin``, inf for rays without
-    samples)."""
+def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096, margins=False, centre=None):
+    """Oracle forward in chunks (of whole 64-ray packets); with ``margins``
+    also the smallest ReLU margin over each ray's samples (``relu_margin``, inf
+    for rays without samples).  ``centre`` gives tile order's per-ray virtual
+    rays when the rays are a scattered subset of a batch."""
     cfg = synth.CONFIGS[ci]
     p = oracle.to_tensors(sc)
     oo = oracle_opts(opts)
@@ -85,7 +86,8 @@ def oracle_render(ci, sc, o, d, opts, ray_ids=None, chunk=4096, margins=False):
         out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"],
                             torch.from_numpy(o[s:e].astype(np.float64)),
                             torch.from_numpy(d[s:e].astype(np.float64)), oracle_model(cfg), oo,
-                            ray_index_base=s, ray_ids=ids, keep_samples=margins)
+                            ray_index_base=s, ray_ids=ids, keep_samples=margins,
+                            centre=None if centre is None else (centre[0][s:e], centre[1][s:e]))
         if margins:
             m = np.full(e - s, np.inf)
             smp = out["samples"]
