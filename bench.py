@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -54,14 +55,15 @@ def mlp_flops_per_sample(cfg) -> int:
     return sum(2 * i * o for i, o in synth.layer_dims(cfg))
 
 
-def setup(cfg, precision, t_stop=None):
+def setup(cfg, precision, t_stop=None, order=0):
     import torch
     import synth
     from paper_2606_03877_amd import NetSpec, RenderOpts, Renderer
     spec = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim, precision)
     opts = RenderOpts(samples_fixed=cfg.samples_fixed, samples_min=cfg.samples_min,
                       samples_max=cfg.samples_max, samples_per_unit=cfg.samples_per_unit,
-                      t_stop=cfg.t_stop if t_stop is None else t_stop, jitter=cfg.jitter, jitter_seed=7)
+                      t_stop=cfg.t_stop if t_stop is None else t_stop, jitter=cfg.jitter, jitter_seed=7,
+                      order=order)
     return Renderer(spec, opts), opts
 
 
@@ -75,11 +77,12 @@ def device_inputs(cfg):
     return sc, o, d, prm, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
 
 
-def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True):
-    """Time fwd+bwd training steps and forward-only renders of one precision."""
+def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, order=0, want_hits=False):
+    """Time fwd+bwd training steps and forward-only renders of one precision
+    (and hit order: 0 exact, 1 tile order)."""
     import torch
     from paper_2606_03877_amd import render, msplat_profile_enable, msplat_profile_read
-    r, opts = setup(cfg, precision)
+    r, opts = setup(cfg, precision, order=order)
     leaf = {k: v.clone().requires_grad_(True) for k, v in prm.items()}
 
     def step():
@@ -115,7 +118,9 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True):
         f1 = time.perf_counter()
     stats = r.stats(ws)
     R = ro.shape[0]
+    hits = r.hits(ws, R)[:2] if want_hits else None
     return {
+        "hits": hits,
         "fwdbwd_ms": 1e3 * (t1 - t0) / steps,
         "fwd_ms": 1e3 * (f1 - f0) / steps,
         "fwdbwd_rays_per_s": R * steps / (t1 - t0),
@@ -135,10 +140,14 @@ def oracle_check(cfg, sc, o, d, rgb_gpu, opts, n=256, seed=11):
     m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
     oo = oracle.Opts(samples_fixed=opts.samples_fixed, samples_min=opts.samples_min,
                      samples_max=opts.samples_max, samples_per_unit=opts.samples_per_unit,
-                     t_stop=opts.t_stop, jitter=opts.jitter, jitter_seed=opts.jitter_seed)
+                     t_stop=opts.t_stop, jitter=opts.jitter, jitter_seed=opts.jitter_seed, order=opts.order)
+    centre = None
+    if opts.order == 1:
+        oc, dc = oracle.packet_centres(o, d)
+        centre = (oc[idx], dc[idx])
     out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"],
                         torch.from_numpy(o[idx].astype(np.float64)),
-                        torch.from_numpy(d[idx].astype(np.float64)), m, oo, ray_ids=idx)
+                        torch.from_numpy(d[idx].astype(np.float64)), m, oo, ray_ids=idx, centre=centre)
     g = rgb_gpu.detach().cpu().numpy()[idx]
     return float(np.abs(g - out["rgb"].numpy()).max())
 
@@ -223,6 +232,7 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tile", action="store_true", help="skip the tile-order leg")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (reference kernel "
@@ -261,7 +271,7 @@ def main():
     # inference form; float32 is the reference form
     MAIN = "bf16x3"
     legs = {}
-    legs[MAIN] = run_leg(cfg, MAIN, prm, ro, rd, target, args.steps, args.warmup)
+    legs[MAIN] = run_leg(cfg, MAIN, prm, ro, rd, target, args.steps, args.warmup, want_hits=not args.no_tile)
     print(f"# {MAIN} fwd+bwd {legs[MAIN]['fwdbwd_ms']:.3f} ms fwd {legs[MAIN]['fwd_ms']:.3f} ms",
           file=sys.stderr, flush=True)
     extra = ["bf16"] + ([] if args.no_fp32 else ["fp32"])
@@ -272,6 +282,30 @@ def main():
 
     _, opts = setup(cfg, MAIN)
     errs = {k: oracle_check(cfg, sc, o, d, v["rgb"], opts) for k, v in legs.items()}
+
+    # tile order (the hits of every 64-ray packet in the order of their depths
+    # along the packet's virtual ray): speed, and the image against exact order
+    tile = None
+    if not args.no_tile:
+        tl = run_leg(cfg, MAIN, prm, ro, rd, target, max(3, args.steps // 2), 1, order=1, want_hits=True)
+        print(f"# {MAIN} tile order fwd+bwd {tl['fwdbwd_ms']:.3f} ms fwd {tl['fwd_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+        diff = (tl["rgb"] - legs[MAIN]["rgb"]).float()
+        mse = float((diff ** 2).mean())
+        (eo, ep), (to_, tp) = legs[MAIN]["hits"], tl["hits"]
+        assert np.array_equal(eo, to_)
+        moved = np.zeros(R, bool)
+        dh = np.nonzero(ep != tp)[0]
+        moved[np.searchsorted(eo, dh, side="right") - 1] = True
+        bf = {k: v[0] / v[1] for k, v in tl["stages"].items() if k == "bin_fill" and v[1] > 0}
+        be = {k: v[0] / v[1] for k, v in legs[MAIN]["stages"].items() if k == "bin_fill" and v[1] > 0}
+        tile = {"fwd_ms": tl["fwd_ms"], "fwdbwd_ms": tl["fwdbwd_ms"],
+                "fwdbwd_speedup_vs_exact": legs[MAIN]["fwdbwd_ms"] / tl["fwdbwd_ms"],
+                "bin_fill_ms": bf.get("bin_fill"), "bin_fill_ms_exact": be.get("bin_fill"),
+                "rays_reordered": int(moved.sum()),
+                "rgb_max_diff_vs_exact": float(diff.abs().max()),
+                "psnr_vs_exact_db": (10.0 * math.log10(1.0 / mse)) if mse > 0 else None,
+                "rgb_max_err_vs_fp64": oracle_check(cfg, sc, o, d, tl["rgb"], setup(cfg, MAIN, order=1)[1])}
 
     # dominant kernel of the training step and its roofline
     b = legs[MAIN]
@@ -318,6 +352,7 @@ def main():
         "roofline": roof,
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "cpu_baseline": cpu,
+        "tile_order": tile,
     }
     out["legs"] = {k: {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"],
                        "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
