@@ -5,10 +5,11 @@ benchmark's cpu_baseline leg.  The product path (paper_2606_03877_amd) never
 imports it and shares no code with it.
 """
 from .render import (Model, Opts, quat_to_rotmat, local_frame, intersect, encode, mlp_apply,
-                     relu_noise, relu_margin, packet_centres, render)
+                     relu_noise, relu_margin, packet_centres, render, TETRA,
+                     slot_gates)
 from .pcg import pcg_hash, sample_offsets
 from .grad import loss_and_grads, complex_step, to_tensors
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect", "encode",
-           "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render", "pcg_hash", "sample_offsets", "loss_and_grads",
+           "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render", "TETRA", "slot_gates", "pcg_hash", "sample_offsets", "loss_and_grads",
            "complex_step", "to_tensors"]

@@ -19,7 +19,9 @@ __all__ = ["to_tensors", "loss_and_grads", "complex_step"]
 
 def to_tensors(scene: dict, dtype=torch.float64, requires_grad=False) -> dict:
     out = {}
-    for k in ("center", "scale", "quat", "mlp"):
+    for k in ("center", "scale", "quat", "mlp", "slots"):
+        if k not in scene:
+            continue
         t = torch.from_numpy(np.asarray(scene[k], dtype=np.float64)).to(dtype)
         if requires_grad:
             t.requires_grad_(True)
@@ -29,7 +31,7 @@ def to_tensors(scene: dict, dtype=torch.float64, requires_grad=False) -> dict:
 
 def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
                    grad_rgb=None, grad_feat=None, target_rgb=None, chunk: int = 4096,
-                   grad_trans=None, ray_ids=None, centre=None):
+                   grad_trans=None, ray_ids=None, centre=None, grad_slot=None):
     """Vector-Jacobian product of the render with upstream gradients.
 
     Either ``grad_rgb`` ([R,3], optionally ``grad_feat``) is given, giving
@@ -37,7 +39,9 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
     given, giving the mean-squared error L = mean((rgb - target)^2) over all
     R x 3 values.  Rays are processed in chunks and gradients accumulated.
     ``centre`` (per-ray virtual rays for tile order, as in ``render``) is
-    sliced with the rays; by default chunks start on packet boundaries.
+    sliced with the rays; by default chunks start on packet boundaries.  A
+    scene with ``slots`` renders slot features; ``grad_slot`` [R, C] adds
+    sum(grad_slot * slot_feat) to the loss.
     Returns (rgb, trans, feat, grads) with grads keyed like the scene.
     """
     prm = to_tensors(scene, requires_grad=True)
@@ -51,7 +55,8 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
         out = render(prm["center"], prm["scale"], prm["quat"], prm["mlp"], o[s:e], d[s:e],
                      model, opts, ray_index_base=s,
                      ray_ids=None if ray_ids is None else ray_ids[s:e],
-                     centre=None if centre is None else (centre[0][s:e], centre[1][s:e]))
+                     centre=None if centre is None else (centre[0][s:e], centre[1][s:e]),
+                     slots=prm.get("slots"))
         if target_rgb is not None:
             tgt = torch.from_numpy(np.asarray(target_rgb[s:e], np.float64))
             loss = ((out["rgb"] - tgt) ** 2).sum() / (3.0 * nr)
@@ -64,6 +69,9 @@ def loss_and_grads(scene: dict, ray_o, ray_d, model: Model, opts: Opts,
             if grad_trans is not None:
                 gt = torch.from_numpy(np.asarray(grad_trans[s:e], np.float64))
                 loss = loss + (out["trans"] * gt).sum()
+            if grad_slot is not None:
+                gs = torch.from_numpy(np.asarray(grad_slot[s:e], np.float64))
+                loss = loss + (out["slot_feat"] * gs).sum()
         if loss.requires_grad:
             loss.backward()
         loss_total += float(loss.detach())

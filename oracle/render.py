@@ -27,7 +27,14 @@ DESIGN.md):
     the normalised sum of its directions (for an 8x8 pixel tile of a pinhole
     camera, the ray through the tile centre up to a second-order term);
   * early termination stops after the first sample whose transmittance falls
-    below the threshold.
+    below the threshold;
+  * slot features (option): the local offset u of a hit is taken at the
+    unclamped contact point (u = -p_c; the paper's clamp moves the point to the
+    ray origin only when the camera is inside the support), the clip to the
+    unit cube is inactive for a hit (|p_c| < 1), the directional frame is the
+    regular tetrahedron (1,1,1), (1,-1,-1), (-1,1,-1), (-1,-1,1) over sqrt 3,
+    and a hit's feature is composited with the hit's total volumetric weight
+    (the sum of its samples' weights).
 """
 from __future__ import annotations
 
@@ -41,7 +48,8 @@ import torch
 from .pcg import sample_offsets
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
-           "encode", "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render"]
+           "encode", "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render",
+           "TETRA", "slot_gates"]
 
 PACKET = 64   # rays per packet (an 8x8 pixel tile)
 
@@ -214,6 +222,18 @@ def _softplus(o):
     return _where(pos, o + torch.log1p(torch.exp(-o)), torch.log1p(torch.exp(o)))
 
 
+TETRA = np.array([[1.0, 1.0, 1.0], [1.0, -1.0, -1.0], [-1.0, 1.0, -1.0], [-1.0, -1.0, 1.0]]) / math.sqrt(3.0)
+
+
+def slot_gates(u: torch.Tensor) -> torch.Tensor:
+    """g_k = softmax_k(a_k . u) over the four directions of the tetrahedral
+    frame (Sec. 3.4, the feature-embedding equation); u [..., 3] -> [..., 4]."""
+    s = u @ torch.from_numpy(TETRA.T).to(u.dtype)
+    s = s - s.real.max(-1, keepdim=True).values.detach()
+    e = torch.exp(s)
+    return e / e.sum(-1, keepdim=True)
+
+
 def packet_centres(ray_o, ray_d, packet: int = PACKET):
     """Virtual ray of every packet of ``packet`` consecutive rays (the last one
     may be shorter), repeated for each of its rays: origin = mean of the
@@ -236,7 +256,7 @@ def packet_centres(ray_o, ray_d, packet: int = PACKET):
 
 def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
            ray_index_base: int = 0, keep_samples: bool = False, ray_ids=None,
-           centre=None) -> dict:
+           centre=None, slots=None) -> dict:
     """Render every ray (Sec. 3.3 front-to-back compositing over the depth-
     sorted hits, each hit sampled at K stratified points of its chord).
 
@@ -247,6 +267,10 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     ``opts.order == 1`` hits are ordered along each ray's packet virtual ray:
     ``centre`` = (origins, directions) per ray, by default
     ``packet_centres(ray_o, ray_d)`` (rays given from a packet boundary).
+    With ``slots`` ([P, 4, C] slot embeddings) the result also holds
+    ``slot_feat`` [R, C]: every hit's feature f = sum_k g_k e_k with gates
+    g = slot_gates(u) of its local offset u = -p_c, composited with the hit's
+    total volumetric weight (Sec. 3.4, F = sum_i T_i alpha_i f_i).
     """
     dt = center.dtype
     nr = ray_o.shape[0]
@@ -329,8 +353,11 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     bg = torch.tensor(list(opts.background), dtype=dt)
     if smax == 0:
         rgb = torch.zeros((nr, 3), dtype=dt) + bg
-        return _pack(rgb, torch.ones(nr, dtype=dt), torch.zeros((nr, cf), dtype=dt),
-                     np.zeros(nr, np.int64), ray_off, pp, tc, eta, ta, tb, kh, isx, None)
+        out = _pack(rgb, torch.ones(nr, dtype=dt), torch.zeros((nr, cf), dtype=dt),
+                    np.zeros(nr, np.int64), ray_off, pp, tc, eta, ta, tb, kh, isx, None)
+        if slots is not None:
+            out["slot_feat"] = torch.zeros((nr, slots.shape[-1]), dtype=dt)
+        return out
     tau_pad = torch.zeros((nr, smax), dtype=dt)
     idx2 = (torch.from_numpy(sray), torch.from_numpy(pos))
     tau_pad = tau_pad.index_put(idx2, tau)
@@ -356,6 +383,16 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     else:
         fout = torch.zeros((nr, 0), dtype=dt)
     n_used = used.sum(1).numpy()
+    slot_feat = None
+    if slots is not None:
+        # the hit's weight: the sum of its samples' compositing weights
+        w_hit = torch.zeros(nh, dtype=dt).index_add(0, hs_t, w[idx2])
+        u_loc = -(ol + tc[:, None] * dl)                   # -p_c, inside the unit ball
+        assert nh == 0 or float(u_loc.real.detach().abs().max()) < 1.0
+        g = slot_gates(u_loc)                               # [nh, 4]
+        f_hit = (g[:, :, None] * slots[pp_t]).sum(1)        # [nh, C]
+        slot_feat = torch.zeros((nr, slots.shape[-1]), dtype=dt).index_add(
+            0, rr_t, w_hit[:, None] * f_hit)
     samples = None
     if keep_samples:
         margin = np.full(len(hs), np.inf)
@@ -364,7 +401,10 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
             margin[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model)
         samples = {"hit": hs, "k": kk, "u": u, "t": tk, "p": pk, "c": col, "sigma": sig,
                    "f": feat, "tau": tau, "ray": sray, "relu_margin": margin}
-    return _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples)
+    out = _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples)
+    if slot_feat is not None:
+        out["slot_feat"] = slot_feat
+    return out
 
 
 def _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples):

@@ -696,3 +696,122 @@ def test_tile_order_keeps_every_rays_hit_set_and_sample_positions():
         moved += int(not np.array_equal(pa, pb))
     # the packets are camera tiles: the orders differ on few rays only
     assert moved <= 0.05 * len(o)
+
+
+# ----------------------------------------------------------- slot features --
+
+def _ray_to_local_foot(mu, s, q, foot_local, d_local, back=6.0):
+    """World ray whose closest approach to the primitive, measured in its
+    scale-normalised frame, is the local point ``foot_local`` (d_local must be
+    orthogonal to it): the local line foot + t d_local mapped to the world."""
+    r = scipy_rot(q)
+    to_world = r @ np.diag(s)
+    x = np.asarray(mu) + to_world @ np.asarray(foot_local)
+    d = to_world @ np.asarray(d_local)
+    d /= np.linalg.norm(d)
+    return x - back * d, d
+
+
+def test_equal_slots_give_opacity_times_embedding():
+    rng = np.random.default_rng(21)
+    mu, s, q = [0.1, -0.2, 0.3], [0.3, 0.15, 0.4], rng.standard_normal(4)
+    sc = _one_prim_scene(SMALL, mu, s, q, [0.2, 0.5, 0.9], 3.7)
+    e = rng.standard_normal(5)
+    sc["slots"] = np.tile(e, (1, 4, 1))
+    eye = np.array([2.0, -2.5, 0.7])
+    d = np.asarray(mu) + rng.uniform(-0.2, 0.2, (30, 3)) - eye
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(eye, d.shape)
+    p = oracle.to_tensors(sc)
+    out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"], t64(o), t64(d), SMALL,
+                        oracle.Opts(samples_fixed=7, jitter=1, jitter_seed=2), slots=p["slots"])
+    for r in range(len(d)):
+        roots = chord(o[r], d[r], mu, s, q)
+        a = 0.0 if roots is None or roots[1] <= 0 else 1 - math.exp(-3.7 * (roots[1] - max(roots[0], 0.0)))
+        np.testing.assert_allclose(out["slot_feat"][r].numpy(), a * e, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [0, 2])
+def test_slot_gates_closed_form_at_a_tetrahedral_offset(k):
+    """A contact offset u = r a_k gives g_k = e^r / (e^r + 3 e^(-r/3)) (the
+    frame's directions meet at a . a' = -1/3), the rest equal; one-hot slot
+    embeddings make the feature the gate vector times the hit's opacity."""
+    rng = np.random.default_rng(22)
+    mu, s, q = [0.3, 0.1, -0.2], [0.5, 0.2, 0.35], rng.standard_normal(4)
+    sigma, rr = 2.5, 0.6
+    sc = _one_prim_scene(SMALL, mu, s, q, [0.5, 0.5, 0.5], sigma)
+    sc["slots"] = np.eye(4)[None].copy()
+    a = oracle.TETRA[k]
+    d_loc = np.cross(a, [0.3, -0.5, 0.8])
+    d_loc /= np.linalg.norm(d_loc)
+    o, d = _ray_to_local_foot(mu, s, q, -rr * a, d_loc)
+    out = render_np(sc, o[None], d[None], SMALL, oracle.Opts(samples_fixed=9, jitter=0), slots=t64(sc["slots"]))
+    out_f = out["slot_feat"][0].numpy()
+    roots = chord(o, d, mu, s, q)
+    alpha = 1 - math.exp(-sigma * (roots[1] - roots[0]))
+    gk = math.exp(rr) / (math.exp(rr) + 3 * math.exp(-rr / 3))
+    want = np.full(4, (1 - gk) / 3)
+    want[k] = gk
+    np.testing.assert_allclose(out_f, alpha * want, rtol=1e-10)
+
+
+def _slot_scene(m):
+    c1, c2 = np.array([0.9, 0.1, 0.2]), np.array([0.1, 0.8, 0.3])
+    return {"center": np.array([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0]]),
+            "scale": np.array([[0.3, 0.3, 0.3], [0.2, 0.2, 0.2]]),
+            "quat": np.array([[1.0, 0, 0, 0], [0.7, 0.1, 0.2, 0.3]]),
+            "mlp": np.stack([const_params(m, c2, 5.0), const_params(m, c1, 2.0)])}
+
+
+def test_slot_features_of_two_disjoint_primitives_compose_in_depth_order():
+    m = SMALL
+    sc = _slot_scene(m)
+    rng = np.random.default_rng(23)
+    e0, e1 = rng.standard_normal(6), rng.standard_normal(6)
+    sc["slots"] = np.stack([np.tile(e0, (4, 1)), np.tile(e1, (4, 1))])
+    o = np.array([[0.0, -4.0, 0.0]])
+    d = np.array([[0.0, 1.0, 0.0]])
+    out = render_np(sc, o, d, m, oracle.Opts(samples_fixed=5, jitter=1), slots=t64(sc["slots"]))
+    a_front = 1 - math.exp(-2.0 * 0.4)      # primitive 1 (radius 0.2, sigma 2) is in front
+    a_back = 1 - math.exp(-5.0 * 0.6)
+    np.testing.assert_allclose(out["slot_feat"][0].numpy(), a_front * e1 + (1 - a_front) * a_back * e0,
+                               rtol=1e-12)
+
+
+def test_slot_feature_gradients_match_central_differences():
+    cfg = synth.CONFIGS[0]
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    sc = {k: v.astype(np.float64) for k, v in synth.make_scene(cfg).items()}
+    rng = np.random.default_rng(24)
+    sc["slots"] = rng.standard_normal((cfg.num_prims, 4, 5))
+    cam = synth.make_camera(np.random.default_rng(5), 24, 24, cfg.camera_radius, cfg.fov_deg)
+    o, d, _ = synth.camera_rays(cam)
+    o, d = o.astype(np.float64), d.astype(np.float64)
+    gs = rng.standard_normal((len(o), 5))
+    # no termination cut, so that a step does not move a discrete decision
+    opts = oracle.Opts(samples_fixed=8, jitter=1, jitter_seed=4)
+    _, _, _, grads, _ = oracle.loss_and_grads(sc, o, d, m, opts, grad_rgb=np.zeros((len(o), 3)), grad_slot=gs)
+
+    def loss(scn):
+        p = oracle.to_tensors(scn)
+        out = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"], t64(o), t64(d), m, opts,
+                            slots=p["slots"])
+        return float((out["slot_feat"].numpy() * gs).sum())
+
+    checked = 0
+    for key in ("center", "scale", "quat", "slots", "mlp"):
+        flat = np.abs(grads[key]).reshape(-1)
+        for idx in np.argsort(flat)[-2:]:
+            # fourth-order central difference at a small step: near-grazing
+            # hits and the encoding's high frequencies give the loss large
+            # higher derivatives (the difference converges to the gradient as
+            # the step shrinks: 1e-5 is off by 6e-4, 1e-7 by 1e-7)
+            def at(step):
+                sp = {k: v.copy() for k, v in sc.items()}
+                sp[key].reshape(-1)[idx] += step
+                return loss(sp)
+            h = 1e-7
+            fd = (8 * (at(h) - at(-h)) - (at(2 * h) - at(-2 * h))) / (12 * h)
+            np.testing.assert_allclose(grads[key].reshape(-1)[idx], fd, rtol=1e-5, atol=1e-9)
+            checked += 1
+    assert checked == 10
