@@ -168,6 +168,39 @@ int msplat_render_backward(msplat_ctx* ctx, const msplat_model* model, const msp
                            float* g_quat, float* g_mlp, void* stream);
 
 /*
+ * Slot features (Sec. 3.4, the feature-embedding equation), rendered from the
+ * hits of the forward call that last wrote `ws` (same model, same num_rays).
+ *   slots [P, 4, slot_dim]: four slot embeddings e_k per primitive.
+ *   out [num_rays, slot_dim] (overwritten): F = sum over the ray's hits of
+ *   W * sum_k g_k e_k, where W is the hit's compositing weight (the sum of its
+ *   samples' weights, T_before (1 - exp(-tau)), zero past the termination
+ *   cut) and g = softmax_k(a_k . u) over the regular tetrahedral frame
+ *   a_k = (1,1,1), (1,-1,-1), (-1,1,-1), (-1,-1,1) / sqrt 3 of the hit's local
+ *   offset u = R^T (mu - p_c) / s at its (unclamped) contact point p_c.
+ * slot_dim must be a positive multiple of 4 (at most 65536), slots and out
+ * 16-byte aligned: MSPLAT_E_INVALID otherwise.  MSPLAT_E_STATE without a
+ * matching forward.
+ */
+int msplat_slot_forward(msplat_ctx* ctx, const msplat_model* model, const float* slots, int32_t slot_dim,
+                        int64_t num_rays, float* out, const void* ws, uint64_t ws_bytes, void* stream);
+
+/*
+ * msplat_render_backward for a loss that also depends on the slot features of
+ * msplat_slot_forward: grad_slot [num_rays, slot_dim] = dL/dF (16-byte
+ * aligned).  Returns the same gradients as msplat_render_backward, now
+ * including the features' dependence on the densities (through W) and on
+ * the geometry (through u), and g_slots [P, 4, slot_dim] = dL/de (overwritten;
+ * accumulated with atomics, so its low bits may differ between runs).
+ */
+int msplat_render_backward_slots(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                                 const float* center, const float* scale, const float* quat,
+                                 const float* mlp, const float* ray_o, const float* ray_d,
+                                 int64_t num_rays, const float* grad_rgb, const float* grad_trans,
+                                 const float* grad_feat, const float* slots, int32_t slot_dim,
+                                 const float* grad_slot, void* ws, uint64_t ws_bytes, float* g_center,
+                                 float* g_scale, float* g_quat, float* g_mlp, float* g_slots, void* stream);
+
+/*
  * Per-stage timing (instrumentation; not part of the rendering method).
  * When enabled, every kernel launch of the context is bracketed by a pair of
  * HIP events recorded on the launch's own stream.  Enabling (or disabling)

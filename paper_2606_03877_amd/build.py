@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmsplat.so")
-SOURCES = ["api.hip", "geometry.hip", "mlp.hip", "mlp_bwd.hip", "mlp_wide.hip", "mlp_bwd_wide.hip", "f64.hip"]
+SOURCES = ["api.hip", "geometry.hip", "mlp.hip", "mlp_bwd.hip", "mlp_wide.hip", "mlp_bwd_wide.hip", "f64.hip",
+           "slots.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

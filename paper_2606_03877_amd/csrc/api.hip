@@ -12,11 +12,13 @@ using namespace msplat;
 // around each launch; pairs are harvested when read (or when a ring fills).
 enum Stage {
   ST_ZERO, ST_PREPROCESS, ST_PACK, ST_BIN_COUNT, ST_SCAN, ST_BIN_FILL, ST_MLP_FWD, ST_COMPOSITE,
-  ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_HIT_GEO, ST_GEO_FINAL, ST_COUNT
+  ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_HIT_GEO, ST_GEO_FINAL, ST_SLOT_FWD, ST_SLOT_BWD_HITS,
+  ST_SLOT_BWD_PRIMS, ST_COUNT
 };
 static const char* kStageNames[ST_COUNT] = {
     "zero", "preprocess", "pack_weights", "bin_count", "scan", "bin_fill", "mlp_forward",
-    "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "hit_geometry", "geo_finalize"};
+    "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "hit_geometry", "geo_finalize",
+    "slot_forward", "slot_backward_hits", "slot_backward_prims"};
 constexpr int kRing = 64;
 struct StageTimer {
   hipEvent_t a[kRing], b[kRing];
@@ -115,6 +117,9 @@ uint64_t layout(const NetShape& n, int64_t R, int64_t hcap, uint8_t* base, Works
   ws.hit_gtot = (float*)take(H * 4);
   ws.hit_gv = (float*)take(H * 4 * 9);
   ws.phit = (int32_t*)take(H * 4);
+  ws.hit_q = (float*)take(H * 4);
+  ws.hit_gpc = (float*)take(H * 12);
+  ws.slot_on = 0;
   ws.num_rays = R;
   ws.hit_cap = hcap;
   ws.nc = nc;
@@ -371,17 +376,53 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   return MSPLAT_OK;
 }
 
-int msplat_render_backward(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
-                           const float* center, const float* scale, const float* quat, const float* mlp,
-                           const float* ray_o, const float* ray_d, int64_t R, const float* grad_rgb,
-                           const float* grad_trans, const float* grad_feat, void* wsp,
-                           uint64_t ws_bytes, float* g_center, float* g_scale, float* g_quat,
-                           float* g_mlp, void* stream) {
+// slot-feature arguments of a backward (null when it carries none)
+struct SlotArgs {
+  const float* slots;
+  int C;
+  const float* grad_slot;
+  float* g_slots;
+};
+
+// C, pointers and alignment of slot-feature arrays (float4 accesses)
+static bool slot_args_ok(const float* slots, int C, const void* a, const void* b) {
+  if (!slots || C <= 0 || C % 4 != 0 || C > (1 << 16)) return false;
+  for (const void* q : {(const void*)slots, a, b})
+    if (q && ((uintptr_t)q % 16) != 0) return false;
+  return true;
+}
+
+// the forward state a call on `wsp` relies on: (work items, hits), or an error
+static int forward_state(msplat_ctx* ctx, const Workspace& ws, const void* wsp, int64_t R, uint64_t ws_bytes,
+                         int64_t hcap, hipStream_t s, int64_t* items, int64_t* nh) {
+  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes) {
+    *items = ctx->last_items;
+    *nh = ctx->last_hits;
+  } else {
+    // workspace of an earlier forward: read its counters
+    HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->host_ctr->magic != kCountersMagic) return MSPLAT_E_STATE;
+    *items = ctx->host_ctr->num_work_items;
+    *nh = ctx->host_ctr->num_hits;
+  }
+  if (*nh > hcap) return MSPLAT_E_STATE;
+  return MSPLAT_OK;
+}
+
+static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o, const float* center,
+                         const float* scale, const float* quat, const float* mlp, const float* ray_o,
+                         const float* ray_d, int64_t R, const float* grad_rgb, const float* grad_trans,
+                         const float* grad_feat, void* wsp, uint64_t ws_bytes, float* g_center, float* g_scale,
+                         float* g_quat, float* g_mlp, const SlotArgs* sa, void* stream) {
   NetShape n;
   if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
   if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
   if (!g_center || !g_scale || !g_quat || !g_mlp) return MSPLAT_E_INVALID;
   if (R > 0 && (!ray_o || !ray_d || !grad_rgb)) return MSPLAT_E_INVALID;
+  if (sa && (!slot_args_ok(sa->slots, sa->C, sa->grad_slot, sa->g_slots) || !sa->g_slots ||
+             (R > 0 && !sa->grad_slot)))
+    return MSPLAT_E_INVALID;
   if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
@@ -389,30 +430,68 @@ int msplat_render_backward(msplat_ctx* ctx, const msplat_model* m, const msplat_
   Workspace ws;
   layout(n, R, hcap, (uint8_t*)wsp, &ws);
   int64_t items, nh;
-  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes) {
-    items = ctx->last_items;
-    nh = ctx->last_hits;
-  } else {
-    // workspace of an earlier forward: read its counters
-    HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (ctx->host_ctr->magic != kCountersMagic) return MSPLAT_E_STATE;
-    items = ctx->host_ctr->num_work_items;
-    nh = ctx->host_ctr->num_hits;
-  }
-  if (nh > hcap) return MSPLAT_E_STATE;
+  int st = forward_state(ctx, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
+  if (st != MSPLAT_OK) return st;
   int cf = n.NOUT - 4;
   STAGE(ctx, ST_ZERO, s, launch_zero(g_mlp, (size_t)n.P * n.n_params * 4, s));
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.geo_grad, (size_t)n.P * 12 * 4, s));
+  if (sa) {
+    STAGE(ctx, ST_ZERO, s, launch_zero(sa->g_slots, (size_t)n.P * 4 * sa->C * 4, s));
+    STAGE(ctx, ST_SLOT_BWD_HITS, s, launch_slot_backward_hits(ws, R, sa->slots, sa->C, sa->grad_slot, s));
+    ws.slot_on = 1;
+  }
   STAGE(ctx, ST_COMP_ADJ, s,
         launch_composite_adjoint(ws, R, *o, grad_rgb, grad_trans, cf > 0 ? grad_feat : nullptr, cf,
                                  ws.ray_tf, s));
   STAGE(ctx, ST_MLP_BWD, s,
         launch_mlp_backward(n, ws, *o, (int)items, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr,
                             g_mlp, s));
+  if (sa)
+    STAGE(ctx, ST_SLOT_BWD_PRIMS, s,
+          launch_slot_backward_prims(ws, n.P, (int)items, sa->slots, sa->C, sa->grad_slot, ray_d, sa->g_slots,
+                                     s));
   STAGE(ctx, ST_HIT_GEO, s, launch_hit_geometry(ws, ray_d, nh, s));
   STAGE(ctx, ST_GEO_FINAL, s, launch_geo_finalize(ws, n.P, g_center, g_scale, g_quat, s));
   return MSPLAT_OK;
+}
+
+int msplat_render_backward(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                           const float* center, const float* scale, const float* quat, const float* mlp,
+                           const float* ray_o, const float* ray_d, int64_t R, const float* grad_rgb,
+                           const float* grad_trans, const float* grad_feat, void* wsp,
+                           uint64_t ws_bytes, float* g_center, float* g_scale, float* g_quat,
+                           float* g_mlp, void* stream) {
+  return backward_impl(ctx, m, o, center, scale, quat, mlp, ray_o, ray_d, R, grad_rgb, grad_trans, grad_feat,
+                       wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, nullptr, stream);
+}
+
+int msplat_slot_forward(msplat_ctx* ctx, const msplat_model* m, const float* slots, int32_t slot_dim,
+                        int64_t R, float* out, const void* wsp, uint64_t ws_bytes, void* stream) {
+  NetShape n;
+  if (!ctx || !shape_of(m, &n) || !wsp || R < 0) return MSPLAT_E_INVALID;
+  if (!slot_args_ok(slots, slot_dim, out, nullptr) || (R > 0 && !out)) return MSPLAT_E_INVALID;
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  int64_t hcap = capacity_of(n, R, ws_bytes);
+  Workspace ws;
+  layout(n, R, hcap, (uint8_t*)const_cast<void*>(wsp), &ws);
+  int64_t items, nh;
+  int st = forward_state(ctx, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
+  if (st != MSPLAT_OK) return st;
+  STAGE(ctx, ST_SLOT_FWD, s, launch_slot_forward(ws, R, slots, slot_dim, out, s));
+  return MSPLAT_OK;
+}
+
+int msplat_render_backward_slots(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                                 const float* center, const float* scale, const float* quat, const float* mlp,
+                                 const float* ray_o, const float* ray_d, int64_t R, const float* grad_rgb,
+                                 const float* grad_trans, const float* grad_feat, const float* slots,
+                                 int32_t slot_dim, const float* grad_slot, void* wsp, uint64_t ws_bytes,
+                                 float* g_center, float* g_scale, float* g_quat, float* g_mlp, float* g_slots,
+                                 void* stream) {
+  SlotArgs sa{slots, slot_dim, grad_slot, g_slots};
+  return backward_impl(ctx, m, o, center, scale, quat, mlp, ray_o, ray_d, R, grad_rgb, grad_trans, grad_feat,
+                       wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, &sa, stream);
 }
 
 int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat_stats* out, void* stream) {

@@ -84,6 +84,9 @@ struct Workspace {
                          // adjoints (dL/dp, s dL/dp, dL/ds_k, omega_k dL/ds_k, dL/dDelta
                          // terms), indexed by the hit's entry in phit
   int32_t* phit;         // [H] hits grouped by primitive
+  float* hit_q;          // [H] slot features, backward: dL/dF . (the hit's feature)
+  float* hit_gpc;        // [3][H] slot features, backward: dL/d(local contact point)
+  int32_t slot_on;       // 1 while a backward carries slot-feature gradients
   int64_t num_rays;
   int64_t hit_cap;
   int64_t wpack_bytes;
@@ -241,6 +244,14 @@ hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t 
 hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
                                float* g_quat, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// slot features (slots.hip)
+hipError_t launch_slot_forward(const Workspace& ws, int64_t R, const float* slots, int C, float* out,
+                               hipStream_t s);
+hipError_t launch_slot_backward_hits(const Workspace& ws, int64_t R, const float* slots, int C,
+                                     const float* grad_slot, hipStream_t s);
+hipError_t launch_slot_backward_prims(const Workspace& ws, int P, int items, const float* slots, int C,
+                                      const float* grad_slot, const float* ray_d, float* g_slots,
+                                      hipStream_t s);
 
 // mlp.hip
 bool mlp_supported(const NetShape& n);

@@ -923,6 +923,9 @@ __global__ __launch_bounds__(256) void composite_adjoint_kernel(
     float gc = g0 * ws.hit_cloc[0 * H + j] + g1 * ws.hit_cloc[1 * H + j] + g2 * ws.hit_cloc[2 * H + j];
     if (grad_feat)
       for (int k = 0; k < cf; ++k) gc += grad_feat[ray * cf + k] * ws.hit_cloc[(3 + k) * H + j];
+    // slot features: a colour channel constant over the hit, composited with
+    // the hit's opacity 1 - exp(-tau), whose upstream product is q
+    if (ws.slot_on) gc += ws.hit_q[j] * -expm1f(-ws.hit_tau[j]);
     ws.hit_tb[j] = tb;
     ws.hit_gtot[j] = tb * gc;
     acc = df_add(acc, two_prod(tb, gc));

@@ -546,6 +546,8 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     const float tb = valid ? ws.hit_tb[hit] : 0.f;
     const float gtot = valid ? ws.hit_gtot[hit] : 0.f;
     const float gsa = valid ? ws.hit_gsa[hit] : 0.f;
+    // slot features enter like a colour channel constant over the hit
+    const float gq = (ws.slot_on && valid) ? ws.hit_q[hit] : 0.f;
     float gr[3] = {0.f, 0.f, 0.f};
     if (valid) {
 #pragma unroll
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
         }
       }
     }
-    const float gc = gcf + other_half(gcf, g);
+    const float gc = gcf + other_half(gcf, g) + gq;
     const bool head = (k == 0);
     SegScan sc(head, col);
     float tincl = sc.incl(tau);

@@ -21,7 +21,8 @@ from ._lib import MsplatError, load
 __all__ = ["NetSpec", "RenderOpts", "Context", "Renderer", "MLPSplat", "render",
            "msplat_render_forward", "msplat_render_backward", "msplat_get_stats",
            "msplat_debug_hits", "msplat_workspace_size", "msplat_num_params",
-           "msplat_render_forward_f64", "msplat_profile_enable", "msplat_profile_read"]
+           "msplat_render_forward_f64", "msplat_profile_enable", "msplat_profile_read",
+           "msplat_slot_forward", "msplat_render_backward_slots"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -182,6 +183,21 @@ def msplat_render_forward_f64(ctx: Context, spec: NetSpec, opts: RenderOpts, cen
     return st, int(need.value)
 
 
+def msplat_slot_forward(ctx: Context, spec: NetSpec, slots, out, ws: torch.Tensor, stream=None) -> int:
+    return ctx.lib.msplat_slot_forward(ctx.handle, ctypes.byref(spec.c()), _p(slots), int(slots.shape[-1]),
+                                       int(out.shape[0]), _p(out), _p(ws), ws.numel(), _stream(stream))
+
+
+def msplat_render_backward_slots(ctx: Context, spec: NetSpec, opts: RenderOpts, center, scale, quat, mlp,
+                                 ray_o, ray_d, grad_rgb, grad_trans, grad_feat, slots, grad_slot, ws,
+                                 g_center, g_scale, g_quat, g_mlp, g_slots, stream=None) -> int:
+    return ctx.lib.msplat_render_backward_slots(
+        ctx.handle, ctypes.byref(spec.c()), ctypes.byref(opts.c()), _p(center), _p(scale), _p(quat),
+        _p(mlp), _p(ray_o), _p(ray_d), int(ray_o.shape[0]), _p(grad_rgb), _p(grad_trans),
+        _p(grad_feat), _p(slots), int(slots.shape[-1]), _p(grad_slot), _p(ws), ws.numel(), _p(g_center),
+        _p(g_scale), _p(g_quat), _p(g_mlp), _p(g_slots), _stream(stream))
+
+
 class Renderer:
     """Context + workspace management around the forward/backward entry points."""
 
@@ -252,6 +268,34 @@ class Renderer:
         if st != _lib.MSPLAT_OK:
             raise MsplatError(st, "msplat_render_backward")
         return g_center, g_scale, g_quat, g_mlp
+
+    def slot_forward(self, ws, slots, num_rays: int):
+        """Slot features [R, C] of the forward that last wrote ``ws``; slots [P, 4, C]."""
+        _check(slots, "slots", (self.spec.num_prims, 4, slots.shape[-1]))
+        out = torch.empty((num_rays, slots.shape[-1]), dtype=torch.float32, device=self.device)
+        st = msplat_slot_forward(self.ctx, self.spec, slots, out, ws)
+        if st != _lib.MSPLAT_OK:
+            raise MsplatError(st, "msplat_slot_forward")
+        return out
+
+    def backward_slots(self, ws, center, scale, quat, mlp, ray_o, ray_d, grad_rgb, slots, grad_slot,
+                       grad_trans=None, grad_feat=None):
+        """backward() of a loss that also depends on slot_forward()'s features;
+        returns (g_center, g_scale, g_quat, g_mlp, g_slots)."""
+        P = self.spec.num_prims
+        g = [torch.empty(sh, dtype=torch.float32, device=self.device)
+             for sh in ((P, 3), (P, 3), (P, 4), (P, self.n_params), tuple(slots.shape))]
+        grad_rgb = grad_rgb.contiguous().float()
+        grad_slot = grad_slot.contiguous().float()
+        if grad_trans is not None:
+            grad_trans = grad_trans.contiguous().float()
+        if grad_feat is not None:
+            grad_feat = grad_feat.contiguous().float()
+        st = msplat_render_backward_slots(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o,
+                                          ray_d, grad_rgb, grad_trans, grad_feat, slots, grad_slot, ws, *g)
+        if st != _lib.MSPLAT_OK:
+            raise MsplatError(st, "msplat_render_backward_slots")
+        return tuple(g)
 
     def stats(self, ws) -> dict:
         return msplat_get_stats(self.ctx, ws)
