@@ -131,6 +131,59 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     }
 
 
+SLOT_DIM = 512   # slot-embedding width (the paper's semantic feature size)
+
+
+def slot_leg(cfg, sc, o, d, prm, ro, rd, steps, warmup, n_check=128):
+    """Slot features on the same frame: the forward (F = sum W sum_k g_k e_k)
+    and the two backward kernels, timed with HIP events per launch, plus F
+    against the oracle on seeded rays."""
+    import torch
+    import oracle
+    from paper_2606_03877_amd import msplat_profile_enable, msplat_profile_read
+    r, opts = setup(cfg, "bf16x3")
+    R = ro.shape[0]
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    slots = torch.randn((cfg.num_prims, 4, SLOT_DIM), device="cuda", generator=gen)
+    g_slot = torch.randn((R, SLOT_DIM), device="cuda", generator=gen) / R
+    g_rgb = torch.zeros((R, 3), device="cuda")
+    rgb, trans, feat, ws = r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)
+    for _ in range(warmup):
+        F = r.slot_forward(ws, slots, R)
+        r.backward_slots(ws, prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd, g_rgb, slots, g_slot)
+    torch.cuda.synchronize()
+    msplat_profile_enable(r.ctx, True)
+    for _ in range(steps):
+        F = r.slot_forward(ws, slots, R)
+        r.backward_slots(ws, prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd, g_rgb, slots, g_slot)
+    torch.cuda.synchronize()
+    stages = msplat_profile_read(r.ctx)
+    msplat_profile_enable(r.ctx, False)
+    st = r.stats(ws)
+    H = int(st["num_hits"])
+    per = {k: stages[k][0] / stages[k][1] for k in ("slot_forward", "slot_backward_hits", "slot_backward_prims")
+           if k in stages and stages[k][1] > 0}
+    # algorithmic bytes of the forward: F written, each ray's offsets, each
+    # hit's record (primitive, cut count, optical depths, contact point), the
+    # embeddings read once
+    fwd_bytes = 4 * R * SLOT_DIM + 8 * R + 32 * H + 16 * cfg.num_prims * SLOT_DIM
+    ach = fwd_bytes / (per["slot_forward"] * 1e-3) / 1e9
+    idx = np.sort(np.random.default_rng(13).choice(len(o), n_check, replace=False))
+    p = oracle.to_tensors(sc)
+    m = oracle.Model(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+    oo = oracle.Opts(samples_fixed=opts.samples_fixed, samples_min=opts.samples_min,
+                     samples_max=opts.samples_max, samples_per_unit=opts.samples_per_unit,
+                     t_stop=opts.t_stop, jitter=opts.jitter, jitter_seed=opts.jitter_seed)
+    ref = oracle.render(p["center"], p["scale"], p["quat"], p["mlp"], torch.from_numpy(o[idx].astype(np.float64)),
+                        torch.from_numpy(d[idx].astype(np.float64)), m, oo, ray_ids=idx,
+                        slots=slots.double().cpu())["slot_feat"].numpy()
+    err = float(np.abs(F.cpu().numpy()[idx] - ref).max())
+    return {"slot_dim": SLOT_DIM, "launch_ms": per,
+            "roofline_forward": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes": fwd_bytes},
+            "max_err_vs_fp64": err, "max_abs_slot": float(slots.abs().max())}
+
+
 def oracle_check(cfg, sc, o, d, rgb_gpu, opts, n=256, seed=11):
     """Max |rgb - rgb_fp64| over n seeded rays (the oracle renders them)."""
     import torch
@@ -233,6 +286,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-order leg")
+    ap.add_argument("--no-slots", action="store_true", help="skip the slot-feature leg")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (reference kernel "
@@ -325,6 +379,11 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
 
+    slots = None
+    if not args.no_slots:
+        slots = slot_leg(cfg, sc, o, d, prm, ro, rd, max(3, args.steps // 4), 1)
+        print(f"# slot features C={SLOT_DIM}: {slots['launch_ms']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, sc, o, d, target.cpu().numpy(), opts, budget_s=args.cpu_budget)
@@ -353,6 +412,7 @@ def main():
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
         "cpu_baseline": cpu,
         "tile_order": tile,
+        "slot_features": slots,
     }
     out["legs"] = {k: {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"],
                        "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
