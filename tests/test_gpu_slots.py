@@ -39,7 +39,7 @@ def _oracle(ci, sc, o, d, opts, slots, chunk=4096):
 
 
 @pytest.mark.parametrize("ci,w,h", [(0, 64, 64), (1, 100, 75), (4, 90, 70)])
-@pytest.mark.parametrize("C", [512, 36])
+@pytest.mark.parametrize("C", [512, 36, 1040])
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_slot_forward_matches_oracle(ci, w, h, C, precision):
     sc = scene(ci)
@@ -59,15 +59,17 @@ def test_slot_forward_matches_oracle(ci, w, h, C, precision):
     assert np.abs(F[~same] - ref[~same]).max(initial=0.0) <= (opts.t_stop + TOL[precision]) * scale
 
 
-@pytest.mark.parametrize("ci,w,h", [(1, 64, 50), (4, 44, 40)])
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_slot_backward_matches_oracle(ci, w, h, precision):
+# slot widths 64 (one 256-channel chunk), 516 (four, the last ragged) and
+# 1040 (beyond the register-resident row: streamed per hit, two passes)
+@pytest.mark.parametrize("ci,w,h,precision,C", [
+    (1, 64, 50, "fp32", 64), (4, 44, 40, "fp32", 64), (1, 64, 50, "bf16x3", 64), (4, 44, 40, "bf16x3", 64),
+    (1, 48, 40, "fp32", 516), (0, 40, 40, "fp32", 1040)])
+def test_slot_backward_matches_oracle(ci, w, h, precision, C):
     tol = TOL[precision]
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
     o, d = view_rays(ci, w, h)
     opts = opts_of(cfg)
-    C = 64
     slots = _slots(ci, C, seed=1)
     R = len(o)
     rng = np.random.default_rng(1000 * ci + 9)
