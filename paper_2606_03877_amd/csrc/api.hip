@@ -163,16 +163,21 @@ hipError_t harvest_one(StageTimer& t) {
   return hipSuccess;
 }
 
+hipError_t create_events(StageTimer& t) {
+  if (t.created) return hipSuccess;
+  for (int i = 0; i < kRing; ++i) {
+    if (hipEventCreate(&t.a[i]) != hipSuccess || hipEventCreate(&t.b[i]) != hipSuccess)
+      return hipErrorOutOfMemory;
+  }
+  t.created = true;
+  return hipSuccess;
+}
+
 hipError_t stage_begin(msplat_ctx* c, int id, hipStream_t s) {
   if (!c->profiling) return hipSuccess;
   StageTimer& t = c->timers[id];
-  if (!t.created) {
-    for (int i = 0; i < kRing; ++i) {
-      if (hipEventCreate(&t.a[i]) != hipSuccess || hipEventCreate(&t.b[i]) != hipSuccess)
-        return hipErrorOutOfMemory;
-    }
-    t.created = true;
-  }
+  hipError_t ce = create_events(t);
+  if (ce != hipSuccess) return ce;
   if (t.pending == kRing) {
     hipError_t e = harvest_one(t);
     if (e != hipSuccess) return e;
@@ -281,6 +286,8 @@ int msplat_profile_enable(msplat_ctx* c, int enable) {
       if (harvest_one(t) != hipSuccess) return MSPLAT_E_HIP;
     t.total_ms = 0.0;
     t.count = 0;
+    // every stage's events exist before the first timed launch
+    if (enable && create_events(t) != hipSuccess) return MSPLAT_E_HIP;
   }
   c->profiling = enable != 0;
   return MSPLAT_OK;
