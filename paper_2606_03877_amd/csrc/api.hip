@@ -359,7 +359,7 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   STAGE(ctx, ST_PREPROCESS, s, launch_preprocess(ws, center, scale, quat, n.P, s));
   STAGE(ctx, ST_PACK, s, launch_pack_weights(n, ws, mlp, s));
   STAGE(ctx, ST_BIN_COUNT, s, launch_bin_count(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
-  STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n.P, s));
+  STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n.P, n.n_params, s));
   HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   int64_t nh = ctx->host_ctr->num_hits;
@@ -400,18 +400,25 @@ static bool slot_args_ok(const float* slots, int C, const void* a, const void* b
 }
 
 // the forward state a call on `wsp` relies on: (work items, hits), or an error
-static int forward_state(msplat_ctx* ctx, const Workspace& ws, const void* wsp, int64_t R, uint64_t ws_bytes,
-                         int64_t hcap, hipStream_t s, int64_t* items, int64_t* nh) {
-  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes) {
+// (the workspace layout follows from the model, the ray count and the byte
+// size: a call whose arguments differ from the forward's would read it at
+// other offsets, so that is refused)
+static int forward_state(msplat_ctx* ctx, const NetShape& n, const Workspace& ws, const void* wsp, int64_t R,
+                         uint64_t ws_bytes, int64_t hcap, hipStream_t s, int64_t* items, int64_t* nh) {
+  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes &&
+      ctx->last_shape.P == n.P && ctx->last_shape.n_params == n.n_params && ctx->last_shape.NOUT == n.NOUT) {
     *items = ctx->last_items;
     *nh = ctx->last_hits;
   } else {
     // workspace of an earlier forward: read its counters
     HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (ctx->host_ctr->magic != kCountersMagic) return MSPLAT_E_STATE;
-    *items = ctx->host_ctr->num_work_items;
-    *nh = ctx->host_ctr->num_hits;
+    const DevCounters& c = *ctx->host_ctr;
+    if (c.magic != kCountersMagic || c.num_rays != R || c.hit_cap != hcap || c.num_prims != n.P ||
+        c.num_params != n.n_params)
+      return MSPLAT_E_STATE;
+    *items = c.num_work_items;
+    *nh = c.num_hits;
   }
   if (*nh > hcap) return MSPLAT_E_STATE;
   return MSPLAT_OK;
@@ -437,7 +444,7 @@ static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_op
   Workspace ws;
   layout(n, R, hcap, (uint8_t*)wsp, &ws);
   int64_t items, nh;
-  int st = forward_state(ctx, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
+  int st = forward_state(ctx, n, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
   if (st != MSPLAT_OK) return st;
   int cf = n.NOUT - 4;
   STAGE(ctx, ST_ZERO, s, launch_zero(g_mlp, (size_t)n.P * n.n_params * 4, s));
@@ -483,7 +490,7 @@ int msplat_slot_forward(msplat_ctx* ctx, const msplat_model* m, const float* slo
   Workspace ws;
   layout(n, R, hcap, (uint8_t*)const_cast<void*>(wsp), &ws);
   int64_t items, nh;
-  int st = forward_state(ctx, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
+  int st = forward_state(ctx, n, ws, wsp, R, ws_bytes, hcap, s, &items, &nh);
   if (st != MSPLAT_OK) return st;
   STAGE(ctx, ST_SLOT_FWD, s, launch_slot_forward(ws, R, slots, slot_dim, out, s));
   return MSPLAT_OK;

@@ -38,8 +38,13 @@ struct DevCounters {
   uint32_t min_abs_g_bits;   // float bits of min |g| (non-negative floats order as ints)
   int32_t overflow;          // set if the hit list outgrew the capacity
   uint32_t magic;            // kCountersMagic once a forward pass has filled the workspace
-  int32_t pad[6];
+  // what the workspace was laid out for (checked by the calls that read it)
+  int64_t num_rays;
+  int64_t hit_cap;
+  int32_t num_prims;
+  int32_t num_params;
 };
+static_assert(sizeof(DevCounters) == 64, "counter block size");
 constexpr uint32_t kCountersMagic = 0x4d53504cu;
 
 // Workspace layout: every section 256-byte aligned, sized from (model, R, H).
@@ -230,7 +235,7 @@ hipError_t launch_preprocess(const Workspace& ws, const float* center, const flo
 hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float* ray_d,
                             const float* center, const float* scale, const float* quat, int64_t R,
                             int P, const msplat_opts& o, hipStream_t s);
-hipError_t launch_scans(const Workspace& ws, int64_t R, int P, hipStream_t s);
+hipError_t launch_scans(const Workspace& ws, int64_t R, int P, int n_params, hipStream_t s);
 hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float* ray_d,
                            const float* center, const float* scale, const float* quat,
                            int64_t R, int P, const msplat_opts& o, hipStream_t s);

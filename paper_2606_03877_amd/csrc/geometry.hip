@@ -441,7 +441,8 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
                                                         int32_t* __restrict__ prim_cursor,
                                                         int32_t* __restrict__ wi_off, int P,
                                                         const int32_t* __restrict__ ray_off,
-                                                        int64_t R, DevCounters* __restrict__ ctr) {
+                                                        int64_t R, DevCounters* __restrict__ ctr,
+                                                        int64_t hit_cap, int n_params) {
   __shared__ int32_t wsum[2][4];
   __shared__ int32_t carry[2];
   if (threadIdx.x == 0) carry[0] = carry[1] = 0;
@@ -480,6 +481,10 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
     wi_off[P] = carry[1];
     ctr->num_hits = ray_off[R];
     ctr->num_work_items = carry[1];
+    ctr->num_rays = R;
+    ctr->hit_cap = hit_cap;
+    ctr->num_prims = P;
+    ctr->num_params = n_params;
     ctr->magic = kCountersMagic;
   }
 }
@@ -1115,7 +1120,7 @@ hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float
   return hipGetLastError();
 }
 
-hipError_t launch_scans(const Workspace& ws, int64_t R, int P, hipStream_t s) {
+hipError_t launch_scans(const Workspace& ws, int64_t R, int P, int n_params, hipStream_t s) {
   // ray_off[0] = 0 and ray_off[1..R] hold counts: inclusive scan of [1..R]
   int64_t n = R;
   int32_t* data = ws.ray_off + 1;
@@ -1129,7 +1134,7 @@ hipError_t launch_scans(const Workspace& ws, int64_t R, int P, hipStream_t s) {
   }
   hipLaunchKernelGGL(prim_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_nhit,
                      ws.prim_off, ws.prim_cursor, ws.wi_off, P, (const int32_t*)ws.ray_off, R,
-                     ws.counters);
+                     ws.counters, ws.hit_cap, n_params);
   return hipGetLastError();
 }
 

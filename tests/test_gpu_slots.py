@@ -120,3 +120,25 @@ def test_slot_arguments_are_validated():
     good = torch.zeros((synth.CONFIGS[ci].num_prims, 4, 8), device="cuda")
     out8 = torch.empty((len(o), 8), device="cuda")
     assert msplat_slot_forward(r.ctx, r.spec, good, out8, fresh) == _lib.MSPLAT_E_STATE
+
+
+def test_calls_on_an_earlier_workspace_check_its_layout():
+    """A workspace that is not the context's last one is read through the
+    identity its forward recorded: the same ray count works, another is
+    refused (the layout would differ)."""
+    from paper_2606_03877_amd import msplat_slot_forward, _lib
+    ci = 0
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 32, 16)
+    g = gpu_render(ci, "fp32", sc, o, d, opts_of(cfg))
+    r = g["renderer"]
+    t, to, td = g["dev"]
+    ws1 = g["ws"]
+    # another forward on a second workspace becomes the context's last one
+    r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to[:64], td[:64])
+    slots = torch.zeros((cfg.num_prims, 4, 8), device="cuda")
+    out = torch.empty((len(o), 8), device="cuda")
+    assert msplat_slot_forward(r.ctx, r.spec, slots, out, ws1) == _lib.MSPLAT_OK
+    more = torch.empty((len(o) + 64, 8), device="cuda")
+    assert msplat_slot_forward(r.ctx, r.spec, slots, more, ws1) == _lib.MSPLAT_E_STATE
