@@ -10,8 +10,7 @@ differentiation).  All discrete decisions -- hit or miss, depth order, sample
 count, ReLU gate, the early-termination cut -- are taken on real parts and are
 held fixed under differentiation.
 
-Readings taken where the paper leaves a choice open (each is listed in
-DESIGN.md):
+Readings taken where the paper leaves a choice open:
   * quaternion order (w, x, y, z), Hamilton product, normalised before use;
   * the scale vector gives the semi-axes of a hard ellipsoid support; density
     is zero outside it (no Gaussian falloff inside);
