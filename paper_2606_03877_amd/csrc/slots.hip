@@ -53,6 +53,7 @@ __device__ __forceinline__ void local_offset(const Workspace& ws, int64_t j, flo
 }
 
 constexpr int kSlotChunk = 4 * kWave;   // channels a wave covers per pass (4 per lane)
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // NCH chunks of 256 channels per walk over the ray's hits (one walk for
 // C <= 256 NCH): the hit records are read once per walk and the chunks' loads
@@ -91,10 +92,14 @@ __global__ __launch_bounds__(256) void slot_forward_kernel(Workspace ws, int64_t
         }
       }
     }
+    // F is written once and not read again here: streaming stores
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
       const int c = cb + q * kSlotChunk + 4 * lane;
-      if (c < C) *reinterpret_cast<float4*>(out + ray * C + c) = acc[q];
+      if (c < C) {
+        const f4v v = {acc[q].x, acc[q].y, acc[q].z, acc[q].w};
+        __builtin_nontemporal_store(v, reinterpret_cast<f4v*>(out + ray * C + c));
+      }
     }
   }
 }
