@@ -9,7 +9,10 @@ from .render import (Model, Opts, quat_to_rotmat, local_frame, intersect, encode
                      slot_gates)
 from .pcg import pcg_hash, sample_offsets
 from .grad import loss_and_grads, complex_step, to_tensors
+from .contact import (KAPPA, ContactModel, encode_vec, contact_terms, render_contact, contact_margins,
+                      contact_loss_and_grads)
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect", "encode",
            "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render", "TETRA", "slot_gates", "pcg_hash", "sample_offsets", "loss_and_grads",
-           "complex_step", "to_tensors"]
+           "complex_step", "to_tensors", "KAPPA", "ContactModel", "encode_vec", "contact_terms",
+           "render_contact", "contact_margins", "contact_loss_and_grads"]

@@ -52,10 +52,15 @@ class Config:
     batch_rays: int = 0             # >0: random batch over the views' pixels
     jitter: int = 1                 # 1 = stratified (hashed) offsets, 0 = midpoints
     fov_deg: float = 50.0
+    # "chord": K samples of the hit chord, input the local position (3 + 6L
+    # encoded values); "contact": the paper's primitive, one interaction at
+    # the contact point, input [d; delta] (12 L encoded values), scale = the
+    # Gaussian support's standard deviations
+    primitive: str = "chord"
 
     @property
     def in_dim(self) -> int:
-        return 3 + 6 * self.pe_freqs
+        return 12 * self.pe_freqs if self.primitive == "contact" else 3 + 6 * self.pe_freqs
 
     @property
     def num_rays(self) -> int:
@@ -80,6 +85,12 @@ CONFIGS: List[Config] = [
     # compiled shape no workload above uses): a parity-test case
     Config(5, "features-64", 64, 6, 64, 3, 20, "uniform", ("loguniform", 0.05, 0.3),
            ((800, 800),), 3.0, 64, t_stop=1e-4),
+    # the paper's own primitive (Sec. 3.2, Sec. 4.1): 72-32-32-4 networks on
+    # the encoded [d; delta], one interaction per hit; 2048 primitives (the
+    # paper's octree gives 1,344-3,862 on Replica) of Gaussian standard
+    # deviations 0.02-0.08, an 800x800 frame
+    Config(6, "contact-800", 2048, 6, 32, 2, 4, "uniform", ("loguniform", 0.02, 0.08),
+           ((800, 800),), 3.0, 1, t_stop=1e-4, jitter=0, primitive="contact"),
 ]
 
 
@@ -121,7 +132,9 @@ def make_scene(cfg: Config, seed: Optional[int] = None) -> dict:
     Weights are Kaiming-uniform U(-sqrt(6/fan_in), +sqrt(6/fan_in)); biases are
     zero except the density output's bias, set to softplus^-1(ln 2 / Lbar) with
     Lbar = 4/3 * (s_x s_y s_z)^(1/3) (mean chord of the volume-equivalent
-    sphere), so a hit's opacity is about one half on average.
+    sphere), so a hit's opacity is about one half on average.  For the
+    contact-point primitive it is softplus^-1(2 / (sqrt(2 pi) sbar)),
+    sbar = (s_x s_y s_z)^(1/3): a ray through the centre sees optical depth 2.
     """
     if seed is None:
         seed = 1000 * cfg.idx
@@ -140,8 +153,13 @@ def make_scene(cfg: Config, seed: Optional[int] = None) -> dict:
             mlp[p, off:off + fi * fo] = rng.uniform(-bound, bound, size=fi * fo)
             off += fi * fo
             if li == len(dims) - 1:
-                lbar = (4.0 / 3.0) * float(np.prod(scale[p])) ** (1.0 / 3.0)
-                target = math.log(2.0) / lbar
+                if cfg.primitive == "contact":
+                    # optical depth 2 for a ray through the centre: density
+                    # times the Gaussian's length sqrt(2 pi) sbar along a ray
+                    target = 2.0 / (math.sqrt(2.0 * math.pi) * float(np.prod(scale[p])) ** (1.0 / 3.0))
+                else:
+                    lbar = (4.0 / 3.0) * float(np.prod(scale[p])) ** (1.0 / 3.0)
+                    target = math.log(2.0) / lbar
                 mlp[p, off + 3] = math.log(math.expm1(target))
             off += fo
     return {
