@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the MLP-Splatting render path on one MI355X.
 
-One step = the whole hot path over one 800x800 frame of the 64-primitive
-scene (39-64-64-64-4 networks, 64 stratified samples per hit, early
-termination at T < 1e-4): ray binning and depth sort, grouped per-primitive
+One step = the whole hot path over the largest single-GPU workload: 16 views
+of mixed resolutions (4x 256x256, 4x 512x512, 4x 800x800, 4x 1024x768; 7.0 M
+rays) of a 512-primitive scene with 39-64-64-64-4 networks, a sample count
+per hit proportional to its chord (clamp(ceil(128 L), 8, 128)) and early
+termination at T < 1e-4: ray binning and depth sort, grouped per-primitive
 networks with hit-local compositing, per-ray compositing, the MSE loss
-against a target frame rendered from a second seeded scene, and the backward
+against target frames rendered from a second seeded scene, and the backward
 pass to every primitive parameter through the autograd Function.
 
-Prints ONE JSON line.  `value` is forward+backward rays/s in the BF16 matrix-
-core form; the FP32 form, forward-only rates, the error against the FP64
-oracle on sampled rays, per-kernel times from HIP events recorded on the
-launch stream, the dominant kernel's roofline and the oracle's CPU rate are
-reported beside it.
+Prints ONE JSON line.  `value` is forward+backward rays/s in the split-BF16
+matrix-core form (the form whose gradients meet the BF16 tolerance); plain
+BF16 is reported forward-only (its gradients do not), FP32 forward and
+forward+backward as the reference form.  Beside them: the error against the
+FP64 oracle on sampled rays, per-kernel times from HIP events recorded on the
+launch stream, the dominant kernel's matrix-core roofline, the HBM rooflines
+of the binning and compositing kernels, the 800x800 single-frame workload
+as a nested object, and the oracle's CPU rate.
 """
 from __future__ import annotations
 
@@ -77,9 +82,10 @@ def device_inputs(cfg):
     return sc, o, d, prm, torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
 
 
-def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, order=0, want_hits=False):
-    """Time fwd+bwd training steps and forward-only renders of one precision
-    (and hit order: 0 exact, 1 tile order)."""
+def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, order=0, want_hits=False,
+            train=True):
+    """Time fwd+bwd training steps (unless ``train`` is off) and forward-only
+    renders of one precision (and hit order: 0 exact, 1 tile order)."""
     import torch
     from paper_2606_03877_amd import render, msplat_profile_enable, msplat_profile_read
     r, opts = setup(cfg, precision, order=order)
@@ -98,22 +104,25 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     # backward runs on the calling thread: autograd's per-device worker thread
     # must otherwise be woken for every step, and the GPU waits for it
     # (1.7-2.7 ms per step in some processes)
-    with torch.autograd.set_multithreading_enabled(False):
+    t0 = t1 = 0.0
+    stages = {}
+    if train:
+        with torch.autograd.set_multithreading_enabled(False):
+            if profile:
+                msplat_profile_enable(r.ctx, True)
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            if profile:
+                msplat_profile_enable(r.ctx, True)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        stages = msplat_profile_read(r.ctx) if profile else {}
         if profile:
-            msplat_profile_enable(r.ctx, True)
-        for _ in range(warmup):
-            step()
-        torch.cuda.synchronize()
-        if profile:
-            msplat_profile_enable(r.ctx, True)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    stages = msplat_profile_read(r.ctx) if profile else {}
-    if profile:
-        msplat_profile_enable(r.ctx, False)
+            msplat_profile_enable(r.ctx, False)
     # forward only
     with torch.no_grad():
         for _ in range(max(1, warmup)):
@@ -129,9 +138,9 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     hits = r.hits(ws, R)[:2] if want_hits else None
     return {
         "hits": hits,
-        "fwdbwd_ms": 1e3 * (t1 - t0) / steps,
+        "fwdbwd_ms": 1e3 * (t1 - t0) / steps if train else None,
         "fwd_ms": 1e3 * (f1 - f0) / steps,
-        "fwdbwd_rays_per_s": R * steps / (t1 - t0),
+        "fwdbwd_rays_per_s": R * steps / (t1 - t0) if train else None,
         "fwd_rays_per_s": R * steps / (f1 - f0),
         "stages": stages,
         "stats": stats,
@@ -213,7 +222,7 @@ def oracle_check(cfg, sc, o, d, rgb_gpu, opts, n=256, seed=11):
     return float(np.abs(g - out["rgb"].numpy()).max())
 
 
-def cpu_baseline(cfg, sc, o, d, target, opts, budget_s=12.0, chunk=2048, seed=5):
+def cpu_baseline(cfg, sc, o, d, target, opts, budget_s=12.0, chunk=1024, seed=5):
     """The FP64 oracle's forward+backward rate on host cores over a bounded
     seeded sample of the same rays (chunks until the time budget is spent)."""
     import torch
@@ -285,16 +294,107 @@ def traffic_from_profiles(kernel: str, workload: str, precision: str):
         return None
 
 
+# Algorithmic HBM bytes per launch of the binning and compositing kernels
+# (what each must move at least once; R rays, H hits, P primitives, NC = 3 +
+# feature channels):
+#   bin_count: ray origin and direction read (24 B) and its hit count written
+#     (4 B) per ray; each primitive's 160-byte frame record read once;
+#   bin_fill: ray read (24 B) and its offset (4 B) per ray; the hit record
+#     written (primitive, ray, sample count, contact depth hi+lo, half chord,
+#     chord start and bin width hi+lo, contact point and direction hi+lo, the
+#     per-primitive list entry: 92 B) per hit;
+#   composite: ray offsets (8 B) read and colour, transmittance and the kept
+#     transmittance (20 B) written per ray; per hit the optical depth, sample
+#     count and colour sums read (8 + 4 NC B), the composited count and the
+#     optical depth before the hit written (12 B);
+#   composite_adjoint: ray offsets, upstream gradient and final transmittance
+#     (24 B) per ray; per hit the composited count, optical depth before it
+#     and colour sums read (12 + 4 NC B), three backward scalars written (12 B).
+def hbm_bytes(kernel: str, R: int, H: int, P: int, nc: int) -> int:
+    return {"bin_count": 28 * R + 160 * P,
+            "bin_fill": 28 * R + 92 * H,
+            "composite": 28 * R + (20 + 4 * nc) * H,
+            "composite_adjoint": 24 * R + (24 + 4 * nc) * H}[kernel]
+
+
+def hbm_rooflines(cfg, leg, workload_key, precision):
+    st = leg["stats"]
+    out = {}
+    for k in ("bin_count", "bin_fill", "composite", "composite_adjoint"):
+        v = leg["stages"].get(k)
+        if not v or v[1] == 0:
+            continue
+        ms = v[0] / v[1]
+        b = hbm_bytes(k, int(st["num_rays"]), int(st["num_hits"]), cfg.num_prims, cfg.out_dim - 1)
+        ach = b / (ms * 1e-3) / 1e9
+        out[k] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                  "avg_launch_ms": ms, "algorithmic_bytes_per_launch": b,
+                  "traffic": traffic_from_profiles(k, workload_key, precision)}
+    return out
+
+
+def mfma_roofline(cfg, leg, workload_key, precision):
+    """The training step's dominant kernel: algorithmic FLOP per launch over its
+    HIP-event launch time, against the dense BF16 matrix-core peak."""
+    st = leg["stats"]
+    fps = mlp_flops_per_sample(cfg)
+    stages = {k: v for k, v in leg["stages"].items() if v[1] > 0}
+    dom = max(stages, key=lambda k: stages[k][0])
+    avg_ms = stages[dom][0] / stages[dom][1]
+    flops = {"mlp_forward": fps * st["num_samples"], "mlp_backward": 2 * fps * st["num_samples"]}
+    if dom in flops:
+        achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
+        return {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"],
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16"],
+                "traffic": traffic_from_profiles(dom, workload_key, precision),
+                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops[dom]}
+    return {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+
+
+def target_frames(cfg, ro, rd):
+    """Target colours of the rays: the same workload rendered (FP32) from a
+    second, independently seeded scene of the same law."""
+    import torch
+    import synth
+    r_t, _ = setup(cfg, "fp32")
+    sc_t = synth.make_scene(cfg, seed=1000 * cfg.idx + 10)
+    pt = {k: torch.from_numpy(v).cuda() for k, v in sc_t.items()}
+    with torch.no_grad():
+        target, _, _, _ = r_t.forward(pt["center"], pt["scale"], pt["quat"], pt["mlp"], ro, rd)
+    torch.cuda.synchronize()
+    return target
+
+
+def nested_workload(ci, steps, warmup):
+    """The training form on another workload: rays/s and the dominant kernel's
+    roofline (a nested object of the bench line)."""
+    import synth
+    cfg = synth.CONFIGS[ci]
+    sc, o, d, prm, ro, rd = device_inputs(cfg)
+    target = target_frames(cfg, ro, rd)
+    leg = run_leg(cfg, "bf16x3", prm, ro, rd, target, steps, warmup)
+    _, opts = setup(cfg, "bf16x3")
+    return {"workload": workload_name(cfg), "rays": len(o), "hits": int(leg["stats"]["num_hits"]),
+            "samples": int(leg["stats"]["num_samples"]), "ms_per_step": leg["fwdbwd_ms"],
+            "fwdbwd_rays_per_s": leg["fwdbwd_rays_per_s"], "fwd_rays_per_s": leg["fwd_rays_per_s"],
+            "rgb_max_err_vs_fp64": oracle_check(cfg, sc, o, d, leg["rgb"], opts),
+            "roofline": mfma_roofline(cfg, leg, f"config{ci}", "bf16x3"),
+            "hbm_rooflines": hbm_rooflines(cfg, leg, f"config{ci}", "bf16x3"),
+            "stages_ms_per_step": {k: v[0] / steps for k, v in leg["stages"].items() if v[1] > 0}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-order leg")
     ap.add_argument("--no-slots", action="store_true", help="skip the slot-feature leg")
+    ap.add_argument("--no-nested", action="store_true", help="skip the 800x800 single-frame object")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (reference kernel "
@@ -319,27 +419,23 @@ def main():
     cfg = synth.CONFIGS[args.config]
     sc, o, d, prm, ro, rd = device_inputs(cfg)
     R = len(o)
-    # target frame: a second, independently seeded scene of the same law
-    r_t, _ = setup(cfg, "fp32")
-    sc_t = synth.make_scene(cfg, seed=1000 * cfg.idx + 10)
-    pt = {k: torch.from_numpy(v).cuda() for k, v in sc_t.items()}
-    with torch.no_grad():
-        target, _, _, _ = r_t.forward(pt["center"], pt["scale"], pt["quat"], pt["mlp"], ro, rd)
-    torch.cuda.synchronize()
+    target = target_frames(cfg, ro, rd)
     print(f"# config {cfg.idx} {cfg.name}: {R} rays, {cfg.num_prims} primitives", file=sys.stderr, flush=True)
+    wkey = f"config{cfg.idx}"
 
     # the training step runs in the split-bfloat16 form (the plain form's
-    # gradients do not meet the bfloat16 tolerance); plain bfloat16 is the
-    # inference form; float32 is the reference form
+    # gradients do not meet the bfloat16 tolerance, so plain bfloat16 is timed
+    # forward-only, as the inference form); float32 is the reference form
     MAIN = "bf16x3"
     legs = {}
     legs[MAIN] = run_leg(cfg, MAIN, prm, ro, rd, target, args.steps, args.warmup, want_hits=not args.no_tile)
     print(f"# {MAIN} fwd+bwd {legs[MAIN]['fwdbwd_ms']:.3f} ms fwd {legs[MAIN]['fwd_ms']:.3f} ms",
           file=sys.stderr, flush=True)
-    extra = ["bf16"] + ([] if args.no_fp32 else ["fp32"])
-    for prec in extra:
-        legs[prec] = run_leg(cfg, prec, prm, ro, rd, target, max(3, args.steps // 4), 1)
-        print(f"# {prec} fwd+bwd {legs[prec]['fwdbwd_ms']:.3f} ms fwd {legs[prec]['fwd_ms']:.3f} ms",
+    legs["bf16"] = run_leg(cfg, "bf16", prm, ro, rd, target, max(3, args.steps // 2), 1, train=False)
+    print(f"# bf16 fwd {legs['bf16']['fwd_ms']:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_fp32:
+        legs["fp32"] = run_leg(cfg, "fp32", prm, ro, rd, target, 3, 1)
+        print(f"# fp32 fwd+bwd {legs['fp32']['fwdbwd_ms']:.3f} ms fwd {legs['fp32']['fwd_ms']:.3f} ms",
               file=sys.stderr, flush=True)
 
     _, opts = setup(cfg, MAIN)
@@ -369,28 +465,20 @@ def main():
                 "psnr_vs_exact_db": (10.0 * math.log10(1.0 / mse)) if mse > 0 else None,
                 "rgb_max_err_vs_fp64": oracle_check(cfg, sc, o, d, tl["rgb"], setup(cfg, MAIN, order=1)[1])}
 
-    # dominant kernel of the training step and its roofline
     b = legs[MAIN]
     st = b["stats"]
-    fps = mlp_flops_per_sample(cfg)
-    stages = {k: v for k, v in b["stages"].items() if v[1] > 0}
-    dom = max(stages, key=lambda k: stages[k][0])
-    avg_ms = stages[dom][0] / stages[dom][1]
-    flops = {"mlp_forward": fps * st["num_samples"], "mlp_backward": 2 * fps * st["num_samples"]}
-    if dom in flops:
-        achieved = flops[dom] / (avg_ms * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS["bf16"],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["bf16"],
-                "traffic": traffic_from_profiles(dom, f"config{cfg.idx}", MAIN),
-                "avg_launch_ms": avg_ms, "algorithmic_flops_per_launch": flops[dom]}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": avg_ms}
+    roof = mfma_roofline(cfg, b, wkey, MAIN)
+    hbm = hbm_rooflines(cfg, b, wkey, MAIN)
 
     slots = None
     if not args.no_slots:
-        slots = slot_leg(cfg, sc, o, d, prm, ro, rd, max(3, args.steps // 4), 1)
+        slots = slot_leg(cfg, sc, o, d, prm, ro, rd, 3, 1)
         print(f"# slot features C={SLOT_DIM}: {slots['launch_ms']}", file=sys.stderr, flush=True)
+
+    nested = None
+    if not args.no_nested and args.config != 1:
+        nested = nested_workload(1, 20, 3)
+        print(f"# config 1 fwd+bwd {nested['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -417,18 +505,31 @@ def main():
         "fwdbwd_rays_per_s": b["fwdbwd_rays_per_s"],
         "rgb_max_err_vs_fp64": errs,
         "roofline": roof,
-        "stages_ms_per_step": {k: v[0] / args.steps for k, v in stages.items()},
+        "hbm_rooflines": hbm,
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in b["stages"].items() if v[1] > 0},
         "cpu_baseline": cpu,
         "tile_order": tile,
         "slot_features": slots,
+        "config1_800x800": nested,
     }
-    out["legs"] = {k: {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"],
-                       "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
-                       "fwd_ms": v["fwd_ms"], "fwdbwd_ms": v["fwdbwd_ms"]} for k, v in legs.items()}
+    out["legs"] = {}
+    for k, v in legs.items():
+        e = {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
+             "fwd_ms": v["fwd_ms"]}
+        if v["fwdbwd_ms"] is not None:
+            e.update({"fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"], "fwdbwd_ms": v["fwdbwd_ms"]})
+        else:
+            e["fwdbwd"] = "not reported: this form's gradients are not held to the BF16 tolerance"
+        out["legs"][k] = e
     if "fp32" in legs:
-        out["speedup_vs_fp32"] = {k: {"fwd": v["fwd_rays_per_s"] / legs["fp32"]["fwd_rays_per_s"],
-                                      "fwdbwd": v["fwdbwd_rays_per_s"] / legs["fp32"]["fwdbwd_rays_per_s"]}
-                                  for k, v in legs.items() if k != "fp32"}
+        sp = {}
+        for k, v in legs.items():
+            if k == "fp32":
+                continue
+            sp[k] = {"fwd": v["fwd_rays_per_s"] / legs["fp32"]["fwd_rays_per_s"]}
+            if v["fwdbwd_rays_per_s"] is not None:
+                sp[k]["fwdbwd"] = v["fwdbwd_rays_per_s"] / legs["fp32"]["fwdbwd_rays_per_s"]
+        out["speedup_vs_fp32"] = sp
     print(json.dumps(out), flush=True)
 
 

@@ -125,7 +125,9 @@ int64_t msplat_num_params(const msplat_model* model);
  * Workspace bytes needed for `num_rays` rays producing at most `max_hits`
  * ray/primitive hits.  The workspace holds the hit lists, per-hit partial
  * colours and everything the backward pass reads; it must stay untouched
- * between a forward call and the backward call that uses it.
+ * between a forward call and the backward call that uses it.  Hit lists are
+ * addressed with 32-bit offsets: num_rays and max_hits above 2^31 - 1 are
+ * MSPLAT_E_INVALID.
  */
 int msplat_workspace_size(const msplat_model* model, int64_t num_rays, int64_t max_hits,
                           uint64_t* bytes);
@@ -141,7 +143,8 @@ int msplat_workspace_size(const msplat_model* model, int64_t num_rays, int64_t m
  * The workspace `ws` (ws_bytes, 256-byte aligned) is written.  If it is too
  * small for the hits found, returns MSPLAT_E_CAPACITY with *need_bytes set and
  * outputs untouched; the caller grows the workspace and calls again.
- * need_bytes may be NULL.
+ * need_bytes may be NULL.  A call whose rays find more than 2^31 - 1 hits in
+ * total returns MSPLAT_E_INVALID (split the rays over several calls).
  */
 int msplat_render_forward(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
                           const float* center, const float* scale, const float* quat,
@@ -150,7 +153,9 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* model, const mspl
                           void* ws, uint64_t ws_bytes, uint64_t* need_bytes, void* stream);
 
 /*
- * Backward of the forward call that last wrote `ws` with the same arguments.
+ * Backward of the forward call that last wrote `ws` with the same arguments
+ * (same network shape and precision, ray count and workspace size; a call
+ * that differs in any of them returns MSPLAT_E_STATE before launching work).
  * grad_rgb [R,3] = dL/drgb, grad_trans [R] = dL/dtrans (NULL = zero),
  * grad_feat [R,out_dim-4] (NULL = zero).
  * Outputs (overwritten, not accumulated): g_center [P,3], g_scale [P,3],

@@ -28,9 +28,8 @@ CFLAGS = [
 # The MLP kernels keep their matrix-core accumulators in ordinary VGPRs and
 # let the compiler sink instructions towards their uses: with the default AGPR
 # form the split-bfloat16 backward spilled about 450 bytes per lane to
-# scratch.  The VGPR form has crashed this compiler on some versions of the
-# wide networks' kernels; a unit whose compile fails with these options is
-# compiled again without them (slower code, same results).
+# scratch.  A unit that does not compile with these options fails the build
+# (a silent rebuild without them would give slower code that passes every test).
 MLP_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form", "-mllvm", "-sink-insts-to-avoid-spills"]
 EXTRA_FLAGS = {"mlp.hip": MLP_FLAGS, "mlp_bwd.hip": MLP_FLAGS,
                "mlp_wide.hip": MLP_FLAGS, "mlp_bwd_wide.hip": MLP_FLAGS}
@@ -38,18 +37,13 @@ EXTRA_FLAGS = {"mlp.hip": MLP_FLAGS, "mlp_bwd.hip": MLP_FLAGS,
 
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    extra = EXTRA_FLAGS.get(src, [])
-    for flags in ([extra, []] if extra else [[]]):
-        cmd = [HIPCC, "-c", *CFLAGS, *flags, os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode == 0:
-            return obj
-        if flags:
-            print(f"warning: hipcc failed for {src} with {' '.join(flags)}; compiling it without them",
-                  file=sys.stderr, flush=True)
-    raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    cmd = [HIPCC, "-c", *CFLAGS, *EXTRA_FLAGS.get(src, []), os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    return obj
 
 
 def build(verbose: bool = False) -> str:

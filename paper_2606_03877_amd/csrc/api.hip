@@ -55,7 +55,7 @@ bool shape_of(const msplat_model* m, NetShape* n) {
   n->D = m->hidden_layers;
   n->NOUT = m->out_dim;
   n->prec = m->precision;
-  if (n->P < 1 || n->L < 1 || n->W < 1 || n->D < 1 || n->NOUT < 4 || n->NOUT > 20) return false;
+  if (n->P < 1 || n->L < 1 || n->W < 1 || n->D < 1 || n->NOUT < 4 || n->NOUT > kMaxOut) return false;
   if (n->prec != MSPLAT_FP32 && n->prec != MSPLAT_BF16 && n->prec != MSPLAT_BF16X3) return false;
   int64_t in = 3 + 6 * n->L, np = 0, prev = in;
   for (int j = 0; j < n->D; ++j) {
@@ -320,6 +320,7 @@ int64_t msplat_num_params(const msplat_model* m) {
 int msplat_workspace_size(const msplat_model* m, int64_t num_rays, int64_t max_hits, uint64_t* bytes) {
   NetShape n;
   if (!bytes || !shape_of(m, &n) || num_rays < 0 || max_hits < 0) return MSPLAT_E_INVALID;
+  if (num_rays >= ((int64_t)1 << 31) || max_hits > kMaxHits) return MSPLAT_E_INVALID;
   if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
   *bytes = layout(n, num_rays, max_hits, nullptr, nullptr) + 32 * kAlign;
   return MSPLAT_OK;
@@ -352,16 +353,16 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.prim_nhit, (size_t)n.P * 4, s));
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.ray_off, 4, s));
   // min |g| starts at +inf
-  {
-    static const uint32_t inf_bits = 0x7f800000u;
-    HIPCHK(hipMemcpyAsync(&ws.counters->min_abs_g_bits, &inf_bits, 4, hipMemcpyHostToDevice, s));
-  }
+  STAGE(ctx, ST_ZERO, s, launch_fill(&ws.counters->min_abs_g_bits, 4, 0x7f800000u, s));
   STAGE(ctx, ST_PREPROCESS, s, launch_preprocess(ws, center, scale, quat, n.P, s));
   STAGE(ctx, ST_PACK, s, launch_pack_weights(n, ws, mlp, s));
   STAGE(ctx, ST_BIN_COUNT, s, launch_bin_count(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
-  STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n.P, n.n_params, s));
+  STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n, s));
   HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  // more hits than 32-bit offsets address: the 32-bit scans have wrapped, so
+  // nothing after them is launched
+  if (ctx->host_ctr->hit_total > kMaxHits) return MSPLAT_E_INVALID;
   int64_t nh = ctx->host_ctr->num_hits;
   int64_t items = ctx->host_ctr->num_work_items;
   if (nh > hcap) {
@@ -403,10 +404,14 @@ static bool slot_args_ok(const float* slots, int C, const void* a, const void* b
 // (the workspace layout follows from the model, the ray count and the byte
 // size: a call whose arguments differ from the forward's would read it at
 // other offsets, so that is refused)
+static bool same_net(const NetShape& a, const NetShape& b) {
+  return a.P == b.P && a.L == b.L && a.W == b.W && a.D == b.D && a.NOUT == b.NOUT && a.prec == b.prec &&
+         a.n_params == b.n_params;
+}
+
 static int forward_state(msplat_ctx* ctx, const NetShape& n, const Workspace& ws, const void* wsp, int64_t R,
                          uint64_t ws_bytes, int64_t hcap, hipStream_t s, int64_t* items, int64_t* nh) {
-  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes &&
-      ctx->last_shape.P == n.P && ctx->last_shape.n_params == n.n_params && ctx->last_shape.NOUT == n.NOUT) {
+  if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes && same_net(ctx->last_shape, n)) {
     *items = ctx->last_items;
     *nh = ctx->last_hits;
   } else {
@@ -414,8 +419,11 @@ static int forward_state(msplat_ctx* ctx, const NetShape& n, const Workspace& ws
     HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const DevCounters& c = *ctx->host_ctr;
+    // (the packed operands, whose size depends on the precision, precede the
+    // hit arrays: another network or precision would read them elsewhere)
     if (c.magic != kCountersMagic || c.num_rays != R || c.hit_cap != hcap || c.num_prims != n.P ||
-        c.num_params != n.n_params)
+        c.num_params != n.n_params || c.net[0] != n.L || c.net[1] != n.W || c.net[2] != n.D ||
+        c.net[3] != n.NOUT || c.net[4] != n.prec || c.net[5] != 0)
       return MSPLAT_E_STATE;
     *items = c.num_work_items;
     *nh = c.num_hits;

@@ -43,8 +43,10 @@ struct DevCounters {
   int64_t hit_cap;
   int32_t num_prims;
   int32_t num_params;
+  int64_t hit_total;         // hits counted in 64 bits (offsets and scans are 32-bit)
+  int32_t net[6];            // network the workspace was laid out for: L, W, D, NOUT, precision, kind
 };
-static_assert(sizeof(DevCounters) == 64, "counter block size");
+static_assert(sizeof(DevCounters) == 96, "counter block size");
 constexpr uint32_t kCountersMagic = 0x4d53504cu;
 
 // Workspace layout: every section 256-byte aligned, sized from (model, R, H).
@@ -228,6 +230,10 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 struct NetShape {
   int P, L, W, D, NOUT, prec, n_params;
 };
+// hits of one call: offsets and scans are 32-bit
+constexpr int64_t kMaxHits = 0x7fffffffLL;
+// outputs of a network: RGB, density and up to 16 feature channels
+constexpr int kMaxOut = 20;
 
 // geometry.hip
 hipError_t launch_preprocess(const Workspace& ws, const float* center, const float* scale,
@@ -235,7 +241,7 @@ hipError_t launch_preprocess(const Workspace& ws, const float* center, const flo
 hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float* ray_d,
                             const float* center, const float* scale, const float* quat, int64_t R,
                             int P, const msplat_opts& o, hipStream_t s);
-hipError_t launch_scans(const Workspace& ws, int64_t R, int P, int n_params, hipStream_t s);
+hipError_t launch_scans(const Workspace& ws, int64_t R, const NetShape& n, hipStream_t s);
 hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float* ray_d,
                            const float* center, const float* scale, const float* quat,
                            int64_t R, int P, const msplat_opts& o, hipStream_t s);
@@ -249,6 +255,8 @@ hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t 
 hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
                                float* g_quat, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+// every 32-bit word of [p, p + bytes) set to value (a kernel: no memset node in a captured graph)
+hipError_t launch_fill(void* p, size_t bytes, uint32_t value, hipStream_t s);
 // slot features (slots.hip)
 hipError_t launch_slot_forward(const Workspace& ws, int64_t R, const float* slots, int C, float* out,
                                hipStream_t s);

@@ -339,27 +339,31 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
   }
   if (valid) ray_cnt[ray + 1] = nhit;
   int64_t ws = wave_sum(nsamp);
+  int64_t wh = wave_sum((int64_t)nhit);
   int wf = wave_sum(nfall);
   float wm = wave_min(min_g);
   // the workgroup's waves combine their counters in LDS first: one set of
   // atomics per workgroup (same-address atomics from every wave serialise)
-  __shared__ unsigned long long bs_samp;
+  __shared__ unsigned long long bs_samp, bs_hits;
   __shared__ int bs_fall;
   __shared__ uint32_t bs_ming;
   if (threadIdx.x == 0) {
     bs_samp = 0ull;
+    bs_hits = 0ull;
     bs_fall = 0;
     bs_ming = 0x7f7fffffu;
   }
   __syncthreads();
   if (lane == 0) {
     atomicAdd(&bs_samp, (unsigned long long)ws);
+    atomicAdd(&bs_hits, (unsigned long long)wh);
     atomicAdd(&bs_fall, wf);
     atomicMin(&bs_ming, __float_as_uint(wm));
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     atomicAdd((unsigned long long*)&ctr->num_samples, bs_samp);
+    atomicAdd((unsigned long long*)&ctr->hit_total, bs_hits);
     if (bs_fall) atomicAdd(&ctr->num_fallbacks, bs_fall);
     atomicMin(&ctr->min_abs_g_bits, bs_ming);
   }
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
                                                         int32_t* __restrict__ wi_off, int P,
                                                         const int32_t* __restrict__ ray_off,
                                                         int64_t R, DevCounters* __restrict__ ctr,
-                                                        int64_t hit_cap, int n_params) {
+                                                        int64_t hit_cap, NetShape net) {
   __shared__ int32_t wsum[2][4];
   __shared__ int32_t carry[2];
   if (threadIdx.x == 0) carry[0] = carry[1] = 0;
@@ -484,7 +488,13 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
     ctr->num_rays = R;
     ctr->hit_cap = hit_cap;
     ctr->num_prims = P;
-    ctr->num_params = n_params;
+    ctr->num_params = net.n_params;
+    ctr->net[0] = net.L;
+    ctr->net[1] = net.W;
+    ctr->net[2] = net.D;
+    ctr->net[3] = net.NOUT;
+    ctr->net[4] = net.prec;
+    ctr->net[5] = 0;
     ctr->magic = kCountersMagic;
   }
 }
@@ -861,8 +871,8 @@ __global__ __launch_bounds__(256) void composite_kernel(Workspace ws, int64_t R,
   int64_t a = ws.ray_off[ray], b = ws.ray_off[ray + 1];
   int64_t H = ws.hit_cap;
   float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-  float f[16];
-  for (int k = 0; k < 16; ++k) f[k] = 0.f;
+  float f[kMaxOut - 4];
+  for (int k = 0; k < kMaxOut - 4; ++k) f[k] = 0.f;
   float shi = 0.f, slo = 0.f;
   bool stopped = false;
   for (int64_t j = a; j < b; ++j) {
@@ -1078,24 +1088,26 @@ __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* 
   g_quat[4 * i + 3] = (dz - z * dot) * inv;
 }
 
-__global__ void zero_kernel(uint32_t* __restrict__ p, int64_t n) {
+__global__ void fill_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) p[i] = 0u;
+  for (; i < n; i += stride) p[i] = v;
 }
 
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
 
-hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+hipError_t launch_fill(void* p, size_t bytes, uint32_t value, hipStream_t s) {
   int64_t n = (int64_t)(bytes / 4);
   if (n == 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t*)p, n, value);
   return hipGetLastError();
 }
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) { return launch_fill(p, bytes, 0u, s); }
 
 hipError_t launch_preprocess(const Workspace& ws, const float* center, const float* scale,
                              const float* quat, int P, hipStream_t s) {
@@ -1120,7 +1132,8 @@ hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float
   return hipGetLastError();
 }
 
-hipError_t launch_scans(const Workspace& ws, int64_t R, int P, int n_params, hipStream_t s) {
+hipError_t launch_scans(const Workspace& ws, int64_t R, const NetShape& net, hipStream_t s) {
+  const int P = net.P;
   // ray_off[0] = 0 and ray_off[1..R] hold counts: inclusive scan of [1..R]
   int64_t n = R;
   int32_t* data = ws.ray_off + 1;
@@ -1134,7 +1147,7 @@ hipError_t launch_scans(const Workspace& ws, int64_t R, int P, int n_params, hip
   }
   hipLaunchKernelGGL(prim_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_nhit,
                      ws.prim_off, ws.prim_cursor, ws.wi_off, P, (const int32_t*)ws.ray_off, R,
-                     ws.counters, ws.hit_cap, n_params);
+                     ws.counters, ws.hit_cap, net);
   return hipGetLastError();
 }
 

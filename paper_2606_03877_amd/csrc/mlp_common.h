@@ -84,7 +84,7 @@ struct Net {
   static constexpr bool PASSES = false;
   static_assert(L % 2 == 0, "encoding split needs an even number of levels");
   static_assert(W % 32 == 0, "hidden width must be a multiple of 32");
-  static_assert(NOUT >= 4 && NOUT <= 24, "4..24 outputs");
+  static_assert(NOUT >= 4 && NOUT <= kMaxOut, "4 to kMaxOut outputs (the compositor holds kMaxOut - 4 features)");
 
   // forward layer j: k-steps, row blocks, padded k-steps
   __host__ __device__ static constexpr int fks(int j) { return j == 0 ? ENC_KS : HID_KS; }

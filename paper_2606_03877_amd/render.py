@@ -257,11 +257,8 @@ class Renderer:
         g_scale = torch.empty((P, 3), dtype=torch.float32, device=self.device)
         g_quat = torch.empty((P, 4), dtype=torch.float32, device=self.device)
         g_mlp = torch.empty((P, self.n_params), dtype=torch.float32, device=self.device)
-        grad_rgb = grad_rgb.contiguous().float()
-        if grad_trans is not None:
-            grad_trans = grad_trans.contiguous().float()
-        if grad_feat is not None:
-            grad_feat = grad_feat.contiguous().float()
+        self.check_inputs(center, scale, quat, mlp, ray_o, ray_d)
+        grad_rgb, grad_trans, grad_feat = self._upstream(ray_o.shape[0], grad_rgb, grad_trans, grad_feat)
         st = msplat_render_backward(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o,
                                     ray_d, grad_rgb, grad_trans, grad_feat, ws, g_center, g_scale,
                                     g_quat, g_mlp)
@@ -269,8 +266,23 @@ class Renderer:
             raise MsplatError(st, "msplat_render_backward")
         return g_center, g_scale, g_quat, g_mlp
 
+    def _upstream(self, R: int, grad_rgb, grad_trans, grad_feat):
+        """Upstream gradients as contiguous float32 tensors of the shapes the
+        kernels index ([R,3], [R], [R, out_dim - 4])."""
+        grad_rgb = grad_rgb.contiguous().float()
+        _check(grad_rgb, "grad_rgb", (R, 3))
+        if grad_trans is not None:
+            grad_trans = grad_trans.contiguous().float()
+            _check(grad_trans, "grad_trans", (R,))
+        if grad_feat is not None:
+            grad_feat = grad_feat.contiguous().float()
+            _check(grad_feat, "grad_feat", (R, self.spec.out_dim - 4))
+        return grad_rgb, grad_trans, grad_feat
+
     def slot_forward(self, ws, slots, num_rays: int):
         """Slot features [R, C] of the forward that last wrote ``ws``; slots [P, 4, C]."""
+        if slots.dim() != 3:
+            raise ValueError(f"slots: expected shape ({self.spec.num_prims}, 4, C), got {tuple(slots.shape)}")
         _check(slots, "slots", (self.spec.num_prims, 4, slots.shape[-1]))
         out = torch.empty((num_rays, slots.shape[-1]), dtype=torch.float32, device=self.device)
         st = msplat_slot_forward(self.ctx, self.spec, slots, out, ws)
@@ -283,14 +295,18 @@ class Renderer:
         """backward() of a loss that also depends on slot_forward()'s features;
         returns (g_center, g_scale, g_quat, g_mlp, g_slots)."""
         P = self.spec.num_prims
-        g = [torch.empty(sh, dtype=torch.float32, device=self.device)
-             for sh in ((P, 3), (P, 3), (P, 4), (P, self.n_params), tuple(slots.shape))]
-        grad_rgb = grad_rgb.contiguous().float()
+        R = ray_o.shape[0]
+        self.check_inputs(center, scale, quat, mlp, ray_o, ray_d)
+        if slots.dim() != 3:
+            raise ValueError(f"slots: expected shape ({P}, 4, C), got {tuple(slots.shape)}")
+        C = slots.shape[-1]
+        slots = slots.contiguous().float()
+        _check(slots, "slots", (P, 4, C))
         grad_slot = grad_slot.contiguous().float()
-        if grad_trans is not None:
-            grad_trans = grad_trans.contiguous().float()
-        if grad_feat is not None:
-            grad_feat = grad_feat.contiguous().float()
+        _check(grad_slot, "grad_slot", (R, C))
+        g = [torch.empty(sh, dtype=torch.float32, device=self.device)
+             for sh in ((P, 3), (P, 3), (P, 4), (P, self.n_params), (P, 4, C))]
+        grad_rgb, grad_trans, grad_feat = self._upstream(R, grad_rgb, grad_trans, grad_feat)
         st = msplat_render_backward_slots(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o,
                                           ray_d, grad_rgb, grad_trans, grad_feat, slots, grad_slot, ws, *g)
         if st != _lib.MSPLAT_OK:

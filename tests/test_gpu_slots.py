@@ -142,3 +142,58 @@ def test_calls_on_an_earlier_workspace_check_its_layout():
     assert msplat_slot_forward(r.ctx, r.spec, slots, out, ws1) == _lib.MSPLAT_OK
     more = torch.empty((len(o) + 64, 8), device="cuda")
     assert msplat_slot_forward(r.ctx, r.spec, slots, more, ws1) == _lib.MSPLAT_E_STATE
+
+
+@pytest.mark.parametrize("fast_path", [True, False])
+def test_another_precision_on_the_same_workspace_is_refused(fast_path):
+    """The packed operands (whose size depends on the precision) precede the
+    hit arrays, so a backward or slot call with another precision than the
+    forward's would read the hits at other offsets: refused with
+    MSPLAT_E_STATE before any launch, both when the workspace is the
+    context's last one and when its recorded identity is read."""
+    from paper_2606_03877_amd import (NetSpec, msplat_render_backward, msplat_slot_forward, _lib)
+    ci = 0
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 32, 16)
+    g = gpu_render(ci, "fp32", sc, o, d, opts_of(cfg))
+    r = g["renderer"]
+    t, to, td = g["dev"]
+    ws1 = g["ws"]
+    if not fast_path:
+        r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to[:64], td[:64])
+    other = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim, "bf16x3")
+    P, R = cfg.num_prims, len(o)
+    gr = torch.zeros((R, 3), device="cuda")
+    outs = [torch.full(sh, 7.0, device="cuda") for sh in ((P, 3), (P, 3), (P, 4), (P, r.n_params))]
+    st = msplat_render_backward(r.ctx, other, r.opts, t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                gr, None, None, ws1, *outs)
+    assert st == _lib.MSPLAT_E_STATE
+    torch.cuda.synchronize()
+    assert all(bool((x == 7.0).all()) for x in outs)   # nothing was launched
+    slots = torch.zeros((P, 4, 8), device="cuda")
+    out = torch.empty((R, 8), device="cuda")
+    assert msplat_slot_forward(r.ctx, other, slots, out, ws1) == _lib.MSPLAT_E_STATE
+    # the forward's own precision is still accepted
+    assert msplat_slot_forward(r.ctx, r.spec, slots, out, ws1) == _lib.MSPLAT_OK
+
+
+def test_backward_checks_upstream_gradient_shapes():
+    ci = 0
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 16, 8)
+    g = gpu_render(ci, "fp32", sc, o, d, opts_of(cfg))
+    r = g["renderer"]
+    t, to, td = g["dev"]
+    R = len(o)
+    with pytest.raises(ValueError):
+        r.backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td, torch.zeros((R - 1, 3),
+                                                                                               device="cuda"))
+    slots = torch.zeros((cfg.num_prims, 4, 8), device="cuda")
+    with pytest.raises(ValueError):
+        r.backward_slots(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                         torch.zeros((R, 3), device="cuda"), slots, torch.zeros((R, 4), device="cuda"))
+    with pytest.raises(ValueError):
+        r.backward_slots(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                         torch.zeros((R, 3), device="cuda"), slots[:, 0], torch.zeros((R, 8), device="cuda"))

@@ -67,5 +67,9 @@ def test_host_argument_checks(lib):
     small = out.value
     assert lib.msplat_workspace_size(ctypes.byref(ok), 4096, 100000, ctypes.byref(out)) == _lib.MSPLAT_OK
     assert out.value > small
+    # hit lists are addressed with 32-bit offsets: at most 2^31 - 1 hits and rays per call
+    assert lib.msplat_workspace_size(ctypes.byref(ok), 4096, 2 ** 31 - 1, ctypes.byref(out)) == _lib.MSPLAT_OK
+    assert lib.msplat_workspace_size(ctypes.byref(ok), 4096, 2 ** 31, ctypes.byref(out)) == _lib.MSPLAT_E_INVALID
+    assert lib.msplat_workspace_size(ctypes.byref(ok), 2 ** 31, 10, ctypes.byref(out)) == _lib.MSPLAT_E_INVALID
     h = ctypes.c_void_p()
     assert lib.msplat_create(-1, ctypes.byref(h)) in (_lib.MSPLAT_E_INVALID, _lib.MSPLAT_E_HIP)
