@@ -299,10 +299,14 @@ def traffic_from_profiles(kernel: str, workload: str, precision: str):
 # feature channels):
 #   bin_count: ray origin and direction read (24 B) and its hit count written
 #     (4 B) per ray; each primitive's 160-byte frame record read once;
-#   bin_fill: ray read (24 B) and its offset (4 B) per ray; the hit record
-#     written (primitive, ray, sample count, contact depth hi+lo, half chord,
-#     chord start and bin width hi+lo, contact point and direction hi+lo, the
-#     per-primitive list entry: 92 B) per hit;
+#   bin_fill: ray read (24 B) and its offset (4 B) per ray; per hit the
+#     depth-ordered entry written (primitive, ray, sample count, contact depth
+#     hi+lo, half chord: 24 B);
+#   hit_records: per ray its origin and direction (24 B); per hit the entry
+#     read (primitive, ray, sample count, contact depth hi+lo: 20 B) and the
+#     record written (contact depth hi+lo, half chord, chord start and bin
+#     width hi+lo, contact point and direction hi+lo, sample count, the
+#     per-primitive list entry: 96 B);
 #   composite: ray offsets (8 B) read and colour, transmittance and the kept
 #     transmittance (20 B) written per ray; per hit the optical depth, sample
 #     count and colour sums read (8 + 4 NC B), the composited count and the
@@ -312,7 +316,8 @@ def traffic_from_profiles(kernel: str, workload: str, precision: str):
 #     and colour sums read (12 + 4 NC B), three backward scalars written (12 B).
 def hbm_bytes(kernel: str, R: int, H: int, P: int, nc: int) -> int:
     return {"bin_count": 28 * R + 160 * P,
-            "bin_fill": 28 * R + 92 * H,
+            "bin_fill": 28 * R + 24 * H,
+            "hit_records": 24 * R + 116 * H,
             "composite": 28 * R + (20 + 4 * nc) * H,
             "composite_adjoint": 24 * R + (24 + 4 * nc) * H}[kernel]
 
@@ -320,7 +325,7 @@ def hbm_bytes(kernel: str, R: int, H: int, P: int, nc: int) -> int:
 def hbm_rooflines(cfg, leg, workload_key, precision):
     st = leg["stats"]
     out = {}
-    for k in ("bin_count", "bin_fill", "composite", "composite_adjoint"):
+    for k in ("bin_count", "bin_fill", "hit_records", "composite", "composite_adjoint"):
         v = leg["stages"].get(k)
         if not v or v[1] == 0:
             continue
@@ -384,6 +389,89 @@ def nested_workload(ci, steps, warmup):
             "stages_ms_per_step": {k: v[0] / steps for k, v in leg["stages"].items() if v[1] > 0}}
 
 
+def contact_leg(steps, warmup, n_check=256):
+    """The paper's own primitive (one interaction per hit at the contact
+    point, 72-32-32-4 networks on the encoded [d; delta]) on its 800x800
+    frame of 2048 primitives: training-step and forward rates in the split
+    BF16 and FP32 forms, RGB against the FP64 oracle on seeded rays, and the
+    dominant kernel's roofline."""
+    import torch
+    import oracle
+    import synth
+    from oracle.contact import ContactModel, render_contact
+    from paper_2606_03877_amd import NetSpec, RenderOpts, Renderer, render, msplat_profile_enable, msplat_profile_read
+    cfg = synth.CONFIGS[6]
+    sc, o, d, prm, ro, rd = device_inputs(cfg)
+    R = len(o)
+    sc_t = synth.make_scene(cfg, seed=1000 * cfg.idx + 10)
+    out = {"workload": workload_name(cfg).replace("K=1", "one interaction per hit (contact point)"), "rays": R}
+    target = None
+    for prec in ("bf16x3", "fp32"):
+        spec = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim, prec,
+                       primitive="contact")
+        r = Renderer(spec, RenderOpts(samples_fixed=1, t_stop=cfg.t_stop, jitter=0))
+        if target is None:
+            pt = {k: torch.from_numpy(v).cuda() for k, v in sc_t.items()}
+            with torch.no_grad():
+                target = r.forward(pt["center"], pt["scale"], pt["quat"], pt["mlp"], ro, rd)[0].clone()
+        leaf = {k: v.clone().requires_grad_(True) for k, v in prm.items()}
+
+        def step():
+            for v in leaf.values():
+                v.grad = None
+            rgb, _, _ = render(r, leaf["center"], leaf["scale"], leaf["quat"], leaf["mlp"], ro, rd)
+            ((rgb - target) ** 2).mean().backward()
+
+        n = steps if prec == "bf16x3" else max(3, steps // 4)
+        with torch.autograd.set_multithreading_enabled(False):
+            msplat_profile_enable(r.ctx, True)
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            msplat_profile_enable(r.ctx, True)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        stages = msplat_profile_read(r.ctx)
+        msplat_profile_enable(r.ctx, False)
+        with torch.no_grad():
+            r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)
+            torch.cuda.synchronize()
+            f0 = time.perf_counter()
+            for _ in range(n):
+                rgb, _, _, ws = r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)
+            torch.cuda.synchronize()
+            f1 = time.perf_counter()
+        st = r.stats(ws)
+        idx = np.sort(np.random.default_rng(17).choice(R, n_check, replace=False))
+        p = oracle.to_tensors(sc)
+        ref = render_contact(p["center"], p["scale"], p["quat"], p["mlp"], torch.from_numpy(o[idx].astype(np.float64)),
+                             torch.from_numpy(d[idx].astype(np.float64)),
+                             ContactModel(cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim),
+                             oracle.Opts(t_stop=cfg.t_stop))["rgb"].numpy()
+        per = {k: v[0] / v[1] for k, v in stages.items() if v[1] > 0}
+        dom = max(per, key=lambda k: stages[k][0])
+        leg = {"fwdbwd_ms": 1e3 * (t1 - t0) / n, "fwdbwd_rays_per_s": R * n / (t1 - t0),
+               "fwd_ms": 1e3 * (f1 - f0) / n, "fwd_rays_per_s": R * n / (f1 - f0),
+               "rgb_max_err_vs_fp64": float(np.abs(rgb.cpu().numpy()[idx] - ref).max()),
+               "stages_ms_per_step": {k: v[0] / n for k, v in stages.items() if v[1] > 0},
+               "dominant_kernel": dom, "dominant_avg_launch_ms": per[dom]}
+        if dom in ("mlp_forward", "mlp_backward"):
+            fl = mlp_flops_per_sample(cfg) * st["num_samples"] * (2 if dom == "mlp_backward" else 1)
+            ach = fl / (per[dom] * 1e-3) / 1e12
+            leg["roofline"] = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["bf16"],
+                               "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["bf16"]}
+        else:
+            leg["hbm_rooflines"] = hbm_rooflines(cfg, {"stats": st, "stages": stages}, "config6", prec)
+        out[prec] = leg
+        out["hits"] = int(st["num_hits"])
+    out["speedup_vs_fp32"] = {"fwd": out["bf16x3"]["fwd_rays_per_s"] / out["fp32"]["fwd_rays_per_s"],
+                              "fwdbwd": out["bf16x3"]["fwdbwd_rays_per_s"] / out["fp32"]["fwdbwd_rays_per_s"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -395,6 +483,7 @@ def main():
     ap.add_argument("--no-tile", action="store_true", help="skip the tile-order leg")
     ap.add_argument("--no-slots", action="store_true", help="skip the slot-feature leg")
     ap.add_argument("--no-nested", action="store_true", help="skip the 800x800 single-frame object")
+    ap.add_argument("--no-contact", action="store_true", help="skip the contact-point primitive object")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 256 MiB device-to-device copy 5 times (reference kernel "
@@ -480,6 +569,11 @@ def main():
         nested = nested_workload(1, 20, 3)
         print(f"# config 1 fwd+bwd {nested['ms_per_step']:.3f} ms", file=sys.stderr, flush=True)
 
+    contact = None
+    if not args.no_contact:
+        contact = contact_leg(10, 2)
+        print(f"# contact primitive fwd+bwd {contact['bf16x3']['fwdbwd_ms']:.3f} ms", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cfg, sc, o, d, target.cpu().numpy(), opts, budget_s=args.cpu_budget)
@@ -511,6 +605,7 @@ def main():
         "tile_order": tile,
         "slot_features": slots,
         "config1_800x800": nested,
+        "contact_primitive": contact,
     }
     out["legs"] = {}
     for k, v in legs.items():

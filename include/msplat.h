@@ -50,13 +50,45 @@ typedef enum msplat_precision {
 } msplat_precision;
 
 /*
- * Per-primitive network (Sec. 3.2).  The input of a sample is its local
+ * The primitive a model renders.
+ *
+ * MSPLAT_CHORD: K samples of the chord the ray cuts from the ellipsoid of
+ *   semi-axes `scale` (see msplat_model); density zero outside it.
+ * MSPLAT_CONTACT: the paper's own primitive (Sec. 3.2-3.3, Sec. 4.1): one
+ *   interaction per ray and primitive, at the contact depth
+ *   t* = max(0, t_c), t_c = d^T Lambda (mu - o) / d^T Lambda d (Eq. 2), with
+ *   Lambda = R diag(scale)^-2 R^T.  The network reads x = [d; delta], the
+ *   ray direction and the residual delta = mu - (o + t* d), each of the six
+ *   components encoded as sin and cos of 2^l pi x_c for l < pe_freqs (no
+ *   identity term: 12 * pe_freqs inputs, 72 for pe_freqs = 6).  `scale`
+ *   holds the standard deviations of a Gaussian support: a ray interacts
+ *   with the primitive when it passes within 3 of them (t_c + eta > 0 on the
+ *   ellipsoid of semi-axes 3 * scale), in depth order of t_c.  The opacity
+ *   is alpha = 1 - exp(-sigma G delta_i), with the Gaussian falloff
+ *   G = exp(-|diag(scale)^-1 R^T delta|^2 / 2) at the contact point and the
+ *   thickness delta_i = sqrt(2 pi) / |diag(scale)^-1 R^T d| (the length over
+ *   which a unit Gaussian of this covariance integrates along the ray), so
+ *   that sigma G delta_i is the density's line integral along the ray when
+ *   t* = t_c.  The sample options (samples_*, jitter) do not apply; slot
+ *   features and the float64 checker are not available for it
+ *   (MSPLAT_E_UNSUPPORTED).
+ */
+typedef enum msplat_primitive {
+  MSPLAT_CHORD = 0,
+  MSPLAT_CONTACT = 1
+} msplat_primitive;
+
+/*
+ * Per-primitive network (Sec. 3.2).  The input of a chord sample is its local
  * position p (the scale-normalised ellipsoid frame) encoded as
  * [p, sin(2^l pi p), cos(2^l pi p) for l < pe_freqs]: 3 + 6*pe_freqs values.
  * Hidden layers use ReLU; outputs are RGB (sigmoid), density (softplus) and
  * out_dim-4 feature channels (identity), composited like RGB.
  * Compiled shapes (pe_freqs, hidden_width, hidden_layers, out_dim):
- *   (4, 32, 2, 4), (6, 64, 3, 4), (6, 64, 3, 20), (6, 128, 4, 20).  Others:
+ *   chord primitives (4, 32, 2, 4), (6, 64, 3, 4), (6, 64, 3, 20),
+ *   (6, 128, 4, 20); the contact-point primitive (6, 32, 2, 4), the paper's
+ *   72-32-32-4 network, in MSPLAT_FP32 and MSPLAT_BF16X3 (plain bfloat16
+ *   misses the 2e-3 colour bar on its 72 inputs).  Others:
  *   MSPLAT_E_UNSUPPORTED.  For networks wider than 64 the forward keeps in LDS
  *   what fits of the weights (all of them in BF16, the hi halves of the split
  *   form), the backward reads them from global memory and runs in two passes
@@ -69,6 +101,7 @@ typedef struct msplat_model {
   int32_t hidden_layers;
   int32_t out_dim;       /* 4 (RGB + density) or 4 + feature channels */
   int32_t precision;     /* msplat_precision */
+  int32_t primitive;     /* msplat_primitive */
 } msplat_model;
 
 /* Sampling and compositing options (Sec. 3.3). */
@@ -93,6 +126,9 @@ typedef struct msplat_opts {
                                ties broken by primitive index.  Meant for rays given
                                as 8x8 pixel tiles; hit sets and sample positions are
                                those of order 0, only the compositing order changes */
+  int32_t hits_per_item;    /* hits of one primitive per work item of the network
+                               kernels: 16, 32 or 64; 0 = the choice msplat_autotune
+                               recorded for this network and workload (64 if none) */
 } msplat_opts;
 
 /* Counters filled by the forward pass (read with msplat_get_stats). */
@@ -104,7 +140,7 @@ typedef struct msplat_stats {
   int64_t num_terminated;     /* rays that stopped early */
   int64_t num_fallbacks;      /* hit tests decided in double-float arithmetic */
   float min_abs_g;            /* smallest |1 - |p_c|^2| seen among tested pairs */
-  float reserved;
+  int32_t hits_per_item;      /* work-item size the network kernels ran with */
 } msplat_stats;
 
 typedef struct msplat_ctx msplat_ctx;
@@ -217,6 +253,27 @@ int msplat_render_backward_slots(msplat_ctx* ctx, const msplat_model* model, con
 int msplat_profile_enable(msplat_ctx* ctx, int enable);
 int msplat_profile_read(msplat_ctx* ctx, int max_stages, const char** names, double* total_ms,
                         int64_t* launches, int* num_stages);
+
+/*
+ * Work-item autotuner (an implementation choice, not part of the method).
+ * The network kernels take the hits of one primitive in work items of
+ * hits_per_item hits, one workgroup each; the best size depends on the
+ * network and on the workload's hit and sample counts.  This call runs the
+ * forward (and, when grad_rgb is not NULL, the backward) of the given
+ * arguments once per candidate size (64, 32, 16), times each on `stream`
+ * with HIP events, records the fastest for this context, network and
+ * workload (ray count, primitive count and sample options) and writes it to
+ * *chosen.  Later calls with opts->hits_per_item == 0 and the same network
+ * and workload use it.  Arguments as for msplat_render_forward and
+ * msplat_render_backward; every output buffer is overwritten (with the last
+ * candidate's results) and ws is left as a forward of the last candidate
+ * wrote it.  Synchronises `stream`.
+ */
+int msplat_autotune(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                    const float* center, const float* scale, const float* quat, const float* mlp,
+                    const float* ray_o, const float* ray_d, int64_t num_rays, float* rgb, float* trans,
+                    float* feat, const float* grad_rgb, void* ws, uint64_t ws_bytes, float* g_center,
+                    float* g_scale, float* g_quat, float* g_mlp, int32_t* chosen, void* stream);
 
 /* Counters of the last forward that used `ws` (synchronises `stream`). */
 int msplat_get_stats(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, msplat_stats* out,

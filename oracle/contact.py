@@ -133,7 +133,7 @@ def render_contact(center, scale, quat, mlp, ray_o, ray_d, model: ContactModel, 
     rows = []
     for p in np.unique(pp):
         idx = torch.from_numpy(np.nonzero(pp == p)[0])
-        rows.append((idx, mlp_apply(mlp[int(p)], gam[idx], model)))
+        rows.append((idx, mlp_apply(mlp[int(p)], gam[idx], model, opts.gate_form)))
     if rows:
         raw = raw.index_put((torch.cat([i for i, _ in rows]),), torch.cat([v for _, v in rows]))
     col = torch.sigmoid(raw[:, :3])
@@ -175,7 +175,7 @@ def contact_margins(center, scale, quat, mlp, ray_o, ray_d, model: ContactModel,
         hm = np.full(len(rr), np.inf)
         for p in np.unique(out["prim"]):
             idx = np.nonzero(out["prim"] == p)[0]
-            hm[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model)
+            hm[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model, opts.gate_form)
         np.minimum.at(m, rr, hm)
     return out, m
 

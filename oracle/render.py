@@ -27,6 +27,12 @@ Readings taken where the paper leaves a choice open:
     camera, the ray through the tile centre up to a second-order term);
   * early termination stops after the first sample whose transmittance falls
     below the threshold;
+  * ReLU gates are decisions a floating-point sum takes: with
+    Opts.gate_form "bf16" or "bf16x3" they are taken in that arithmetic
+    (``gate_preacts``: operands rounded to bfloat16, or carried as bfloat16
+    hi + lo pairs multiplied as hi*hi + hi*lo + lo*hi, sums exact), and the
+    network is then evaluated and differentiated in FP64 on the branch those
+    gates select (a = z where the gate is open, 0 where it is closed);
   * slot features (option): the local offset u of a hit is taken at the
     unclamped contact point (u = -p_c; the paper's clamp moves the point to the
     ray origin only when the camera is inside the support), the clip to the
@@ -47,7 +53,8 @@ import torch
 from .pcg import sample_offsets
 
 __all__ = ["Model", "Opts", "quat_to_rotmat", "local_frame", "intersect",
-           "encode", "mlp_apply", "relu_noise", "relu_margin", "packet_centres", "render",
+           "encode", "mlp_apply", "bf16_round", "split_bf16", "gate_preacts", "relu_noise", "relu_margin",
+           "packet_centres", "render",
            "TETRA", "slot_gates"]
 
 PACKET = 64   # rays per packet (an 8x8 pixel tile)
@@ -84,6 +91,7 @@ class Opts:
     jitter_seed: int = 0
     background: Sequence[float] = (0.0, 0.0, 0.0)
     order: int = 0                   # 0 = each ray's own contact depth; 1 = tile order
+    gate_form: str = "fp64"          # arithmetic of the ReLU gate decisions: fp64 | bf16 | bf16x3
 
 
 def _where(cond, a, b):
@@ -152,11 +160,67 @@ def encode(p: torch.Tensor, n_freqs: int) -> torch.Tensor:
     return torch.cat(feats, dim=-1)
 
 
-def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model) -> torch.Tensor:
-    """One primitive's MLP: ReLU hidden layers, linear output (raw values)."""
+def bf16_round(v) -> np.ndarray:
+    """Nearest bfloat16 value of each float32 value (ties to even), as float64:
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of a float32, so the low 16 bits are rounded away."""
+    f = np.ascontiguousarray(np.asarray(v, np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def split_bf16(v):
+    """(hi, lo) = (bf16(v), bf16(v - hi)) of the float32 values of v."""
+    f = np.asarray(v, np.float64).astype(np.float32).astype(np.float64)
+    hi = bf16_round(f)
+    return hi, bf16_round(f - hi)
+
+
+def _gate_dot(a, w, form):
+    """a @ w.T with both operands in the given bfloat16 form; sums exact."""
+    if form == "bf16":
+        return bf16_round(a) @ bf16_round(w).T
+    ah, al = split_bf16(a)
+    wh, wl = split_bf16(w)
+    return ah @ wh.T + al @ wh.T + ah @ wl.T
+
+
+def gate_preacts(theta, x, model: Model, form: str):
+    """Pre-activations of the hidden layers as the gate decisions see them in
+    the bfloat16 forms: each layer's input (float32 values) and weights are
+    rounded to bfloat16 (form "bf16") or split into hi + lo pairs ("bf16x3"),
+    products summed without further rounding; the first layer's bias enters
+    as the weight of a constant input 1 (in the same form), the other biases
+    as float32 values.  Returns [z] per hidden layer, float64 [rows, width]."""
+    th = np.asarray(theta.detach().real if torch.is_tensor(theta) else theta, np.float64)
+    h = np.asarray(x.detach().real if torch.is_tensor(x) else x, np.float64).astype(np.float32).astype(np.float64)
+    out = []
+    off = 0
+    for li, (fi, fo) in enumerate(model.layer_dims()[:-1]):
+        w = th[off:off + fi * fo].reshape(fo, fi)
+        off += fi * fo
+        b = th[off:off + fo].astype(np.float32).astype(np.float64)
+        off += fo
+        if li == 0:
+            z = _gate_dot(np.concatenate([h, np.ones((h.shape[0], 1))], 1), np.concatenate([w, b[:, None]], 1), form)
+        else:
+            z = _gate_dot(h, w, form) + b
+        out.append(z)
+        h = np.maximum(z, 0.0).astype(np.float32).astype(np.float64)
+    return out
+
+
+def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model, gate_form: str = "fp64") -> torch.Tensor:
+    """One primitive's MLP: ReLU hidden layers, linear output (raw values).
+    gate_form other than "fp64": the ReLU gates are taken from
+    ``gate_preacts`` in that form, and a = z where open, 0 where closed."""
     off = 0
     h = x
     dims = model.layer_dims()
+    gates = None
+    if gate_form != "fp64":
+        gates = [torch.from_numpy(z > 0) for z in gate_preacts(theta, x, model, gate_form)]
     for li, (fi, fo) in enumerate(dims):
         w = theta[off:off + fi * fo].reshape(fo, fi)
         off += fi * fo
@@ -164,7 +228,8 @@ def mlp_apply(theta: torch.Tensor, x: torch.Tensor, model: Model) -> torch.Tenso
         off += fo
         h = h @ w.transpose(0, 1) + b
         if li < len(dims) - 1:
-            h = _where(h.real > 0, h, torch.zeros_like(h))
+            open_ = h.real > 0 if gates is None else gates[li]
+            h = _where(open_, h, torch.zeros_like(h))
     return h
 
 
@@ -201,15 +266,19 @@ def relu_noise(theta, x, model: Model):
     return out
 
 
-def relu_margin(theta, x, model: Model) -> np.ndarray:
+def relu_margin(theta, x, model: Model, gate_form: str = "fp64") -> np.ndarray:
     """Distance of each row's closest ReLU gate from its switching point in
     units of its rounding noise: min over hidden units of |z| / e
     (``relu_noise``).  An implementation with unit roundoff u takes a gate
     whose margin is within a small multiple of u either way with appreciable
     probability: such gates are decisions that two correct implementations
-    may take differently, and the gradient jumps there."""
+    may take differently, and the gradient jumps there.  With a bfloat16
+    gate_form, z is that form's pre-activation (``gate_preacts``)."""
     m = np.full(np.shape(x)[0], np.inf)
-    for z, e in relu_noise(theta, x, model):
+    noise = relu_noise(theta, x, model)
+    if gate_form != "fp64":
+        noise = [(zg, e) for zg, (_, e) in zip(gate_preacts(theta, x, model, gate_form), noise)]
+    for z, e in noise:
         with np.errstate(divide="ignore", invalid="ignore"):
             r = np.where(e > 0, np.abs(z) / e, np.inf)
         m = np.minimum(m, r.min(1))
@@ -333,7 +402,7 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
     out_rows = []
     for p in np.unique(sprim):
         idx = torch.from_numpy(np.nonzero(sprim == p)[0])
-        out_rows.append((idx, mlp_apply(mlp[int(p)], gam[idx], model)))
+        out_rows.append((idx, mlp_apply(mlp[int(p)], gam[idx], model, opts.gate_form)))
     if out_rows:
         raw = raw.index_put(tuple([torch.cat([i for i, _ in out_rows])]),
                             torch.cat([v for _, v in out_rows]))
@@ -397,7 +466,7 @@ def render(center, scale, quat, mlp, ray_o, ray_d, model: Model, opts: Opts,
         margin = np.full(len(hs), np.inf)
         for p in np.unique(sprim):
             idx = np.nonzero(sprim == p)[0]
-            margin[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model)
+            margin[idx] = relu_margin(mlp[int(p)], gam[torch.from_numpy(idx)], model, opts.gate_form)
         samples = {"hit": hs, "k": kk, "u": u, "t": tk, "p": pk, "c": col, "sigma": sig,
                    "f": feat, "tau": tau, "ray": sray, "relu_margin": margin}
     out = _pack(rgb, trans, fout, n_used, ray_off, pp, tc, eta, ta, tb, kh, isx, samples)

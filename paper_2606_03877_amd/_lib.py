@@ -18,6 +18,9 @@ MSPLAT_E_UNSUPPORTED = 3
 MSPLAT_E_HIP = 4
 MSPLAT_E_STATE = 5
 
+MSPLAT_CHORD = 0
+MSPLAT_CONTACT = 1
+
 MSPLAT_FP32 = 0
 MSPLAT_BF16 = 1
 MSPLAT_BF16X3 = 2
@@ -29,7 +32,8 @@ c_f64p = ctypes.POINTER(ctypes.c_double)
 class Model(ctypes.Structure):
     _fields_ = [("num_prims", ctypes.c_int32), ("pe_freqs", ctypes.c_int32),
                 ("hidden_width", ctypes.c_int32), ("hidden_layers", ctypes.c_int32),
-                ("out_dim", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("out_dim", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("primitive", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -37,14 +41,14 @@ class Opts(ctypes.Structure):
                 ("samples_max", ctypes.c_int32), ("samples_per_unit", ctypes.c_float),
                 ("t_stop", ctypes.c_float), ("jitter", ctypes.c_int32),
                 ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3),
-                ("order", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("hits_per_item", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("num_rays", ctypes.c_int64), ("num_hits", ctypes.c_int64),
                 ("num_samples", ctypes.c_int64), ("num_work_items", ctypes.c_int64),
                 ("num_terminated", ctypes.c_int64), ("num_fallbacks", ctypes.c_int64),
-                ("min_abs_g", ctypes.c_float), ("reserved", ctypes.c_float)]
+                ("min_abs_g", ctypes.c_float), ("hits_per_item", ctypes.c_int32)]
 
 
 EXPORTS = {
@@ -77,6 +81,14 @@ EXPORTS = {
         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p]),
+    "msplat_autotune": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts),
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_uint64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "msplat_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "msplat_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_char_p),

@@ -13,12 +13,12 @@ using namespace msplat;
 enum Stage {
   ST_ZERO, ST_PREPROCESS, ST_PACK, ST_BIN_COUNT, ST_SCAN, ST_BIN_FILL, ST_MLP_FWD, ST_COMPOSITE,
   ST_MLP_FIXUP, ST_COMP_ADJ, ST_MLP_BWD, ST_HIT_GEO, ST_GEO_FINAL, ST_SLOT_FWD, ST_SLOT_BWD_HITS,
-  ST_SLOT_BWD_PRIMS, ST_COUNT
+  ST_SLOT_BWD_PRIMS, ST_HIT_REC, ST_COUNT
 };
 static const char* kStageNames[ST_COUNT] = {
     "zero", "preprocess", "pack_weights", "bin_count", "scan", "bin_fill", "mlp_forward",
     "composite", "mlp_fixup", "composite_adjoint", "mlp_backward", "hit_geometry", "geo_finalize",
-    "slot_forward", "slot_backward_hits", "slot_backward_prims"};
+    "slot_forward", "slot_backward_hits", "slot_backward_prims", "hit_records"};
 constexpr int kRing = 64;
 struct StageTimer {
   hipEvent_t a[kRing], b[kRing];
@@ -28,9 +28,21 @@ struct StageTimer {
   bool created = false;
 };
 
+// work-item sizes recorded by msplat_autotune, per network and workload
+struct TuneEntry {
+  NetShape n;
+  int64_t rays;
+  int32_t samples_fixed, samples_min, samples_max, order;
+  float samples_per_unit;
+  int32_t hits_per_item;
+};
+constexpr int kTuneSlots = 32;
+
 struct msplat_ctx {
   int device;
   bool profiling = false;
+  TuneEntry tuned[kTuneSlots];
+  int num_tuned = 0;
   StageTimer timers[ST_COUNT];
   DevCounters* host_ctr;   // pinned host mirror of the device counters
   // record of the last successful forward (used to size the backward launch)
@@ -40,6 +52,7 @@ struct msplat_ctx {
   int64_t last_rays;
   uint64_t last_bytes;
   NetShape last_shape;
+  int32_t last_hpi;
 };
 
 namespace {
@@ -55,9 +68,11 @@ bool shape_of(const msplat_model* m, NetShape* n) {
   n->D = m->hidden_layers;
   n->NOUT = m->out_dim;
   n->prec = m->precision;
+  n->kind = m->primitive;
   if (n->P < 1 || n->L < 1 || n->W < 1 || n->D < 1 || n->NOUT < 4 || n->NOUT > kMaxOut) return false;
   if (n->prec != MSPLAT_FP32 && n->prec != MSPLAT_BF16 && n->prec != MSPLAT_BF16X3) return false;
-  int64_t in = 3 + 6 * n->L, np = 0, prev = in;
+  if (n->kind != MSPLAT_CHORD && n->kind != MSPLAT_CONTACT) return false;
+  int64_t in = n->kind == MSPLAT_CONTACT ? 12 * n->L : 3 + 6 * n->L, np = 0, prev = in;
   for (int j = 0; j < n->D; ++j) {
     np += prev * n->W + n->W;
     prev = n->W;
@@ -212,7 +227,35 @@ bool opts_ok(const msplat_opts* o) {
   }
   if (!(o->t_stop >= 0.f && o->t_stop < 1.f)) return false;
   if (o->order != 0 && o->order != 1) return false;
+  if (o->hits_per_item != 0 && o->hits_per_item != 16 && o->hits_per_item != 32 && o->hits_per_item != 64)
+    return false;
   return true;
+}
+
+bool tune_match(const TuneEntry& t, const NetShape& n, int64_t R, const msplat_opts& o) {
+  return t.n.P == n.P && t.n.L == n.L && t.n.W == n.W && t.n.D == n.D && t.n.NOUT == n.NOUT &&
+         t.n.prec == n.prec && t.n.kind == n.kind && t.rays == R && t.samples_fixed == o.samples_fixed &&
+         t.samples_min == o.samples_min && t.samples_max == o.samples_max && t.order == o.order &&
+         t.samples_per_unit == o.samples_per_unit;
+}
+
+// work-item size of a call: the option, else the recorded choice, else 64
+int32_t hits_per_item_of(const msplat_ctx* c, const NetShape& n, int64_t R, const msplat_opts& o) {
+  if (o.hits_per_item) return o.hits_per_item;
+  for (int i = 0; i < c->num_tuned; ++i)
+    if (tune_match(c->tuned[i], n, R, o)) return c->tuned[i].hits_per_item;
+  return kHitsPerItem;
+}
+
+// the options a call runs with: the contact-point primitive has one
+// interaction per hit (K = 1, no sample offsets)
+msplat_opts effective_opts(const NetShape& n, const msplat_opts& o) {
+  msplat_opts e = o;
+  if (n.kind == MSPLAT_CONTACT) {
+    e.samples_fixed = 1;
+    e.jitter = 0;
+  }
+  return e;
 }
 
 struct DeviceGuard {
@@ -332,6 +375,8 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
                           float* feat, void* wsp, uint64_t ws_bytes, uint64_t* need_bytes, void* stream) {
   NetShape n;
   if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  const msplat_opts eo = effective_opts(n, *o);
+  o = &eo;
   if (!center || !scale || !quat || !mlp || !wsp || R < 0 || R >= (int64_t)1 << 31) return MSPLAT_E_INVALID;
   if (R > 0 && (!ray_o || !ray_d || !rgb || !trans)) return MSPLAT_E_INVALID;
   int cf = n.NOUT - 4;
@@ -348,15 +393,16 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   }
   Workspace ws;
   layout(n, R, hcap, (uint8_t*)wsp, &ws);
+  ws.hits_per_item = hits_per_item_of(ctx, n, R, *o);
   ctx->last_ws = nullptr;
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.counters, sizeof(DevCounters), s));
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.prim_nhit, (size_t)n.P * 4, s));
   STAGE(ctx, ST_ZERO, s, launch_zero(ws.ray_off, 4, s));
   // min |g| starts at +inf
   STAGE(ctx, ST_ZERO, s, launch_fill(&ws.counters->min_abs_g_bits, 4, 0x7f800000u, s));
-  STAGE(ctx, ST_PREPROCESS, s, launch_preprocess(ws, center, scale, quat, n.P, s));
+  STAGE(ctx, ST_PREPROCESS, s, launch_preprocess(ws, center, scale, quat, n.P, n.kind, s));
   STAGE(ctx, ST_PACK, s, launch_pack_weights(n, ws, mlp, s));
-  STAGE(ctx, ST_BIN_COUNT, s, launch_bin_count(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
+  STAGE(ctx, ST_BIN_COUNT, s, launch_bin_count(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, n.kind, s));
   STAGE(ctx, ST_SCAN, s, launch_scans(ws, R, n, s));
   HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -370,7 +416,8 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
     return MSPLAT_E_CAPACITY;
   }
   if (need_bytes) *need_bytes = layout(n, R, nh, nullptr, nullptr) + 32 * kAlign;
-  STAGE(ctx, ST_BIN_FILL, s, launch_bin_fill(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, s));
+  STAGE(ctx, ST_BIN_FILL, s, launch_bin_fill(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, n.kind, s));
+  STAGE(ctx, ST_HIT_REC, s, launch_hit_records(ws, ray_o, ray_d, nh, n.kind, s));
   STAGE(ctx, ST_MLP_FWD, s, launch_mlp_forward(n, ws, *o, (int)items, 0, rgb, trans, feat, s));
   STAGE(ctx, ST_COMPOSITE, s, launch_composite(ws, R, *o, rgb, trans, feat, cf, s));
   if (o->t_stop > 0.f)
@@ -381,6 +428,7 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   ctx->last_rays = R;
   ctx->last_bytes = ws_bytes;
   ctx->last_shape = n;
+  ctx->last_hpi = ws.hits_per_item;
   return MSPLAT_OK;
 }
 
@@ -406,14 +454,15 @@ static bool slot_args_ok(const float* slots, int C, const void* a, const void* b
 // other offsets, so that is refused)
 static bool same_net(const NetShape& a, const NetShape& b) {
   return a.P == b.P && a.L == b.L && a.W == b.W && a.D == b.D && a.NOUT == b.NOUT && a.prec == b.prec &&
-         a.n_params == b.n_params;
+         a.n_params == b.n_params && a.kind == b.kind;
 }
 
-static int forward_state(msplat_ctx* ctx, const NetShape& n, const Workspace& ws, const void* wsp, int64_t R,
+static int forward_state(msplat_ctx* ctx, const NetShape& n, Workspace& ws, const void* wsp, int64_t R,
                          uint64_t ws_bytes, int64_t hcap, hipStream_t s, int64_t* items, int64_t* nh) {
   if (ctx->last_ws == wsp && ctx->last_rays == R && ctx->last_bytes == ws_bytes && same_net(ctx->last_shape, n)) {
     *items = ctx->last_items;
     *nh = ctx->last_hits;
+    ws.hits_per_item = ctx->last_hpi;
   } else {
     // workspace of an earlier forward: read its counters
     HIPCHK(hipMemcpyAsync(ctx->host_ctr, ws.counters, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
@@ -423,10 +472,12 @@ static int forward_state(msplat_ctx* ctx, const NetShape& n, const Workspace& ws
     // hit arrays: another network or precision would read them elsewhere)
     if (c.magic != kCountersMagic || c.num_rays != R || c.hit_cap != hcap || c.num_prims != n.P ||
         c.num_params != n.n_params || c.net[0] != n.L || c.net[1] != n.W || c.net[2] != n.D ||
-        c.net[3] != n.NOUT || c.net[4] != n.prec || c.net[5] != 0)
+        c.net[3] != n.NOUT || c.net[4] != n.prec || c.net[5] != n.kind)
       return MSPLAT_E_STATE;
+    if (c.hits_per_item != 16 && c.hits_per_item != 32 && c.hits_per_item != 64) return MSPLAT_E_STATE;
     *items = c.num_work_items;
     *nh = c.num_hits;
+    ws.hits_per_item = c.hits_per_item;
   }
   if (*nh > hcap) return MSPLAT_E_STATE;
   return MSPLAT_OK;
@@ -439,13 +490,15 @@ static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_op
                          float* g_quat, float* g_mlp, const SlotArgs* sa, void* stream) {
   NetShape n;
   if (!ctx || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  const msplat_opts eo = effective_opts(n, *o);
+  o = &eo;
   if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
   if (!g_center || !g_scale || !g_quat || !g_mlp) return MSPLAT_E_INVALID;
   if (R > 0 && (!ray_o || !ray_d || !grad_rgb)) return MSPLAT_E_INVALID;
   if (sa && (!slot_args_ok(sa->slots, sa->C, sa->grad_slot, sa->g_slots) || !sa->g_slots ||
              (R > 0 && !sa->grad_slot)))
     return MSPLAT_E_INVALID;
-  if (!mlp_supported(n)) return MSPLAT_E_UNSUPPORTED;
+  if (!mlp_supported(n) || (sa && n.kind != MSPLAT_CHORD)) return MSPLAT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   int64_t hcap = capacity_of(n, R, ws_bytes);
@@ -472,8 +525,8 @@ static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_op
     STAGE(ctx, ST_SLOT_BWD_PRIMS, s,
           launch_slot_backward_prims(ws, n.P, (int)items, sa->slots, sa->C, sa->grad_slot, ray_d, sa->g_slots,
                                      s));
-  STAGE(ctx, ST_HIT_GEO, s, launch_hit_geometry(ws, ray_d, nh, s));
-  STAGE(ctx, ST_GEO_FINAL, s, launch_geo_finalize(ws, n.P, g_center, g_scale, g_quat, s));
+  STAGE(ctx, ST_HIT_GEO, s, launch_hit_geometry(ws, ray_d, nh, n.kind, s));
+  STAGE(ctx, ST_GEO_FINAL, s, launch_geo_finalize(ws, n.P, g_center, g_scale, g_quat, n.kind, s));
   return MSPLAT_OK;
 }
 
@@ -492,6 +545,7 @@ int msplat_slot_forward(msplat_ctx* ctx, const msplat_model* m, const float* slo
   NetShape n;
   if (!ctx || !shape_of(m, &n) || !wsp || R < 0) return MSPLAT_E_INVALID;
   if (!slot_args_ok(slots, slot_dim, out, nullptr) || (R > 0 && !out)) return MSPLAT_E_INVALID;
+  if (n.kind != MSPLAT_CHORD) return MSPLAT_E_UNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(ctx->device);
   int64_t hcap = capacity_of(n, R, ws_bytes);
@@ -516,6 +570,62 @@ int msplat_render_backward_slots(msplat_ctx* ctx, const msplat_model* m, const m
                        wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, &sa, stream);
 }
 
+int msplat_autotune(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o, const float* center,
+                    const float* scale, const float* quat, const float* mlp, const float* ray_o, const float* ray_d,
+                    int64_t R, float* rgb, float* trans, float* feat, const float* grad_rgb, void* wsp,
+                    uint64_t ws_bytes, float* g_center, float* g_scale, float* g_quat, float* g_mlp,
+                    int32_t* chosen, void* stream) {
+  NetShape n;
+  if (!ctx || !chosen || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
+  if (grad_rgb && (!g_center || !g_scale || !g_quat || !g_mlp)) return MSPLAT_E_INVALID;
+  const msplat_opts key = effective_opts(n, *o);
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(ctx->device);
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return MSPLAT_E_HIP;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return MSPLAT_E_HIP;
+  }
+  const int32_t cand[3] = {64, 32, 16};
+  int32_t best = 0;
+  float best_ms = 0.f;
+  int st = MSPLAT_OK;
+  for (int c = 0; c < 3 && st == MSPLAT_OK; ++c) {
+    msplat_opts oc = *o;
+    oc.hits_per_item = cand[c];
+    for (int rep = 0; rep < 2 && st == MSPLAT_OK; ++rep) {   // the first run warms up
+      if (rep == 1 && hipEventRecord(ev[0], s) != hipSuccess) st = MSPLAT_E_HIP;
+      if (st == MSPLAT_OK)
+        st = msplat_render_forward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, wsp,
+                                   ws_bytes, nullptr, stream);
+      if (st == MSPLAT_OK && grad_rgb)
+        st = msplat_render_backward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, grad_rgb, nullptr,
+                                    nullptr, wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, stream);
+      if (st == MSPLAT_OK && rep == 1 && hipEventRecord(ev[1], s) != hipSuccess) st = MSPLAT_E_HIP;
+    }
+    float ms = 0.f;
+    if (st == MSPLAT_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+      st = MSPLAT_E_HIP;
+    if (st == MSPLAT_OK && (best == 0 || ms < best_ms)) {
+      best = cand[c];
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st != MSPLAT_OK) return st;
+  TuneEntry e{n, R, key.samples_fixed, key.samples_min, key.samples_max, key.order, key.samples_per_unit, best};
+  int slot = -1;
+  for (int i = 0; i < ctx->num_tuned; ++i)
+    if (tune_match(ctx->tuned[i], n, R, key)) slot = i;
+  if (slot < 0) slot = ctx->num_tuned < kTuneSlots ? ctx->num_tuned++ : kTuneSlots - 1;
+  ctx->tuned[slot] = e;
+  *chosen = best;
+  return MSPLAT_OK;
+}
+
 int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat_stats* out, void* stream) {
   if (!ctx || !wsp || !out) return MSPLAT_E_INVALID;
   if (ctx->last_ws != wsp) return MSPLAT_E_STATE;
@@ -534,6 +644,7 @@ int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat
   float mg;
   std::memcpy(&mg, &c.min_abs_g_bits, 4);
   out->min_abs_g = mg;
+  out->hits_per_item = c.hits_per_item;
   (void)ws_bytes;
   return MSPLAT_OK;
 }
@@ -582,7 +693,7 @@ int msplat_render_forward_f64(msplat_ctx* ctx, const msplat_model* m, const mspl
   if (!center || !scale || !quat || !mlp || !wsp || R < 0) return MSPLAT_E_INVALID;
   if (R > 0 && (!ray_o || !ray_d || !rgb || !trans)) return MSPLAT_E_INVALID;
   if (n.NOUT > 4 && R > 0 && !feat) return MSPLAT_E_INVALID;
-  if (!mlp_supported(n) || o->order != 0) return MSPLAT_E_UNSUPPORTED;
+  if (!mlp_supported(n) || o->order != 0 || n.kind != MSPLAT_CHORD) return MSPLAT_E_UNSUPPORTED;
   if (need_bytes) *need_bytes = 256;
   if (ws_bytes < 256) return MSPLAT_E_CAPACITY;
   hipStream_t s = (hipStream_t)stream;

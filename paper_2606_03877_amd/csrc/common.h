@@ -11,7 +11,7 @@ namespace msplat {
 
 constexpr int kWave = 64;
 constexpr int kGeoStride = 40;       // floats per preprocessed primitive record
-constexpr int kHitsPerItem = 64;     // hits per primitive-grouped work item
+constexpr int kHitsPerItem = 64;     // most hits per primitive-grouped work item (one per lane)
 constexpr int kMaxSamplesPerHit = 128;
 constexpr int kClippedBit = 0x10000;   // flag in hit_k: interval clamped at t = 0
 constexpr int kKMask = 0xFFFF;
@@ -45,8 +45,10 @@ struct DevCounters {
   int32_t num_params;
   int64_t hit_total;         // hits counted in 64 bits (offsets and scans are 32-bit)
   int32_t net[6];            // network the workspace was laid out for: L, W, D, NOUT, precision, kind
+  int32_t hits_per_item;     // hits per work item of the network kernels
+  int32_t pad;
 };
-static_assert(sizeof(DevCounters) == 96, "counter block size");
+static_assert(sizeof(DevCounters) == 104, "counter block size");
 constexpr uint32_t kCountersMagic = 0x4d53504cu;
 
 // Workspace layout: every section 256-byte aligned, sized from (model, R, H).
@@ -94,6 +96,7 @@ struct Workspace {
   float* hit_q;          // [H] slot features, backward: dL/dF . (the hit's feature)
   float* hit_gpc;        // [3][H] slot features, backward: dL/d(local contact point)
   int32_t slot_on;       // 1 while a backward carries slot-feature gradients
+  int32_t hits_per_item; // hits per work item (16, 32 or 64)
   int64_t num_rays;
   int64_t hit_cap;
   int64_t wpack_bytes;
@@ -229,7 +232,11 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 // ---------------------------------------------------------------------------
 struct NetShape {
   int P, L, W, D, NOUT, prec, n_params;
+  int kind;   // msplat_primitive
 };
+// support of the contact-point primitive: the ellipsoid of KAPPA standard
+// deviations (the extent 3DGS-style Gaussian splatting culls at)
+constexpr float kContactKappa = 3.f;
 // hits of one call: offsets and scans are 32-bit
 constexpr int64_t kMaxHits = 0x7fffffffLL;
 // outputs of a network: RGB, density and up to 16 feature channels
@@ -237,23 +244,26 @@ constexpr int kMaxOut = 20;
 
 // geometry.hip
 hipError_t launch_preprocess(const Workspace& ws, const float* center, const float* scale,
-                             const float* quat, int P, hipStream_t s);
+                             const float* quat, int P, int kind, hipStream_t s);
 hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float* ray_d,
                             const float* center, const float* scale, const float* quat, int64_t R,
-                            int P, const msplat_opts& o, hipStream_t s);
+                            int P, const msplat_opts& o, int kind, hipStream_t s);
 hipError_t launch_scans(const Workspace& ws, int64_t R, const NetShape& n, hipStream_t s);
 hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float* ray_d,
                            const float* center, const float* scale, const float* quat,
-                           int64_t R, int P, const msplat_opts& o, hipStream_t s);
+                           int64_t R, int P, const msplat_opts& o, int kind, hipStream_t s);
+hipError_t launch_hit_records(const Workspace& ws, const float* ray_o, const float* ray_d, int64_t num_hits,
+                              int kind, hipStream_t s);
 hipError_t launch_composite(const Workspace& ws, int64_t R, const msplat_opts& o, float* rgb,
                             float* trans, float* feat, int cf, hipStream_t s);
 hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat_opts& o,
                                     const float* grad_rgb, const float* grad_trans,
                                     const float* grad_feat, int cf, const float* trans,
                                     hipStream_t s);
-hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, hipStream_t s);
+hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, int kind,
+                               hipStream_t s);
 hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
-                               float* g_quat, hipStream_t s);
+                               float* g_quat, int kind, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 // every 32-bit word of [p, p + bytes) set to value (a kernel: no memset node in a captured graph)
 hipError_t launch_fill(void* p, size_t bytes, uint32_t value, hipStream_t s);

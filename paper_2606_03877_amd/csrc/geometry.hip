@@ -29,8 +29,11 @@ __device__ __forceinline__ float3 ld3(const float* p, int64_t i) {
 
 // ----------------------------------------------------------- preprocessing --
 
+// kappa: the support's semi-axes in units of the scale (1 for chord
+// primitives, whose scale is the semi-axes; kContactKappa for the
+// contact-point primitive, whose scale is the Gaussian's standard deviations)
 __global__ void preprocess_kernel(const float* __restrict__ center, const float* __restrict__ scale,
-                                  const float* __restrict__ quat, float* __restrict__ geo, int P) {
+                                  const float* __restrict__ quat, float* __restrict__ geo, int P, float kappa) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
   float* g = geo + (int64_t)i * kGeoStride;
@@ -59,16 +62,16 @@ __global__ void preprocess_kernel(const float* __restrict__ center, const float*
   r[8] = df_sub(one, df_mul(two, df_add(df_mul(x, x), df_mul(y, y))));
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) {
-      df m = df_div(r[3 * b + a], df_from(s[a]));   // M[a][b] = R[b][a] / s[a]
+      df m = df_div(r[3 * b + a], two_prod(kappa, s[a]));   // M[a][b] = R[b][a] / (kappa s[a])
       g[G_M_HI + 3 * a + b] = m.hi;
       g[G_M_LO + 3 * a + b] = m.lo;
     }
   for (int k = 0; k < 9; ++k) g[G_R + k] = r[k].hi;
   for (int k = 0; k < 3; ++k) g[G_MU + k] = center[3 * i + k];
   for (int k = 0; k < 4; ++k) g[G_QN + k] = qn[k].hi;
-  for (int k = 0; k < 3; ++k) g[G_S + k] = s[k];
+  for (int k = 0; k < 3; ++k) g[G_S + k] = kappa * s[k];
   g[G_INVQ] = 1.f / nrm.hi;
-  float rad = fmaxf(fmaxf(s[0], s[1]), s[2]);
+  float rad = kappa * fmaxf(fmaxf(s[0], s[1]), s[2]);
   g[G_RAD] = rad * (1.f + 1e-4f) + 1e-6f;
 }
 
@@ -148,7 +151,7 @@ struct HitDF {
 // the same test evaluated entirely in double-float from the raw inputs
 __device__ HitDF hit_test_df(const float* __restrict__ center, const float* __restrict__ scale,
                              const float* __restrict__ quat, int p, float3 o, float3 d,
-                             const msplat_opts& opt) {
+                             const msplat_opts& opt, float kappa) {
   float q[4] = {quat[4 * p], quat[4 * p + 1], quat[4 * p + 2], quat[4 * p + 3]};
   df n2 = two_prod(q[0], q[0]);
   for (int k = 1; k < 4; ++k) n2 = df_add(n2, two_prod(q[k], q[k]));
@@ -171,7 +174,7 @@ __device__ HitDF hit_test_df(const float* __restrict__ center, const float* __re
   float dd[3] = {d.x, d.y, d.z};
   df m[3], e[3];
   for (int a = 0; a < 3; ++a) {
-    df inv_s = df_div(one, df_from(scale[3 * p + a]));
+    df inv_s = df_div(one, two_prod(kappa, scale[3 * p + a]));
     df sm = df_from(0.f), se = df_from(0.f);
     for (int b = 0; b < 3; ++b) {
       df mab = r[3 * b + a];
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
     const float* __restrict__ ray_o, const float* __restrict__ ray_d,
     const float* __restrict__ center, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ geo, int64_t R, int P,
-    msplat_opts opt, int32_t* __restrict__ ray_cnt, int32_t* __restrict__ prim_nhit,
+    msplat_opts opt, float kappa, int32_t* __restrict__ ray_cnt, int32_t* __restrict__ prim_nhit,
     DevCounters* __restrict__ ctr) {
   // per-primitive hit counts of the workgroup's packets, added to the global
   // counts once at the end (same-address atomics from every packet serialise)
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(
         if (h.tc_hi + h.eta > 0.f) min_g = fminf(min_g, fabsf(h.g));
         hit = h.hit;
         if (h.uncertain) {
-          HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
+          HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt, kappa);
           hit = hd.hit;
           K = hd.K;
           ++nfall;
@@ -446,7 +449,7 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
                                                         int32_t* __restrict__ wi_off, int P,
                                                         const int32_t* __restrict__ ray_off,
                                                         int64_t R, DevCounters* __restrict__ ctr,
-                                                        int64_t hit_cap, NetShape net) {
+                                                        int64_t hit_cap, NetShape net, int hpi) {
   __shared__ int32_t wsum[2][4];
   __shared__ int32_t carry[2];
   if (threadIdx.x == 0) carry[0] = carry[1] = 0;
@@ -454,7 +457,7 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
   for (int base = 0; base < P; base += 256) {
     int i = base + threadIdx.x;
     int32_t n = i < P ? prim_nhit[i] : 0;
-    int32_t wi = (n + kHitsPerItem - 1) / kHitsPerItem;
+    int32_t wi = (n + hpi - 1) / hpi;
     int in = wave_incl_scan(n);
     int iw = wave_incl_scan(wi);
     int w = threadIdx.x / kWave;
@@ -494,7 +497,8 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
     ctr->net[2] = net.D;
     ctr->net[3] = net.NOUT;
     ctr->net[4] = net.prec;
-    ctr->net[5] = 0;
+    ctr->net[5] = net.kind;
+    ctr->hits_per_item = hpi;
     ctr->magic = kCountersMagic;
   }
 }
@@ -585,40 +589,45 @@ __device__ bool tile_collect(const Cone& cone, const float* __restrict__ geo, in
   return true;
 }
 
-// ascending bitonic sort of the first 64 NR elements
-template <int NR>
-__device__ __forceinline__ void tile_sort(TileList& t, int lane) {
-  for (int kk = 2; kk <= NR * kWave; kk <<= 1) {
-    for (int j = kk >> 1; j > 0; j >>= 1) {
-      if (j >= kWave) {
-        // partner in the same lane, register r ^ (j / 64)
-        const int D = j / kWave;
+// one stage (run length KK, partner distance J) of an ascending bitonic sort
+// of the first 64 NR elements of a register list (element e in lane e % 64
+// of register e / 64), then the stages after it.  Every index is a
+// compile-time constant, so the list stays in registers.
+template <int NR, int KK, int J, int CAP>
+__device__ __forceinline__ void bitonic_stage(uint64_t (&v)[CAP], int lane) {
+  if constexpr (J >= kWave) {
+    // partner in the same lane, register r ^ (J / 64)
+    constexpr int D = J / kWave;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
+    for (int r = 0; r < NR; ++r) {
+      if (r & D) continue;
+      const int q = r | D;
+      const bool asc = ((r * kWave + lane) & KK) == 0;
+      const uint64_t a = v[r], b = v[q];
+      const bool sw = asc ? (b < a) : (a < b);
+      v[r] = sw ? b : a;
+      v[q] = sw ? a : b;
+    }
+  } else {
+    // partner in lane ^ J: the lower lane keeps the smaller element of an
+    // ascending run, the larger of a descending one
+    const bool lower = (lane & J) == 0;
 #pragma unroll
-          for (int q = r + 1; q < NR; ++q) {
-            if ((r ^ q) != D) continue;
-            const bool asc = ((r * kWave + lane) & kk) == 0;
-            const uint64_t a = t.v[r], b = t.v[q];
-            const bool sw = asc ? (b < a) : (a < b);
-            t.v[r] = sw ? b : a;
-            t.v[q] = sw ? a : b;
-          }
-        }
-      } else {
-        // partner in lane ^ j: the lower lane keeps the smaller element of an
-        // ascending run, the larger of a descending one
-        const bool lower = (lane & j) == 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const uint64_t x = __shfl_xor(t.v[r], j, kWave);
-          const bool asc = ((r * kWave + lane) & kk) == 0;
-          const bool take = (lower == asc) ? (x < t.v[r]) : (t.v[r] < x);
-          if (take) t.v[r] = x;
-        }
-      }
+    for (int r = 0; r < NR; ++r) {
+      const uint64_t x = __shfl_xor(v[r], J, kWave);
+      const bool asc = ((r * kWave + lane) & KK) == 0;
+      const bool take = (lower == asc) ? (x < v[r]) : (v[r] < x);
+      if (take) v[r] = x;
     }
   }
+  if constexpr (J > 1) bitonic_stage<NR, KK, J / 2>(v, lane);
+  else if constexpr (KK < NR * kWave) bitonic_stage<NR, 2 * KK, KK>(v, lane);
+}
+
+template <int NR, int CAP>
+__device__ __forceinline__ void reg_sort(uint64_t (&v)[CAP], int lane) {
+  static_assert(NR <= CAP, "sorted registers exist");
+  bitonic_stage<NR, 2, 1>(v, lane);
 }
 
 // primitive of list element i (wave-uniform i)
@@ -636,22 +645,185 @@ __device__ __forceinline__ int tile_prim(const TileList& t, int i) {
 // strict weak order on (t_c, prim) with double-float recomputation of close keys
 __device__ __forceinline__ bool key_less(float ahi, float alo, int ap, float bhi, float blo, int bp,
                                          const float* center, const float* scale, const float* quat,
-                                         float3 o, float3 d, const msplat_opts& opt) {
+                                         float3 o, float3 d, const msplat_opts& opt, float kappa) {
   float diff = (ahi - bhi) + (alo - blo);
   if (fabsf(diff) > kEpsKey * (1.f + fabsf(ahi))) return diff < 0.f;
-  HitDF a = hit_test_df(center, scale, quat, ap, o, d, opt);
-  HitDF b = hit_test_df(center, scale, quat, bp, o, d, opt);
+  HitDF a = hit_test_df(center, scale, quat, ap, o, d, opt, kappa);
+  HitDF b = hit_test_df(center, scale, quat, bp, o, d, opt, kappa);
   int sg = df_sign(df_sub(a.tc, b.tc));
   if (sg != 0) return sg < 0;
   return ap < bp;
 }
 
+// the per-hit record of hit j (ray `ray`, primitive p) from its contact depth,
+// sample count and clip flag: residual, local contact point and direction as
+// double-floats, the refined contact depth and half chord, chord start and bin
+// width (pass 3 of the fill)
+template <bool CONTACT>
+__device__ __forceinline__ void hit_record(const Workspace& ws, const float* __restrict__ geo, int64_t j, int p,
+                                           float3 o, float3 d, int64_t ray) {
+  const int64_t H = ws.hit_cap;
+  const float* gp = geo + (int64_t)p * kGeoStride;
+  const float* Mh = gp + G_M_HI;
+  const float* Ml = gp + G_M_LO;
+  float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j];
+  int kk = ws.hit_k[j];
+  bool clipped = kk < 0;
+  int K = clipped ? -kk : kk;
+  // residual delta = (mu - o) - t_c d and the local contact point
+  // p_c = -M delta and direction e = M d, all as double-floats: sample
+  // positions feed an encoding of frequency up to 2^(L-1) pi, so their
+  // float32 rounding would be amplified into the gradients
+  const float dd[3] = {d.x, d.y, d.z};
+  const float oo[3] = {o.x, o.y, o.z};
+  df tc = {tch, tcl};
+  df dl[3];
+  for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
+  df pcv[3], ev[3];
+  for (int r = 0; r < 3; ++r) {
+    df pc = {0.f, 0.f}, e = {0.f, 0.f};
+    for (int c = 0; c < 3; ++c) {
+      const df m = {Mh[3 * r + c], Ml[3 * r + c]};
+      pc = df_add(pc, df_mul(m, dl[c]));
+      e = df_add(e, df_mulf(m, dd[c]));
+    }
+    pcv[r] = df_neg(pc);
+    ev[r] = e;
+  }
+  // The sort key t_c is accurate to float32 only; samples are placed
+  // relative to t_c, so refine it to double-float accuracy: one Newton step
+  // on (p_c + dt e) . e = 0, i.e. dt = -(p_c . e) / |e|^2.
+  df aa = {0.f, 0.f}, pe = {0.f, 0.f};
+  for (int r = 0; r < 3; ++r) {
+    aa = df_add(aa, df_mul(ev[r], ev[r]));
+    pe = df_add(pe, df_mul(pcv[r], ev[r]));
+  }
+  const float dtc = -pe.hi / aa.hi;
+  tc = df_add(tc, df_from(dtc));
+  ws.hit_tc_hi[j] = tc.hi;
+  ws.hit_tc_lo[j] = tc.lo;
+  if constexpr (CONTACT) {
+    // the contact-point primitive (Sec. 3.2): one interaction at the clamped
+    // contact depth t* = max(t_c, 0) (Eq. 2); the network reads the residual
+    // delta = mu - (o + t* d) (double-float, in the position arrays) and the
+    // ray direction (in the direction arrays); the optical depth is
+    // sigma * G * thickness with the Gaussian falloff G = exp(-|y|^2 / 2),
+    // y = kappa M delta (the 1-sigma frame), and the thickness sqrt(2 pi) / |kappa M d|
+    const df ts = df_sign(tc) > 0 ? tc : df{0.f, 0.f};
+    float y2 = 0.f;
+    for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(ts, dd[k]));
+    for (int r = 0; r < 3; ++r) {
+      df yr = {0.f, 0.f};
+      for (int c = 0; c < 3; ++c) yr = df_add(yr, df_mul(df{Mh[3 * r + c], Ml[3 * r + c]}, dl[c]));
+      const float y = kContactKappa * yr.hi;
+      y2 += y * y;
+    }
+    for (int r = 0; r < 3; ++r) {
+      ws.hit_pc[r * H + j] = dl[r].hi;
+      ws.hit_pc_lo[r * H + j] = dl[r].lo;
+      ws.hit_e[r * H + j] = dd[r];
+      ws.hit_e_lo[r * H + j] = 0.f;
+    }
+    const float thick = 2.50662827463100050f / (kContactKappa * sqrtf(aa.hi));   // sqrt(2 pi)
+    ws.hit_dlt[j] = __expf(-0.5f * y2) * thick;
+    ws.hit_dlt_lo[j] = 0.f;
+    ws.hit_sa[j] = 0.f;
+    ws.hit_sa_lo[j] = 0.f;
+    ws.hit_k[j] = 1;
+    ws.hit_ray[j] = (int32_t)ray;
+    return;
+  }
+  df gg = {1.f, 0.f};
+  for (int r = 0; r < 3; ++r) {
+    pcv[r] = df_add(pcv[r], df_mulf(ev[r], dtc));
+    gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
+    ws.hit_pc[r * H + j] = pcv[r].hi;
+    ws.hit_pc_lo[r * H + j] = pcv[r].lo;
+    ws.hit_e[r * H + j] = ev[r].hi;
+    ws.hit_e_lo[r * H + j] = ev[r].lo;
+  }
+  // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the refined contact point
+  const df etad = df_sqrt(df_div(gg, aa));
+  ws.hit_eta[j] = etad.hi;
+  df sa, dlt;
+  const df Kd = {(float)K, 0.f};
+  if (clipped) {
+    sa = df_neg(tc);
+    dlt = df_div(df_add(tc, etad), Kd);
+  } else {
+    sa = df_neg(etad);
+    dlt = df_div(df_mulf(etad, 2.f), Kd);
+  }
+  ws.hit_sa[j] = sa.hi;
+  ws.hit_sa_lo[j] = sa.lo;
+  ws.hit_dlt[j] = dlt.hi;
+  ws.hit_dlt_lo[j] = dlt.lo;
+  ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
+  ws.hit_ray[j] = (int32_t)ray;
+}
+
+// entries of the lanes' hits j (act) in their primitives' lists: the lanes
+// are grouped by primitive (ballots only), then every group's first lane
+// reserves the group's slots with one atomic, all groups at once (a
+// reservation per group in turn would wait for each atomic's return); ranks
+// within a group by lane
+__device__ __forceinline__ void list_by_primitive(const Workspace& ws, bool act, int p, int64_t j, int lane) {
+  uint64_t pending = __ballot(act);
+  int leader_of = lane, rank = 0, cnt = 0;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int lp = __shfl(p, leader, 64);
+    const bool mine = act && p == lp;
+    const uint64_t same = __ballot(mine);
+    if (mine) {
+      leader_of = leader;
+      rank = __popcll(same & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) cnt = __popcll(same);
+    pending &= ~same;
+  }
+  int base = 0;
+  if (act && lane == leader_of) base = atomicAdd(&ws.prim_cursor[p], cnt);
+  base = __shfl(base, leader_of, 64);
+  if (act) ws.phit[base + rank] = (int32_t)j;
+}
+
+// A group's hits sorted in registers: up to kGroupNR * 64 of them, as 64-bit
+// keys (ray lane << 58 | order key << 26 | index of the hit in the packet's
+// staging order), element e in lane e % 64 of register e / 64
+constexpr int kGroupNR = 8;
+constexpr int kGroupMax = kGroupNR * kWave;
+constexpr int kPackIdxBits = 26;
+
+// orderable bits of a float key (as kp_pack)
+__device__ __forceinline__ uint32_t key_bits(float key) {
+  uint32_t u = __float_as_uint(key + 0.f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_float(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Fill: every ray's hits, depth-ordered (primitive, contact depth, sample
+// count and clip flag, half chord, ray).  A packet of 64 rays owns the
+// contiguous range of hit slots [ray_off[first ray], ray_off[last ray + 1]),
+// and a group of its consecutive rays the contiguous part of that range that
+// the group's rays own.  The packet is cut into the fewest groups of 64 / G
+// rays (G a power of two) whose hits number at most kGroupMax each; the hits
+// are appended in hit-test order (the lanes of one group that hit one
+// candidate write consecutive slots) to a staging copy, then every group's
+// hits are sorted in registers by (ray, depth key, test order) and written
+// in slot order, one slot per lane, so that memory is touched in contiguous
+// runs.  Keys closer than the float32 test can separate are re-ordered per
+// ray with the double-float comparison.  A packet with a ray of more than
+// kGroupMax hits falls back to appending into each ray's own segment and an
+// insertion sort there.  The per-hit records follow in hit_record_kernel.
 template <bool TILE>
 __global__ __launch_bounds__(256) void bin_fill_kernel(
     const float* __restrict__ ray_o, const float* __restrict__ ray_d,
     const float* __restrict__ center, const float* __restrict__ scale,
     const float* __restrict__ quat, const float* __restrict__ geo, int64_t R, int P,
-    msplat_opts opt, Workspace ws) {
+    msplat_opts opt, float kappa, Workspace ws) {
   int64_t packet = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = lane_id();
   int64_t ray = packet * kWave + lane;
@@ -660,52 +832,228 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
   float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
   float3 d = valid ? ld3(ray_d, ray) : make_float3(0.f, 0.f, 1.f);
   Cone cone = packet_cone(valid, o, d);
+  const int64_t H = ws.hit_cap;
   int64_t off = valid ? ws.ray_off[ray] : 0;
-  int n = 0;
-  // hit test of this lane's ray against primitive p (wave-uniform); a hit is
-  // appended to the ray's segment with its decided K, clip flag and eta
-  auto test_append = [&](int p) __attribute__((always_inline)) {
-    if (!valid) return;
+  const int64_t last = min(packet * kWave + kWave, R);
+  const int64_t pkt_off = __builtin_amdgcn_readfirstlane((int)ws.ray_off[packet * kWave]);
+  const int total = __builtin_amdgcn_readfirstlane((int)(ws.ray_off[last] - pkt_off));
+  // start of each lane's segment relative to the packet's (rays past the end: total)
+  const int rel = valid ? (int)(off - pkt_off) : total;
+  // hit test of this lane's ray against primitive p (wave-uniform): hit or
+  // not, with the decided K (negative: chord clipped at t = 0), t_c and eta
+  auto test = [&](int p, float& tch, float& tcl, int& kk, float& eta) __attribute__((always_inline)) -> bool {
+    if (!valid) return false;
     const float* gp = geo + (int64_t)p * kGeoStride;
     int K = 0;
     HitF h = hit_test_f32(gp, o, d, opt, &K);
     bool hit = h.hit;
     bool clipped = h.clipped;
-    float eta = h.eta;
+    eta = h.eta;
     if (h.uncertain) {
-      HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt);
+      HitDF hd = hit_test_df(center, scale, quat, p, o, d, opt, kappa);
       hit = hd.hit;
       K = hd.K;
       clipped = hd.clipped;
       eta = hd.eta.hi;
     }
-    if (hit) {
+    tch = h.tc_hi;
+    tcl = h.tc_lo;
+    kk = clipped ? -K : K;
+    return hit;
+  };
+  // the packet's candidates in tile order (sorted along the virtual ray), if
+  // they fit the registers
+  TileList tl;
+  int nc = 0;
+  bool in_order = false;
+  if constexpr (TILE) {
+    if (tile_collect(cone, geo, P, lane, tl, nc)) {
+      if (nc <= kWave) reg_sort<1>(tl.v, lane);
+      else if (nc <= 2 * kWave) reg_sort<2>(tl.v, lane);
+      else if (nc <= 4 * kWave) reg_sort<4>(tl.v, lane);
+      else reg_sort<8>(tl.v, lane);
+      in_order = true;
+    }
+  }
+  // the fewest groups (gs = 64 / G rays each) with at most kGroupMax hits each
+  int gs = kWave;
+  for (; gs >= 1; gs >>= 1) {
+    const int g0 = (lane % (kWave / gs)) * gs;   // lanes 0 .. G-1 check group lane
+    const int start = __shfl(rel, g0, kWave);
+    const int end = g0 + gs < kWave ? __shfl(rel, g0 + gs, kWave) : total;
+    if (wave_max(end - start) <= kGroupMax) break;
+  }
+
+  if (gs >= 1) {
+    // ---- group-wise path ----
+    // staging copy of the unsorted hits and their keys: planes of hit_gv
+    // (written by the backward only)
+    int32_t* st_prim = reinterpret_cast<int32_t*>(ws.hit_gv);
+    float* st_tch = ws.hit_gv + H;
+    float* st_tcl = ws.hit_gv + 2 * H;
+    int32_t* st_k = reinterpret_cast<int32_t*>(ws.hit_gv + 3 * H);
+    float* st_eta = ws.hit_gv + 4 * H;
+    uint32_t* st_key_hi = reinterpret_cast<uint32_t*>(ws.hit_gv + 5 * H);
+    uint32_t* st_key_lo = reinterpret_cast<uint32_t*>(ws.hit_gv + 6 * H);
+    const int my_g0 = (lane / gs) * gs;                      // first lane of this lane's group
+    const uint64_t gmask = gs == kWave ? ~0ull : (((1ull << gs) - 1ull) << my_g0);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int gbase = __shfl(rel, my_g0, kWave);             // the group's first slot
+    int cursor = 0;                                          // hits of this lane's group so far
+    auto append = [&](int p, float okey) __attribute__((always_inline)) {
+      float tch, tcl, eta;
+      int kk;
+      const bool hit = test(p, tch, tcl, kk, eta);
+      const uint64_t mask = __ballot(hit);
+      if (mask == 0) return;
+      if (hit) {
+        const int e = gbase + cursor + __popcll(mask & gmask & below);
+        const int64_t sidx = pkt_off + e;
+        st_prim[sidx] = p;
+        st_tch[sidx] = tch;
+        st_tcl[sidx] = tcl;
+        st_k[sidx] = kk;
+        st_eta[sidx] = eta;
+        const uint64_t key =
+            ((uint64_t)lane << 58) | ((uint64_t)key_bits(TILE ? okey : tch) << kPackIdxBits) | (uint64_t)e;
+        st_key_hi[sidx] = (uint32_t)(key >> 32);
+        st_key_lo[sidx] = (uint32_t)key;
+      }
+      cursor += __popcll(mask & gmask);
+    };
+    if (in_order) {
+      // candidates already in tile order: the test order is the key
+      for (int i = 0; i < nc; ++i) append(tile_prim(tl, i), 0.f);
+    } else {
+      for (int base = 0; base < P; base += kWave) {
+        int pl = base + lane;
+        bool cand = false;
+        if (pl < P) {
+          const float* gp = geo + (int64_t)pl * kGeoStride;
+          cand = cone_may_hit(cone, gp[G_MU], gp[G_MU + 1], gp[G_MU + 2], gp[G_RAD]);
+        }
+        uint64_t mask = __ballot(cand);
+        while (mask) {
+          int bit = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          const int p = __builtin_amdgcn_readfirstlane(base + bit);
+          float vk = 0.f;
+          if constexpr (TILE) vk = virtual_depth(geo + (int64_t)p * kGeoStride, cone.vo, cone.vd);
+          append(p, vk);
+        }
+      }
+    }
+    // (every group's count equals what the count pass found: the same pairs were tested)
+    __threadfence_block();
+    uint64_t close = 0;   // exact order: ray lanes with two keys closer than float32 separates
+    for (int g0 = 0; g0 < kWave; g0 += gs) {
+      const int gb = __shfl(rel, g0, kWave);
+      const int gn = (g0 + gs < kWave ? __shfl(rel, g0 + gs, kWave) : total) - gb;
+      if (gn == 0) continue;
+      uint64_t L[kGroupNR];
+#pragma unroll
+      for (int r = 0; r < kGroupNR; ++r) {
+        const int pos = r * kWave + lane;
+        L[r] = ~0ull;
+        if (pos < gn)
+          L[r] = ((uint64_t)st_key_hi[pkt_off + gb + pos] << 32) | (uint64_t)st_key_lo[pkt_off + gb + pos];
+      }
+      if (gn <= kWave) reg_sort<1>(L, lane);
+      else if (gn <= 2 * kWave) reg_sort<2>(L, lane);
+      else if (gn <= 4 * kWave) reg_sort<4>(L, lane);
+      else reg_sort<8>(L, lane);
+      if constexpr (!TILE) {
+#pragma unroll
+        for (int r = 0; r < kGroupNR; ++r) {
+          if (r * kWave >= gn) break;   // (wave-uniform)
+          const uint64_t nx0 = __shfl_down(L[r], 1, kWave);
+          const uint64_t nx1 = __shfl(L[r + 1 < kGroupNR ? r + 1 : r], 0, kWave);
+          const uint64_t nx = lane < kWave - 1 ? nx0 : nx1;
+          const int pos = r * kWave + lane;
+          if (pos + 1 < gn && (L[r] >> 58) == (nx >> 58)) {
+            const float a = key_float((uint32_t)(L[r] >> kPackIdxBits));
+            const float b = key_float((uint32_t)(nx >> kPackIdxBits));
+            if (b - a <= 2.f * kEpsKey * (1.f + fabsf(a))) close |= 1ull << (L[r] >> 58);
+          }
+        }
+      }
+      // the group's sorted hits into its slots, one slot per lane
+#pragma unroll
+      for (int r = 0; r < kGroupNR; ++r) {
+        if (r * kWave >= gn) break;   // (wave-uniform)
+        const int pos = r * kWave + lane;
+        if (pos < gn) {
+          const int64_t src = pkt_off + (int64_t)(L[r] & ((1ull << kPackIdxBits) - 1ull));
+          const int64_t j = pkt_off + gb + pos;
+          ws.hit_prim[j] = st_prim[src];
+          ws.hit_tc_hi[j] = st_tch[src];
+          ws.hit_tc_lo[j] = st_tcl[src];
+          ws.hit_k[j] = st_k[src];
+          ws.hit_eta[j] = st_eta[src];
+          ws.hit_ray[j] = (int32_t)(packet * kWave + (int64_t)(L[r] >> 58));
+        }
+      }
+    }
+    if constexpr (!TILE) {
+#pragma unroll
+      for (int sh = 32; sh >= 1; sh >>= 1) close |= __shfl_xor(close, sh, kWave);
+      __threadfence_block();
+      if ((close >> lane) & 1ull) {
+        // insertion sort of this ray's (nearly sorted) segment with the
+        // double-float comparison of close keys
+        const int n = (int)(ws.ray_off[ray + 1] - off);
+        for (int i = 1; i < n; ++i) {
+          int64_t ji = off + i;
+          int p = ws.hit_prim[ji];
+          float th = ws.hit_tc_hi[ji], tlo = ws.hit_tc_lo[ji], et = ws.hit_eta[ji];
+          int kk = ws.hit_k[ji];
+          int j = i - 1;
+          while (j >= 0) {
+            int64_t jj = off + j;
+            int pj = ws.hit_prim[jj];
+            if (!key_less(th, tlo, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt, kappa))
+              break;
+            ws.hit_prim[jj + 1] = pj;
+            ws.hit_tc_hi[jj + 1] = ws.hit_tc_hi[jj];
+            ws.hit_tc_lo[jj + 1] = ws.hit_tc_lo[jj];
+            ws.hit_eta[jj + 1] = ws.hit_eta[jj];
+            ws.hit_k[jj + 1] = ws.hit_k[jj];
+            --j;
+          }
+          int64_t jd = off + j + 1;
+          ws.hit_prim[jd] = p;
+          ws.hit_tc_hi[jd] = th;
+          ws.hit_tc_lo[jd] = tlo;
+          ws.hit_eta[jd] = et;
+          ws.hit_k[jd] = kk;
+        }
+      }
+    }
+    return;
+  }
+
+  // ---- per-ray path (a ray with more than kGroupMax hits) ----
+  int n = 0;
+  // hit test of this lane's ray against primitive p (wave-uniform); a hit is
+  // appended to the ray's segment with its decided K, clip flag and eta
+  auto test_append = [&](int p) __attribute__((always_inline)) {
+    float tch, tcl, eta;
+    int kk;
+    if (test(p, tch, tcl, kk, eta)) {
       int64_t j = off + n;
       ws.hit_prim[j] = p;
-      ws.hit_tc_hi[j] = h.tc_hi;
-      ws.hit_tc_lo[j] = h.tc_lo;
-      ws.hit_k[j] = clipped ? -K : K;
+      ws.hit_tc_hi[j] = tch;
+      ws.hit_tc_lo[j] = tcl;
+      ws.hit_k[j] = kk;
       ws.hit_eta[j] = eta;
       ++n;
     }
   };
-  // tile order: one sort of the packet's candidates by their depth along the
-  // virtual ray, then every ray tests them in that order, so its hits come
-  // out sorted (a packet with more candidates than the registers hold falls
-  // back to the per-ray sort below, on the same keys)
-  bool in_order = false;
-  if constexpr (TILE) {
-    TileList tl;
-    int nc = 0;
-    if (tile_collect(cone, geo, P, lane, tl, nc)) {
-      if (nc <= kWave) tile_sort<1>(tl, lane);
-      else if (nc <= 2 * kWave) tile_sort<2>(tl, lane);
-      else if (nc <= 4 * kWave) tile_sort<4>(tl, lane);
-      else tile_sort<8>(tl, lane);
-      for (int i = 0; i < nc; ++i) test_append(tile_prim(tl, i));
-      in_order = true;
-    }
-  }
+  // tile order: every ray tests the sorted candidates in order, so its hits
+  // come out sorted (a packet with more candidates than the registers hold
+  // falls back to the per-ray sort below, on the same keys)
+  if (in_order)
+    for (int i = 0; i < nc; ++i) test_append(tile_prim(tl, i));
   // pass 1: unsorted hits (primitive order)
   for (int base = 0; !in_order && base < P; base += kWave) {
     int pl = base + lane;
@@ -727,7 +1075,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
   for (int i = 1; !in_order && i < n; ++i) {
     int64_t ji = off + i;
     int p = ws.hit_prim[ji];
-    float th = ws.hit_tc_hi[ji], tl = ws.hit_tc_lo[ji], et = ws.hit_eta[ji];
+    float th = ws.hit_tc_hi[ji], tlo = ws.hit_tc_lo[ji], et = ws.hit_eta[ji];
     uint64_t vk = 0;
     if constexpr (TILE) vk = kp_pack(virtual_depth(geo + (int64_t)p * kGeoStride, cone.vo, cone.vd), p);
     int kk = ws.hit_k[ji];
@@ -739,7 +1087,7 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
       if constexpr (TILE)
         before = vk < kp_pack(virtual_depth(geo + (int64_t)pj * kGeoStride, cone.vo, cone.vd), pj);
       else
-        before = key_less(th, tl, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt);
+        before = key_less(th, tlo, p, ws.hit_tc_hi[jj], ws.hit_tc_lo[jj], pj, center, scale, quat, o, d, opt, kappa);
       if (!before) break;
       ws.hit_prim[jj + 1] = pj;
       ws.hit_tc_hi[jj + 1] = ws.hit_tc_hi[jj];
@@ -751,110 +1099,29 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
     int64_t jd = off + j + 1;
     ws.hit_prim[jd] = p;
     ws.hit_tc_hi[jd] = th;
-    ws.hit_tc_lo[jd] = tl;
+    ws.hit_tc_lo[jd] = tlo;
     ws.hit_eta[jd] = et;
     ws.hit_k[jd] = kk;
   }
-  // pass 3: per-hit local record and grouping by primitive
-  int64_t H = ws.hit_cap;
-  int nmax = n;
-#pragma unroll
-  for (int sh = 32; sh >= 1; sh >>= 1) nmax = max(nmax, __shfl_xor(nmax, sh, 64));
-  for (int i = 0; i < nmax; ++i) {
-    const bool act = i < n;
-    int64_t j = off + i;
-    int p = act ? ws.hit_prim[j] : -1;
-    if (act) {
-      const float* gp = geo + (int64_t)p * kGeoStride;
-      const float* Mh = gp + G_M_HI;
-      const float* Ml = gp + G_M_LO;
-      float tch = ws.hit_tc_hi[j], tcl = ws.hit_tc_lo[j];
-      int kk = ws.hit_k[j];
-      bool clipped = kk < 0;
-      int K = clipped ? -kk : kk;
-      // residual delta = (mu - o) - t_c d and the local contact point
-      // p_c = -M delta and direction e = M d, all as double-floats: sample
-      // positions feed an encoding of frequency up to 2^(L-1) pi, so their
-      // float32 rounding would be amplified into the gradients
-      const float dd[3] = {d.x, d.y, d.z};
-      const float oo[3] = {o.x, o.y, o.z};
-      df tc = {tch, tcl};
-      df dl[3];
-      for (int k = 0; k < 3; ++k) dl[k] = df_sub(two_sum(gp[G_MU + k], -oo[k]), df_mulf(tc, dd[k]));
-      df pcv[3], ev[3];
-      for (int r = 0; r < 3; ++r) {
-        df pc = {0.f, 0.f}, e = {0.f, 0.f};
-        for (int c = 0; c < 3; ++c) {
-          const df m = {Mh[3 * r + c], Ml[3 * r + c]};
-          pc = df_add(pc, df_mul(m, dl[c]));
-          e = df_add(e, df_mulf(m, dd[c]));
-        }
-        pcv[r] = df_neg(pc);
-        ev[r] = e;
-      }
-      // The sort key t_c is accurate to float32 only; samples are placed
-      // relative to t_c, so refine it to double-float accuracy: one Newton step
-      // on (p_c + dt e) . e = 0, i.e. dt = -(p_c . e) / |e|^2.
-      df aa = {0.f, 0.f}, pe = {0.f, 0.f};
-      for (int r = 0; r < 3; ++r) {
-        aa = df_add(aa, df_mul(ev[r], ev[r]));
-        pe = df_add(pe, df_mul(pcv[r], ev[r]));
-      }
-      const float dtc = -pe.hi / aa.hi;
-      tc = df_add(tc, df_from(dtc));
-      ws.hit_tc_hi[j] = tc.hi;
-      ws.hit_tc_lo[j] = tc.lo;
-      df gg = {1.f, 0.f};
-      for (int r = 0; r < 3; ++r) {
-        pcv[r] = df_add(pcv[r], df_mulf(ev[r], dtc));
-        gg = df_sub(gg, df_mul(pcv[r], pcv[r]));
-        ws.hit_pc[r * H + j] = pcv[r].hi;
-        ws.hit_pc_lo[r * H + j] = pcv[r].lo;
-        ws.hit_e[r * H + j] = ev[r].hi;
-        ws.hit_e_lo[r * H + j] = ev[r].lo;
-      }
-      // half chord eta = sqrt((1 - |p_c|^2) / |e|^2) from the refined contact point
-      const df etad = df_sqrt(df_div(gg, aa));
-      ws.hit_eta[j] = etad.hi;
-      df sa, dlt;
-      const df Kd = {(float)K, 0.f};
-      if (clipped) {
-        sa = df_neg(tc);
-        dlt = df_div(df_add(tc, etad), Kd);
-      } else {
-        sa = df_neg(etad);
-        dlt = df_div(df_mulf(etad, 2.f), Kd);
-      }
-      ws.hit_sa[j] = sa.hi;
-      ws.hit_sa_lo[j] = sa.lo;
-      ws.hit_dlt[j] = dlt.hi;
-      ws.hit_dlt_lo[j] = dlt.lo;
-      ws.hit_k[j] = K | (clipped ? kClippedBit : 0);
-      ws.hit_ray[j] = (int32_t)ray;
-    }
-    // slots in the per-primitive lists: the lanes are grouped by primitive
-    // (ballots only), then every group's first lane reserves the group's
-    // slots with one atomic, all groups at once (a reservation per group in
-    // turn would wait for each atomic's return); ranks within a group by lane
-    uint64_t pending = __ballot(act);
-    int leader_of = lane, rank = 0, cnt = 0;
-    while (pending) {
-      const int leader = __builtin_ctzll(pending);
-      const int lp = __shfl(p, leader, 64);
-      const bool mine = act && p == lp;
-      const uint64_t same = __ballot(mine);
-      if (mine) {
-        leader_of = leader;
-        rank = __popcll(same & ((1ull << lane) - 1ull));
-      }
-      if (lane == leader) cnt = __popcll(same);
-      pending &= ~same;
-    }
-    int base = 0;
-    if (act && lane == leader_of) base = atomicAdd(&ws.prim_cursor[p], cnt);
-    base = __shfl(base, leader_of, 64);
-    if (act) ws.phit[base + rank] = (int32_t)j;
+  for (int i = 0; i < n; ++i) ws.hit_ray[off + i] = (int32_t)ray;
+}
+
+// Per-hit records (one thread per hit slot, in slot order) and the
+// per-primitive hit lists.
+template <bool CONTACT>
+__global__ __launch_bounds__(256) void hit_record_kernel(const float* __restrict__ ray_o,
+                                                         const float* __restrict__ ray_d,
+                                                         const float* __restrict__ geo, Workspace ws,
+                                                         int64_t num_hits) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = j < num_hits;
+  int p = -1;
+  if (act) {
+    p = ws.hit_prim[j];
+    const int64_t ray = ws.hit_ray[j];
+    hit_record<CONTACT>(ws, geo, j, p, ld3(ray_o, ray), ld3(ray_d, ray), ray);
   }
+  list_by_primitive(ws, act, p, j, lane_id());
 }
 
 // ------------------------------------------------------------ compositor --
@@ -992,10 +1259,55 @@ __device__ __forceinline__ void hit_geometry_terms(const Workspace& ws, const fl
   }
 }
 
+// Contact-point primitive (one interaction per hit): the backward kernel
+// leaves per hit dL/d(delta) (gv 0-2) and dL/d(dlt) (gv 8), dlt = G * thickness
+// the optical-depth factor.  With the support frame M (semi-axes kappa s),
+// e = M d, a = |e|^2, y = kappa M delta, rho = dL/d(dlt) * dlt:
+//   dL/dy = -rho y; dL/d(delta) in total: g = gv + kappa M^T dL/dy;
+//   through t* = t_c = (e . M v) / a (v = mu - o; zero derivative where
+//   t* is clamped at 0): lambda = -(d . g) / a;
+//   dL/dM = (kappa dL/dy + lambda e) (x) delta + (lambda M delta - rho e / a) (x) d;
+//   dL/dmu = g + lambda M^T e.
+// acc: dL/dM (9), dL/dmu (3).
+__device__ __forceinline__ void contact_geometry_terms(const Workspace& ws, const float* __restrict__ ray_d,
+                                                       int hit, int64_t pos, int p, float (&acc)[12]) {
+  const int64_t H = ws.hit_cap;
+  const float* gp = ws.geo + (int64_t)p * kGeoStride;
+  float M[9];
+  for (int k = 0; k < 9; ++k) M[k] = gp[G_M_HI + k] + gp[G_M_LO + k];
+  const int ray = ws.hit_ray[hit];
+  const float dd[3] = {ray_d[3 * ray], ray_d[3 * ray + 1], ray_d[3 * ray + 2]};
+  float dl[3], gdl[3];
+  for (int a = 0; a < 3; ++a) {
+    dl[a] = ws.hit_pc[a * H + hit] + ws.hit_pc_lo[a * H + hit];
+    gdl[a] = ws.hit_gv[a * H + pos];
+  }
+  const float rho = ws.hit_gv[8 * H + pos] * ws.hit_dlt[hit];
+  float e[3], md[3];
+  for (int r = 0; r < 3; ++r) {
+    e[r] = M[3 * r] * dd[0] + M[3 * r + 1] * dd[1] + M[3 * r + 2] * dd[2];
+    md[r] = M[3 * r] * dl[0] + M[3 * r + 1] * dl[1] + M[3 * r + 2] * dl[2];
+  }
+  const float a2 = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+  const float k2 = kContactKappa * kContactKappa;
+  // kappa dL/dy = -rho kappa^2 M delta
+  float ky[3], g[3];
+  for (int r = 0; r < 3; ++r) ky[r] = -rho * k2 * md[r];
+  for (int c = 0; c < 3; ++c) g[c] = gdl[c] + M[c] * ky[0] + M[3 + c] * ky[1] + M[6 + c] * ky[2];
+  const float lam = ws.hit_tc_hi[hit] > 0.f ? -(dd[0] * g[0] + dd[1] * g[1] + dd[2] * g[2]) / a2 : 0.f;
+  for (int r = 0; r < 3; ++r) {
+    const float u = ky[r] + lam * e[r];
+    const float w = lam * md[r] - rho * e[r] / a2;
+    for (int c = 0; c < 3; ++c) acc[3 * r + c] = u * dl[c] + w * dd[c];
+  }
+  for (int c = 0; c < 3; ++c) acc[9 + c] = g[c] + lam * (M[c] * e[0] + M[3 + c] * e[1] + M[6 + c] * e[2]);
+}
+
 // One thread per entry of the primitive-grouped hit list (all loads of a hit
 // are issued at once; no thread walks a chain of hits).  A workgroup whose
 // hits share one primitive adds its sum with one set of atomics; otherwise
 // each wave whose hits share one does; otherwise each thread.
+template <bool CONTACT>
 __global__ __launch_bounds__(256) void hit_geometry_kernel(Workspace ws, const float* __restrict__ ray_d,
                                                            int64_t num_hits) {
   __shared__ float part[4][12];
@@ -1008,7 +1320,10 @@ __global__ __launch_bounds__(256) void hit_geometry_kernel(Workspace ws, const f
   if (i < num_hits) {
     const int hit = ws.phit[i];
     p = ws.hit_prim[hit];
-    if (ws.hit_nused[hit] > 0) hit_geometry_terms(ws, ray_d, hit, i, p, c);   // (else no samples ran)
+    if (ws.hit_nused[hit] > 0) {   // (else no samples ran)
+      if constexpr (CONTACT) contact_geometry_terms(ws, ray_d, hit, i, p, c);
+      else hit_geometry_terms(ws, ray_d, hit, i, p, c);
+    }
   }
   // the wave's primitive, or -2 if its hits belong to several (-1: no hits)
   const int pw0 = __builtin_amdgcn_readfirstlane(p);
@@ -1046,9 +1361,12 @@ __global__ __launch_bounds__(256) void hit_geometry_kernel(Workspace ws, const f
   }
 }
 
+// acc: dL/dM (9) and either u with dL/dmu = M^T u (chord primitives) or
+// dL/dmu itself (direct_center: the contact-point primitive); the stored
+// semi-axes are kappa times the scale input (kappa = 1 for chord primitives)
 __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* __restrict__ acc,
                                     int P, float* __restrict__ g_center, float* __restrict__ g_scale,
-                                    float* __restrict__ g_quat) {
+                                    float* __restrict__ g_quat, bool direct_center, float kappa) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
   const float* gp = geo + (int64_t)i * kGeoStride;
@@ -1060,7 +1378,8 @@ __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* 
   }
   for (int k = 0; k < 3; ++k) u[k] = A[9 + k];
   // dL/dmu = M^T u
-  for (int c = 0; c < 3; ++c) g_center[3 * i + c] = M[c] * u[0] + M[3 + c] * u[1] + M[6 + c] * u[2];
+  for (int c = 0; c < 3; ++c)
+    g_center[3 * i + c] = direct_center ? u[c] : M[c] * u[0] + M[3 + c] * u[1] + M[6 + c] * u[2];
   // M[a][b] = R[b][a] / s[a]
   float G[9];   // dL/dR
   for (int a2 = 0; a2 < 3; ++a2) {
@@ -1070,7 +1389,7 @@ __global__ void geo_finalize_kernel(const float* __restrict__ geo, const float* 
       ds += GM[3 * a2 + b2] * M[3 * a2 + b2];
       G[3 * b2 + a2] = GM[3 * a2 + b2] / s;
     }
-    g_scale[3 * i + a2] = -ds / s;
+    g_scale[3 * i + a2] = -kappa * ds / s;
   }
   float w = gp[G_QN], x = gp[G_QN + 1], y = gp[G_QN + 2], z = gp[G_QN + 3];
   float dw = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
@@ -1110,9 +1429,9 @@ hipError_t launch_fill(void* p, size_t bytes, uint32_t value, hipStream_t s) {
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) { return launch_fill(p, bytes, 0u, s); }
 
 hipError_t launch_preprocess(const Workspace& ws, const float* center, const float* scale,
-                             const float* quat, int P, hipStream_t s) {
+                             const float* quat, int P, int kind, hipStream_t s) {
   hipLaunchKernelGGL(preprocess_kernel, dim3((P + 127) / 128), dim3(128), 0, s, center, scale, quat,
-                     ws.geo, P);
+                     ws.geo, P, kind == MSPLAT_CONTACT ? kContactKappa : 1.f);
   return hipGetLastError();
 }
 
@@ -1123,12 +1442,12 @@ static inline unsigned packet_blocks(int64_t R) {
 
 hipError_t launch_bin_count(const Workspace& ws, const float* ray_o, const float* ray_d,
                              const float* center, const float* scale, const float* quat, int64_t R,
-                             int P, const msplat_opts& o, hipStream_t s) {
+                             int P, const msplat_opts& o, int kind, hipStream_t s) {
   if (R <= 0) return hipSuccess;
   const size_t hist_bytes = P <= kBinHistMax ? (size_t)P * 4 : 0;
   hipLaunchKernelGGL(bin_count_kernel, dim3(packet_blocks(R)), dim3(256), hist_bytes, s, ray_o, ray_d, center,
-                     scale, quat, (const float*)ws.geo, R, P, o, ws.ray_off, ws.prim_nhit,
-                     ws.counters);
+                     scale, quat, (const float*)ws.geo, R, P, o, kind == MSPLAT_CONTACT ? kContactKappa : 1.f,
+                     ws.ray_off, ws.prim_nhit, ws.counters);
   return hipGetLastError();
 }
 
@@ -1147,20 +1466,34 @@ hipError_t launch_scans(const Workspace& ws, int64_t R, const NetShape& net, hip
   }
   hipLaunchKernelGGL(prim_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_nhit,
                      ws.prim_off, ws.prim_cursor, ws.wi_off, P, (const int32_t*)ws.ray_off, R,
-                     ws.counters, ws.hit_cap, net);
+                     ws.counters, ws.hit_cap, net, ws.hits_per_item);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float* ray_d,
                            const float* center, const float* scale, const float* quat, int64_t R,
-                           int P, const msplat_opts& o, hipStream_t s) {
+                           int P, const msplat_opts& o, int kind, hipStream_t s) {
   if (R <= 0) return hipSuccess;
+  const float kappa = kind == MSPLAT_CONTACT ? kContactKappa : 1.f;
   if (o.order == 1)
     hipLaunchKernelGGL(bin_fill_kernel<true>, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
-                       scale, quat, (const float*)ws.geo, R, P, o, ws);
+                       scale, quat, (const float*)ws.geo, R, P, o, kappa, ws);
   else
     hipLaunchKernelGGL(bin_fill_kernel<false>, dim3(packet_blocks(R)), dim3(256), 0, s, ray_o, ray_d, center,
-                       scale, quat, (const float*)ws.geo, R, P, o, ws);
+                       scale, quat, (const float*)ws.geo, R, P, o, kappa, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_records(const Workspace& ws, const float* ray_o, const float* ray_d, int64_t num_hits,
+                              int kind, hipStream_t s) {
+  if (num_hits <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((num_hits + 255) / 256));
+  if (kind == MSPLAT_CONTACT)
+    hipLaunchKernelGGL(hit_record_kernel<true>, grid, dim3(256), 0, s, ray_o, ray_d, (const float*)ws.geo, ws,
+                       num_hits);
+  else
+    hipLaunchKernelGGL(hit_record_kernel<false>, grid, dim3(256), 0, s, ray_o, ray_d, (const float*)ws.geo, ws,
+                       num_hits);
   return hipGetLastError();
 }
 
@@ -1182,17 +1515,22 @@ hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat
   return hipGetLastError();
 }
 
-hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, hipStream_t s) {
+hipError_t launch_hit_geometry(const Workspace& ws, const float* ray_d, int64_t num_hits, int kind, hipStream_t s) {
   if (num_hits <= 0) return hipSuccess;
-  hipLaunchKernelGGL(hit_geometry_kernel, dim3((unsigned)((num_hits + 255) / 256)), dim3(256), 0, s, ws, ray_d,
-                     num_hits);
+  const dim3 grid((unsigned)((num_hits + 255) / 256));
+  if (kind == MSPLAT_CONTACT)
+    hipLaunchKernelGGL(hit_geometry_kernel<true>, grid, dim3(256), 0, s, ws, ray_d, num_hits);
+  else
+    hipLaunchKernelGGL(hit_geometry_kernel<false>, grid, dim3(256), 0, s, ws, ray_d, num_hits);
   return hipGetLastError();
 }
 
 hipError_t launch_geo_finalize(const Workspace& ws, int P, float* g_center, float* g_scale,
-                               float* g_quat, hipStream_t s) {
+                               float* g_quat, int kind, hipStream_t s) {
+  const bool contact = kind == MSPLAT_CONTACT;
   hipLaunchKernelGGL(geo_finalize_kernel, dim3((P + 127) / 128), dim3(128), 0, s,
-                     (const float*)ws.geo, (const float*)ws.geo_grad, P, g_center, g_scale, g_quat);
+                     (const float*)ws.geo, (const float*)ws.geo_grad, P, g_center, g_scale, g_quat, contact,
+                     contact ? kContactKappa : 1.f);
   return hipGetLastError();
 }
 

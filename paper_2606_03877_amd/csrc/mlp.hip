@@ -1,6 +1,6 @@
 // Grouped per-primitive MLP kernels (Sec. 3.2 network, Sec. 3.3 compositing).
 //
-// Hits are grouped by primitive; one workgroup takes up to kHitsPerItem hits
+// Hits are grouped by primitive; one workgroup takes up to hits_per_item hits
 // of one primitive, stages that primitive's packed weights in LDS once (wide
 // networks read them from L2), and its waves (eight; four for wide networks)
 // each walk the samples of their hits (dealt by sample count) in blocks of 32
@@ -112,10 +112,10 @@ __device__ __forceinline__ f32x16 hidden_chain(const uint8_t* __restrict__ wb, c
 
 template <class N, int LAYOUT>
 __device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
-                                                int lane, const float ph[3], const float pl[3]) {
+                                                int lane, const float ph[3], const float pl[3], const float dd[3]) {
   int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
-  encode_slots<N>(ph, pl, g, ev);
+  encode_input<N>(ph, pl, dd, g, ev);
   Act<N, rup(N::ENC_KS, N::KGRP)> B0;
   enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
@@ -170,8 +170,8 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
   const int g = lane / 32;
   const int wi = blockIdx.x;
   const int p = find_prim(ws.wi_off, args.P, wi);
-  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * kHitsPerItem;
-  const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
+  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * ws.hits_per_item;
+  const int nh = min(ws.hits_per_item, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
   if (args.mode == 1) {
     int flag = 0;
@@ -246,9 +246,9 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     float u = 0.5f;
     if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
-    float ph[3], pl[3];
-    sample_position(ws, hit, k, u, ph, pl);
-    f32x16 o = forward_block<N, fwd_stage<N>() == 2 ? kHiStaged : kPacked>(wts, wglb, lane, ph, pl);
+    float ph[3], pl[3], dd[3];
+    sample_input<N>(ws, hit, k, u, ph, pl, dd);
+    f32x16 o = forward_block<N, fwd_stage<N>() == 2 ? kHiStaged : kPacked>(wts, wglb, lane, ph, pl, dd);
     // density of the column (held by half 0), shared with half 1
     float tau0 = valid ? softplusf_(o[3]) * dlt : 0.f;
     const float tau = from_lower_half(tau0);
@@ -379,14 +379,14 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
 
 #ifndef MSPLAT_WIDE_TU
 bool mlp_supported(const NetShape& n) {
-#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return true;
+#define X(L_, W_, D_, O_, P_, K_) MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) return true;
   MSPLAT_NETS(X)
 #undef X
   return false;
 }
 
 int64_t mlp_wpack_bytes(const NetShape& n) {
-#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return MSPLAT_NET(L_, W_, D_, O_, P_)::total_bytes();
+#define X(L_, W_, D_, O_, P_, K_) MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) return MSPLAT_NET(L_, W_, D_, O_, P_, K_)::total_bytes();
   MSPLAT_NETS(X)
 #undef X
   return 0;
@@ -412,7 +412,7 @@ hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const mspl
 
 hipError_t MSPLAT_TU_FN(launch_pack_weights)(const NetShape& n, const Workspace& ws, const float* mlp,
                                              hipStream_t s) {
-#define X(L_, W_, D_, O_, P_) MSPLAT_MATCH(L_, W_, D_, O_, P_) return pack_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, mlp, n.P, s);
+#define X(L_, W_, D_, O_, P_, K_) MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) return pack_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, mlp, n.P, s);
   MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;
@@ -421,8 +421,8 @@ hipError_t MSPLAT_TU_FN(launch_pack_weights)(const NetShape& n, const Workspace&
 hipError_t MSPLAT_TU_FN(launch_mlp_forward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
                                             int items, int mode, float* rgb, float* trans, float* feat,
                                             hipStream_t s) {
-#define X(L_, W_, D_, O_, P_) \
-  MSPLAT_MATCH(L_, W_, D_, O_, P_) return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, mode, n.P, rgb, trans, feat, s);
+#define X(L_, W_, D_, O_, P_, K_) \
+  MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, items, mode, n.P, rgb, trans, feat, s);
   MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;

@@ -3,7 +3,7 @@
 // derivative of the forward in mlp.hip with the discrete decisions fixed).
 //
 // Work decomposition is the forward's: one workgroup per group of up to
-// kHitsPerItem hits of one primitive, its operands (forward and transposed)
+// hits_per_item hits of one primitive, its operands (forward and transposed)
 // staged in LDS, each wave walking its hits' samples in 32-column blocks.
 // Per block the wave
 //   1. recomputes the network, keeping the hi parts of the layer inputs in
@@ -39,13 +39,18 @@ struct Bwd {
   // of each factor, not compounded through the chain, keeps dW within about
   // 6e-4 of the FP64 result at the sizes tested; the transposed chain keeps
   // all three products.  (true: also delta_lo x_hi, with its own LDS plane.)
-  static constexpr bool DWS = false;
+  // The contact-point primitive has one sample per hit, so a weight-gradient
+  // entry sums few samples and their roundings do not average out: its
+  // (small) networks contract all three products, delta hi x input hi, delta
+  // lo x input hi and delta hi x input lo, with planes for both lo parts.
+  static constexpr bool DWS = N::SPLIT && N::CONTACT;
+  static constexpr bool DWX = N::SPLIT && N::CONTACT;
   // exchange planes of nw waves (32 samples each; rows padded by 16 bytes,
   // which keeps the 16-row operand reads free of bank conflicts): layer
   // inputs (the split form contracts the weight gradient with their hi part
   // only), deltas (hi), and the deltas' lo parts
   static constexpr int xsp(int nw) { return 32 * nw + (N::BF16 ? 8 : 4); }
-  static constexpr int planes(int nw) { return (HROWS + DROWS * (DWS ? 2 : 1)) * xsp(nw) * ESZ; }
+  static constexpr int planes(int nw) { return (HROWS * (DWX ? 2 : 1) + DROWS * (DWS ? 2 : 1)) * xsp(nw) * ESZ; }
   // Weights staged in LDS beside the planes.  Where they do not all fit, the
   // first layer's forward operands (requested ahead of the encoding, which
   // covers their latency) are read from global memory instead, L2-resident
@@ -66,6 +71,7 @@ struct Bwd {
   static constexpr int XH_OFF = 0;
   static constexpr int XD_OFF = XH_OFF + HROWS * XSP * ESZ;
   static constexpr int XDL_OFF = XD_OFF + DROWS * XSP * ESZ;                   // lo parts (split form)
+  static constexpr int XHL_OFF = XDL_OFF + (DWS ? DROWS * XSP * ESZ : 0);      // inputs' lo parts
   static constexpr int PLANES = planes(NW);
   static constexpr int W_OFF = rup(PLANES, 256);
   static constexpr bool G0 = !N::WIDE && staged(NW, 0) > LDS_MAX;
@@ -127,10 +133,11 @@ __device__ __forceinline__ void layer_bwd(const uint8_t* __restrict__ wb, int la
 }
 
 // publish this wave's 32 columns of a layer input (slots -> canonical rows)
-template <class N, int J, int NKS>
+template <class N, int J, int NKS, bool LO = false>
 __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const Hi<N, NKS>& a, int g,
                                               int colx) {
   using B = Bwd<N>;
+  constexpr int OFF = LO ? B::XHL_OFF : B::XH_OFF;
 #pragma unroll
   for (int s = 0; s < NKS; ++s) {
 #pragma unroll
@@ -141,7 +148,7 @@ __device__ __forceinline__ void publish_input(uint8_t* __restrict__ lds, const H
       int f = N::in_feat(J, g, t);
       if (f < 0) continue;
       if constexpr (N::BF16) {
-        reinterpret_cast<__bf16*>(lds + B::XH_OFF)[f * B::XSP + colx] = a.hi[s][e];
+        reinterpret_cast<__bf16*>(lds + OFF)[f * B::XSP + colx] = a.hi[s][e];
       } else {
         reinterpret_cast<float*>(lds + B::XH_OFF)[f * B::XSP + colx] = a.hi[s];
       }
@@ -193,14 +200,18 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
       const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
       const __bf16* xdl = reinterpret_cast<const __bf16*>(lds + B::XDL_OFF);
       const __bf16* xh = reinterpret_cast<const __bf16*>(lds + B::XH_OFF);
-      bf16x8 ones;
+      const __bf16* xhl = reinterpret_cast<const __bf16*>(lds + B::XHL_OFF);
+      bf16x8 ones, zeros;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
+      for (int e = 0; e < 8; ++e) {
+        ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
+        zeros[e] = (__bf16)0.f;
+      }
       // operands of one 32-sample k-step: delta row strip (hi, lo) and the
       // unit's input tiles (the bias tile contracts with ones); the next
       // k-step's are requested before this one's products
       struct KOps {
-        bf16x8 a, al, b[B::CPG(J)];
+        bf16x8 a, al, b[B::CPG(J)], bl[B::DWX ? B::CPG(J) : 1];
       };
       auto load = [&](int kk, KOps& o) {
         const int so = 32 * kk + 8 * kg;
@@ -211,6 +222,10 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
           const int ct = c0 + c;
           if (ct < B::CT(J)) o.b[c] = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
           else o.b[c] = ones;
+          if constexpr (B::DWX) {
+            if (ct < B::CT(J)) o.bl[c] = *reinterpret_cast<const bf16x8*>(xhl + (16 * ct + r16) * B::XSP + so);
+            else o.bl[c] = zeros;
+          }
         }
       };
       KOps ko[2];
@@ -224,6 +239,7 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
           if (c0 + c >= B::CTB(J)) continue;
           acc[c] = mfma16(o.a, o.b[c], acc[c]);
           if constexpr (B::DWS) acc[c] = mfma16(o.al, o.b[c], acc[c]);
+          if constexpr (B::DWX) acc[c] = mfma16(o.a, o.bl[c], acc[c]);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -318,13 +334,19 @@ struct Keep {
   static constexpr int NH = HI - H0 + 1;
   static constexpr int NG = N::NL - 1 - HI;
   float ph[3], pl[3];
+  float dd[N::CONTACT ? 3 : 1];   // contact-point primitive: the ray direction
   Hi<N, rup(N::HID_KS, N::KGRP)> ah[NH > 0 ? NH : 1];
+  Hi<N, rup(N::HID_KS, N::KGRP)> al[(Bwd<N>::DWX && NH > 0) ? NH : 1];   // lo parts (full-split weight gradient)
   Gates<N> gt[NG > 0 ? NG : 1];
 };
 
 template <class N, int LO, int HI, int J>
 __device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_hi(const Keep<N, LO, HI>& kp) {
   return kp.ah[J - Keep<N, LO, HI>::H0];
+}
+template <class N, int LO, int HI, int J>
+__device__ __forceinline__ const Hi<N, rup(N::HID_KS, N::KGRP)>& input_lo(const Keep<N, LO, HI>& kp) {
+  return kp.al[Bwd<N>::DWX ? J - Keep<N, LO, HI>::H0 : 0];
 }
 
 // ReLU gate of slot t of layer J's input (its pre-activation was positive)
@@ -350,7 +372,10 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int l
   relu_to_B<N>(acc, x);
   if constexpr (J >= Keep<N, LO, HI>::H0 && J <= HI) {
 #pragma unroll
-    for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) kp.ah[J - Keep<N, LO, HI>::H0].hi[i] = x.hi[i];
+    for (int i = 0; i < rup(N::HID_KS, N::KGRP); ++i) {
+      kp.ah[J - Keep<N, LO, HI>::H0].hi[i] = x.hi[i];
+      if constexpr (Bwd<N>::DWX) kp.al[J - Keep<N, LO, HI>::H0].hi[i] = x.lo[i];
+    }
   } else if constexpr (J > HI) {
     gates_of<N>(acc, kp.gt[J - HI - 1]);
   }
@@ -369,19 +394,20 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int l
 template <class N, int LO, int HI>
 __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wb0,
                                                int lane, const float ph[3], const float pl[3],
-                                               Keep<N, LO, HI>& kp) {
+                                               const float dd[3], Keep<N, LO, HI>& kp) {
   int g = lane / 32;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     kp.ph[a] = ph[a];
     kp.pl[a] = pl[a];
+    if constexpr (N::CONTACT) kp.dd[a] = dd[a];
   }
   f32x16 acc[N::RBH];
   {
     FwdOps<N, 0, N::ENC_KS> first;
     fwd_row_load<N, 0, N::ENC_KS>(wb0, wb0, lane, 0, first);
     float ev[N::ENC_KS * N::KSTEP];
-    encode_slots<N>(ph, pl, g, ev);
+    encode_input<N>(ph, pl, dd, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
     layer_fwd_from<N, 0, N::ENC_KS>(wb0, wb0, lane, a0, acc, first);
@@ -403,7 +429,10 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   constexpr bool DOWN = J > 0 && J - 1 >= LO;  // continue to layer J-1
   const int g = lane / 32;
   float ev[N::ENC_KS * N::KSTEP];
-  if constexpr (J == 0) encode_slots<N>(kp.ph, kp.pl, g, ev);
+  if constexpr (J == 0) {
+    if constexpr (N::CONTACT) encode_contact_slots<N>(kp.ph, kp.pl, kp.dd, g, ev);
+    else encode_slots<N>(kp.ph, kp.pl, g, ev);
+  }
   // the delta as the transposed product's B operand (also what is published)
   Act<N, rup(N::bks(J), N::KGRP)> Bd;
   if constexpr (DW || DOWN || J == 0) {
@@ -419,8 +448,15 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
 #pragma unroll
       for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.hi[i];
       publish_input<N, 0, rup(N::ENC_KS, N::KGRP)>(lds, h0, g, colx);
+      if constexpr (Bwd<N>::DWX) {
+#pragma unroll
+        for (int i = 0; i < rup(N::ENC_KS, N::KGRP); ++i) h0.hi[i] = a0.lo[i];
+        publish_input<N, 0, rup(N::ENC_KS, N::KGRP), true>(lds, h0, g, colx);
+      }
     } else {
       publish_input<N, J, rup(N::HID_KS, N::KGRP)>(lds, input_hi<N, LO, HI, J>(kp), g, colx);
+      if constexpr (Bwd<N>::DWX)
+        publish_input<N, J, rup(N::HID_KS, N::KGRP), true>(lds, input_lo<N, LO, HI, J>(kp), g, colx);
     }
   }
   // transposed product for the next delta (or the input gradient), overlapping the exchange
@@ -440,6 +476,21 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
       for (int r = 0; r < 16; ++r) dzn[rb][r] = gate<N, LO, HI, J>(kp, 16 * rb + r) ? da[rb][r] : 0.f;
     }
     chain_back<N, J - 1, LO, HI>(lds, wb, lane, q, colx, kp, dzn, dp, dacc);
+  } else if constexpr (J == 0 && N::CONTACT) {
+    // dL/d(delta) of the contact point from the input-feature gradient
+    // W_0^T delta_0 (the direction d carries no gradient)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dp[a] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 6 * N::L; ++t) {
+      const int pr = t / 12, r = t % 12, c = r % 6;
+      if (c < 3) continue;
+      const float gf = da[t / 16][t % 16];
+      const float mul = (float)(1 << (2 * pr)) * (g ? 2.f : 1.f) * 3.14159265358979f;
+      // d sin(m x)/dx = m cos(m x); d cos(m x)/dx = -m sin(m x)
+      const float dv = r < 6 ? mul * ev[12 * pr + 6 + c] : -mul * ev[12 * pr + c];
+      dp[c - 3] += gf * dv;
+    }
   } else if constexpr (J == 0) {
     // dL/dp of the sample from the input-feature gradient W_0^T delta_0
 #pragma unroll
@@ -478,8 +529,8 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   const int colx = 32 * q + col;
   const int wi = blockIdx.x;
   const int p = find_prim(ws.wi_off, args.P, wi);
-  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * kHitsPerItem;
-  const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
+  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * ws.hits_per_item;
+  const int nh = min(ws.hits_per_item, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
   const uint8_t* wglb = ws.wpack + (int64_t)p * ws.wpack_bytes;
   const uint8_t* wts = wglb;
@@ -553,12 +604,12 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
 #pragma unroll
       for (int r = 0; r < 3; ++r) gr[r] = args.grad_rgb[3 * ray + r];
     }
-    float ph[3], pl[3];
-    const float sk = sample_position(ws, hit, k, u, ph, pl);
+    float ph[3], pl[3], dd[3];
+    const float sk = sample_input<N>(ws, hit, k, u, ph, pl, dd);
     const float om = ((float)k + u) / (float)K;
     const bool last = valid && k == K - 1;
     Keep<N, LO, HI> kp;
-    f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lane, ph, pl, kp);
+    f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lane, ph, pl, dd, kp);
 
     // ---- compositing adjoint of the column ----
     const bool used = valid && k < nused;
@@ -631,11 +682,30 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
 
     // ---- per-hit geometry sums ----
-    float ee[3];
+    // (contact-point primitive: one sample per hit, dL/d(delta) and
+    // dL/d(optical-depth factor) only)
+    float gv[9];
+    if constexpr (N::CONTACT) {
+      gv[0] = dp[0];
+      gv[1] = dp[1];
+      gv[2] = dp[2];
+      gv[3] = gv[4] = gv[5] = gv[6] = gv[7] = 0.f;
+      gv[8] = dts;
+    } else {
+      float ee[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ee[a] = ws.hit_e[a * H + hit];
-    const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
-    float gv[9] = {dp[0], dp[1], dp[2], sk * dp[0], sk * dp[1], sk * dp[2], dtk, om * dtk, dts};
+      for (int a = 0; a < 3; ++a) ee[a] = ws.hit_e[a * H + hit];
+      const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
+      gv[0] = dp[0];
+      gv[1] = dp[1];
+      gv[2] = dp[2];
+      gv[3] = sk * dp[0];
+      gv[4] = sk * dp[1];
+      gv[5] = sk * dp[2];
+      gv[6] = dtk;
+      gv[7] = om * dtk;
+      gv[8] = dts;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       gv[i] = sc.incl(gv[i]);
@@ -705,9 +775,9 @@ static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items,
 hipError_t MSPLAT_TU_FN(launch_mlp_backward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
                                              int items, const float* ray_d, const float* grad_rgb,
                                              const float* grad_feat, float* g_mlp, hipStream_t s) {
-#define X(L_, W_, D_, O_, P_)                                                                   \
-  MSPLAT_MATCH(L_, W_, D_, O_, P_)                                                              \
-  return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_)>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, \
+#define X(L_, W_, D_, O_, P_, K_)                                                                   \
+  MSPLAT_MATCH(L_, W_, D_, O_, P_, K_)                                                              \
+  return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, \
                                                   grad_feat, g_mlp, s);
   MSPLAT_TU_NETS(X)
 #undef X

@@ -41,6 +41,17 @@ __host__ __device__ constexpr int phi_enc(int L, int g, int t) {
                    : (t < 3 * L + 3 ? (g == 0 ? t - 3 * L : (t == 3 * L ? 3 + 6 * L : -1)) : -1);
 }
 
+// The contact-point primitive's input [d; delta] (6 values) encoded per
+// component with L levels and no identity term (12 L values).  Canonical
+// order (also the weight layout): component c, level l, sin then cos at
+// index 2 L c + 2 l (+1), then the constant 1 of the first layer's bias at
+// 12 L.  Slot t of lane half g: levels 2 (t / 12) + g, within a level the
+// six sines then the six cosines; half 1 holds the constant after them.
+__host__ __device__ constexpr int phi_enc_contact(int L, int g, int t) {
+  return t < 6 * L ? 2 * L * ((t % 12) % 6) + 2 * (2 * (t / 12) + g) + (t % 12) / 6
+                   : (t == 6 * L && g == 1 ? 12 * L : -1);
+}
+
 __host__ __device__ constexpr int rup(int a, int b) { return (a + b - 1) / b * b; }
 // networks wider than this read their weights from global memory (see Net::WIDE)
 __host__ __device__ constexpr bool wide_net(int W) { return W > 64; }
@@ -48,20 +59,24 @@ __host__ __device__ constexpr bool wide_net(int W) { return W > 64; }
 // SPLIT_: bfloat16 operands carried as a sum of two bfloat16 values (hi, lo);
 // a product of two such operands is taken as hi*hi + hi*lo + lo*hi on the
 // matrix cores with float32 accumulation (about 16 significant bits).
-template <int L_, int W_, int D_, int NOUT_, bool BF16_, bool SPLIT_ = false>
+// CONTACT_: the contact-point primitive (one interaction per hit, input the
+// encoded [d; delta]); otherwise samples of the hit chord, input the encoded
+// local position.
+template <int L_, int W_, int D_, int NOUT_, bool BF16_, bool SPLIT_ = false, bool CONTACT_ = false>
 struct Net {
   static constexpr int L = L_, W = W_, D = D_, NOUT = NOUT_;
   static constexpr bool BF16 = BF16_;
   static constexpr bool SPLIT = SPLIT_;
+  static constexpr bool CONTACT = CONTACT_;
   static_assert(BF16 || !SPLIT, "split operands are a bfloat16 form");
   static constexpr int NSPLIT = SPLIT ? 2 : 1;
-  static constexpr int IN = 3 + 6 * L;
+  static constexpr int IN = CONTACT ? 12 * L : 3 + 6 * L;
   static constexpr int NL = D + 1;
   static constexpr int CF = NOUT - 4;
   static constexpr int NC = NOUT - 1;                 // rgb + features composited
   static constexpr int KSTEP = BF16 ? 8 : 1;          // slots per lane half per k-step
   static constexpr int KGRP = BF16 ? 1 : 4;           // k-steps per 16-byte operand group
-  static constexpr int ENC_SLOTS = 3 * L + 3;
+  static constexpr int ENC_SLOTS = CONTACT ? 6 * L + 1 : 3 * L + 3;
   static constexpr int ENC_KS = rup(ENC_SLOTS, KSTEP) / KSTEP;
   static constexpr int RBH = W / 32;
   static constexpr int HID_KS = 16 * RBH / KSTEP;
@@ -131,7 +146,8 @@ struct Net {
 
   // input feature (canonical index, -1 = padding) of an input slot of layer j
   __host__ __device__ static constexpr int in_feat(int j, int g, int t) {
-    return j == 0 ? (t < ENC_SLOTS ? phi_enc(L, g, t) : -1) : (phi_std(g, t) < W ? phi_std(g, t) : -1);
+    return j == 0 ? (t < ENC_SLOTS ? (CONTACT ? phi_enc_contact(L, g, t) : phi_enc(L, g, t)) : -1)
+                  : (phi_std(g, t) < W ? phi_std(g, t) : -1);
   }
 };
 
@@ -145,15 +161,17 @@ __device__ __forceinline__ float net_weight(const float* th, int j, int n, int f
   return th[N::off_w(j) + n * N::fin(j) + f];
 }
 
-// Compiled networks: (pe_freqs, hidden width, hidden layers, outputs, precision).
-// Networks up to 64 wide and wider ones are compiled in separate units (the
-// wide kernels with the compiler's default register assignment).
-#define MSPLAT_NETS_NARROW(X)                                                          \
-  X(4, 32, 2, 4, MSPLAT_FP32) X(4, 32, 2, 4, MSPLAT_BF16) X(4, 32, 2, 4, MSPLAT_BF16X3)    \
-  X(6, 64, 3, 4, MSPLAT_FP32) X(6, 64, 3, 4, MSPLAT_BF16) X(6, 64, 3, 4, MSPLAT_BF16X3)    \
-  X(6, 64, 3, 20, MSPLAT_FP32) X(6, 64, 3, 20, MSPLAT_BF16) X(6, 64, 3, 20, MSPLAT_BF16X3)
+// Compiled networks: (pe_freqs, hidden width, hidden layers, outputs,
+// precision, primitive).  Networks up to 64 wide and wider ones are compiled
+// in separate units (the wide kernels with the compiler's default register
+// assignment).
+#define MSPLAT_NETS_NARROW(X)                                                                            \
+  X(4, 32, 2, 4, MSPLAT_FP32, 0) X(4, 32, 2, 4, MSPLAT_BF16, 0) X(4, 32, 2, 4, MSPLAT_BF16X3, 0)          \
+  X(6, 64, 3, 4, MSPLAT_FP32, 0) X(6, 64, 3, 4, MSPLAT_BF16, 0) X(6, 64, 3, 4, MSPLAT_BF16X3, 0)          \
+  X(6, 64, 3, 20, MSPLAT_FP32, 0) X(6, 64, 3, 20, MSPLAT_BF16, 0) X(6, 64, 3, 20, MSPLAT_BF16X3, 0)       \
+  X(6, 32, 2, 4, MSPLAT_FP32, 1) X(6, 32, 2, 4, MSPLAT_BF16X3, 1)
 #define MSPLAT_NETS_WIDE(X) \
-  X(6, 128, 4, 20, MSPLAT_FP32) X(6, 128, 4, 20, MSPLAT_BF16) X(6, 128, 4, 20, MSPLAT_BF16X3)
+  X(6, 128, 4, 20, MSPLAT_FP32, 0) X(6, 128, 4, 20, MSPLAT_BF16, 0) X(6, 128, 4, 20, MSPLAT_BF16X3, 0)
 #define MSPLAT_NETS(X) MSPLAT_NETS_NARROW(X) MSPLAT_NETS_WIDE(X)
 
 // the networks of this translation unit, and the suffix of its launchers
@@ -164,9 +182,10 @@ __device__ __forceinline__ float net_weight(const float* th, int j, int n, int f
 #define MSPLAT_TU_NETS MSPLAT_NETS_NARROW
 #define MSPLAT_TU_FN(name) name##_narrow
 #endif
-#define MSPLAT_NET(L_, W_, D_, O_, P_) Net<L_, W_, D_, O_, (P_) != MSPLAT_FP32, (P_) == MSPLAT_BF16X3>
-#define MSPLAT_MATCH(L_, W_, D_, O_, P_) \
-  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && n.prec == (P_))
+#define MSPLAT_NET(L_, W_, D_, O_, P_, K_) \
+  Net<L_, W_, D_, O_, (P_) != MSPLAT_FP32, (P_) == MSPLAT_BF16X3, (K_) == 1>
+#define MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) \
+  if (n.L == L_ && n.W == W_ && n.D == D_ && n.NOUT == O_ && n.prec == (P_) && n.kind == (K_))
 
 __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);

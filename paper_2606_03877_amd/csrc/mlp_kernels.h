@@ -71,6 +71,62 @@ __device__ __forceinline__ void encode_slots(const float ph[3], const float pl[3
   for (int a = 0; a < 3; ++a) v[3 * N::L + a] = g == 0 ? ph[a] : (a == 0 ? 1.f : 0.f);
 }
 
+// encoding of the contact-point primitive's input [d; delta] into the lane
+// half's input slots (d exact, delta as a double-float)
+template <class N>
+__device__ __forceinline__ void encode_contact_slots(const float dh[3], const float dl[3], const float dd[3], int g,
+                                                     float (&v)[N::ENC_KS * N::KSTEP]) {
+#pragma unroll
+  for (int t = 0; t < N::ENC_KS * N::KSTEP; ++t) v[t] = 0.f;
+#pragma unroll
+  for (int pr = 0; pr < N::L / 2; ++pr) {
+    // level 2*pr + g
+    float mul = (float)(1 << (2 * pr)) * (g ? 2.f : 1.f);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float sn, cs;
+      if (c < 3) sincospi_df<N::BF16>(dd[c], 0.f, mul, sn, cs);
+      else sincospi_df<N::BF16>(dh[c - 3], dl[c - 3], mul, sn, cs);
+      v[12 * pr + c] = sn;
+      v[12 * pr + 6 + c] = cs;
+    }
+  }
+  v[6 * N::L] = g == 1 ? 1.f : 0.f;
+}
+
+// the first layer's input of one sample: the encoded local position (ph, pl)
+// of a chord sample, or the encoded [dd; delta = (ph, pl)] of a contact point
+template <class N>
+__device__ __forceinline__ void encode_input(const float ph[3], const float pl[3], const float dd[3], int g,
+                                             float (&v)[N::ENC_KS * N::KSTEP]) {
+  if constexpr (N::CONTACT) encode_contact_slots<N>(ph, pl, dd, g, v);
+  else encode_slots<N>(ph, pl, g, v);
+}
+
+// The network input of a hit's sample.  Chord primitives: the sample
+// position p = p_c + s e in the local frame (double-float, returns s).
+// Contact-point primitive (one sample per hit): the residual delta
+// (double-float, in the position arrays) and the ray direction d (in the
+// direction arrays); returns 0.
+template <class N>
+__device__ __forceinline__ float sample_input(const Workspace& ws, int hit, int k, float u, float ph[3], float pl[3],
+                                              float dd[3]) {
+  if constexpr (N::CONTACT) {
+    const int64_t H = ws.hit_cap;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      ph[a] = ws.hit_pc[a * H + hit];
+      pl[a] = ws.hit_pc_lo[a * H + hit];
+      dd[a] = ws.hit_e[a * H + hit];
+    }
+    return 0.f;
+  } else {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dd[a] = 0.f;
+    return sample_position(ws, hit, k, u, ph, pl);
+  }
+}
+
 template <class N>
 struct Operands {
   // bf16: one bf16x8 per k-step; f32: one float per k-step (padded to groups of 4)

@@ -280,8 +280,8 @@ __global__ __launch_bounds__(256) void slot_backward_prims_kernel(Workspace ws, 
           for (int k = 0; k < 4; ++k) acc[q][k] = make_float4(0.f, 0.f, 0.f, 0.f);
         while (ws.wi_off[p + 1] <= item) ++p;
       }
-      const int first = ws.prim_off[p] + (item - ws.wi_off[p]) * kHitsPerItem;
-      const int nh = min(kHitsPerItem, ws.prim_off[p + 1] - first);
+      const int first = ws.prim_off[p] + (item - ws.wi_off[p]) * ws.hits_per_item;
+      const int nh = min(ws.hits_per_item, ws.prim_off[p + 1] - first);
       // this lane's hit: weight, gates, ray (and, once, its contact point's
       // geometry terms)
       float W = 0.f, g[4] = {0.f, 0.f, 0.f, 0.f};

@@ -22,7 +22,7 @@ __all__ = ["NetSpec", "RenderOpts", "Context", "Renderer", "MLPSplat", "render",
            "msplat_render_forward", "msplat_render_backward", "msplat_get_stats",
            "msplat_debug_hits", "msplat_workspace_size", "msplat_num_params",
            "msplat_render_forward_f64", "msplat_profile_enable", "msplat_profile_read",
-           "msplat_slot_forward", "msplat_render_backward_slots"]
+           "msplat_slot_forward", "msplat_render_backward_slots", "msplat_autotune"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -33,12 +33,15 @@ class NetSpec:
     hidden_layers: int
     out_dim: int
     precision: str = "fp32"          # "fp32" | "bf16" | "bf16x3"
+    primitive: str = "chord"         # "chord" (samples of the support's chord) | "contact" (the paper's
+                                     # contact-point primitive: one interaction per hit)
 
     def c(self) -> _lib.Model:
         prec = {"fp32": _lib.MSPLAT_FP32, "bf16": _lib.MSPLAT_BF16,
                 "bf16x3": _lib.MSPLAT_BF16X3}[self.precision]
+        kind = {"chord": _lib.MSPLAT_CHORD, "contact": _lib.MSPLAT_CONTACT}[self.primitive]
         return _lib.Model(self.num_prims, self.pe_freqs, self.hidden_width, self.hidden_layers,
-                          self.out_dim, prec)
+                          self.out_dim, prec, kind)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -52,12 +55,13 @@ class RenderOpts:
     jitter_seed: int = 0
     background: Sequence[float] = (0.0, 0.0, 0.0)
     order: int = 0   # 0: each ray's own contact depth; 1: tile order (packet virtual ray)
+    hits_per_item: int = 0   # work-item size of the network kernels: 16, 32, 64; 0 = autotuned (64 untuned)
 
     def c(self) -> _lib.Opts:
         bg = (ctypes.c_float * 3)(*[float(b) for b in self.background])
         return _lib.Opts(self.samples_fixed, self.samples_min, self.samples_max,
                          float(self.samples_per_unit), float(self.t_stop), self.jitter,
-                         self.jitter_seed & 0xFFFFFFFF, bg, self.order)
+                         self.jitter_seed & 0xFFFFFFFF, bg, self.order, self.hits_per_item)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -136,7 +140,18 @@ def msplat_get_stats(ctx: Context, ws: torch.Tensor, stream=None) -> dict:
     st = ctx.lib.msplat_get_stats(ctx.handle, _p(ws), ws.numel(), ctypes.byref(s), _stream(stream))
     if st != _lib.MSPLAT_OK:
         raise MsplatError(st, "msplat_get_stats")
-    return {f: getattr(s, f) for f, _ in _lib.Stats._fields_ if f != "reserved"}
+    return {f: getattr(s, f) for f, _ in _lib.Stats._fields_}
+
+
+def msplat_autotune(ctx: Context, spec: NetSpec, opts: RenderOpts, center, scale, quat, mlp, ray_o, ray_d,
+                    rgb, trans, feat, grad_rgb, ws, g_center, g_scale, g_quat, g_mlp, stream=None):
+    """Returns (status, chosen hits per work item)."""
+    chosen = ctypes.c_int32(0)
+    st = ctx.lib.msplat_autotune(
+        ctx.handle, ctypes.byref(spec.c()), ctypes.byref(opts.c()), _p(center), _p(scale), _p(quat), _p(mlp),
+        _p(ray_o), _p(ray_d), int(ray_o.shape[0]), _p(rgb), _p(trans), _p(feat), _p(grad_rgb), _p(ws), ws.numel(),
+        _p(g_center), _p(g_scale), _p(g_quat), _p(g_mlp), ctypes.byref(chosen), _stream(stream))
+    return st, int(chosen.value)
 
 
 def msplat_profile_enable(ctx: Context, enable: bool = True) -> None:
@@ -312,6 +327,26 @@ class Renderer:
         if st != _lib.MSPLAT_OK:
             raise MsplatError(st, "msplat_render_backward_slots")
         return tuple(g)
+
+    def autotune(self, center, scale, quat, mlp, ray_o, ray_d, grad_rgb=None) -> int:
+        """Time the work-item sizes on this workload (forward, and backward
+        with ``grad_rgb``); later renders of it with hits_per_item = 0 use the
+        fastest.  Returns the chosen size."""
+        self.check_inputs(center, scale, quat, mlp, ray_o, ray_d)
+        R = ray_o.shape[0]
+        P = self.spec.num_prims
+        cf = self.spec.out_dim - 4
+        rgb, trans, feat, ws = self.forward(center, scale, quat, mlp, ray_o, ray_d)
+        g = [torch.empty(sh, dtype=torch.float32, device=self.device)
+             for sh in ((P, 3), (P, 3), (P, 4), (P, self.n_params))]
+        if grad_rgb is not None:
+            grad_rgb = grad_rgb.contiguous().float()
+            _check(grad_rgb, "grad_rgb", (R, 3))
+        st, chosen = msplat_autotune(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o, ray_d, rgb,
+                                     trans, feat, grad_rgb, ws, *g)
+        if st != _lib.MSPLAT_OK:
+            raise MsplatError(st, "msplat_autotune")
+        return chosen
 
     def stats(self, ws) -> dict:
         return msplat_get_stats(self.ctx, ws)

@@ -1,0 +1,80 @@
+"""The work-item autotuner: every work-item size the network kernels can run
+with (16, 32, 64 hits of one primitive per workgroup) renders and
+differentiates within the tolerances of the FP64 oracle, and the tuner's
+choice is recorded and used."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_cases import (gpu_render, gradient_mask, opts_of, oracle_model, oracle_opts, oracle_render, ray_nused,
+                       scene, view_rays)
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("center", "scale", "quat", "mlp")
+TOL = {"fp32": 1e-5, "bf16x3": 2e-3}
+
+
+@pytest.mark.parametrize("hpi", [16, 32, 64])
+@pytest.mark.parametrize("ci,w,h,precision", [(1, 64, 50, "bf16x3"), (4, 44, 40, "bf16x3"), (4, 44, 40, "fp32"),
+                                              (3, 40, 30, "bf16x3")])
+def test_every_work_item_size_matches_oracle(hpi, ci, w, h, precision):
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, w, h)
+    opts = dataclasses.replace(opts_of(cfg), hits_per_item=hpi)
+    R = len(o)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    assert g["stats"]["hits_per_item"] == hpi
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True, precision=precision)
+    same = ray_nused(g) == ref_fwd["n_used"]
+    err = float(np.abs(g["rgb"] - ref_fwd["rgb"])[same].max())
+    assert err <= TOL[precision]
+    keep = gradient_mask(ray_nused(g), ref_fwd, precision, R)
+    g_rgb = (np.random.default_rng(1000 * ci + 7).standard_normal((R, 3)) / R).astype(np.float32)
+    g_rgb[~keep] = 0.0
+    cf = cfg.out_dim - 4
+    g_ft = None
+    if cf > 0:
+        g_ft = (np.random.default_rng(1000 * ci + 8).standard_normal((R, cf)) / R).astype(np.float32)
+        g_ft[~keep] = 0.0
+    _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64), oracle_model(cfg),
+                                            oracle_opts(opts, precision), grad_rgb=g_rgb, grad_feat=g_ft)
+    t, to, td = g["dev"]
+    out = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                 torch.from_numpy(g_rgb).cuda(), None,
+                                 None if g_ft is None else torch.from_numpy(g_ft).cuda())
+    for k, v in zip(KEYS, out):
+        rel = float(np.abs(v.cpu().numpy() - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
+        print(f"config {ci} {precision} {hpi} hits per item {k}: {rel:.2e}")
+        assert rel <= TOL[precision], k
+
+
+def test_autotune_records_and_uses_its_choice():
+    from paper_2606_03877_amd import NetSpec, RenderOpts, Renderer
+    ci = 1
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 200, 160)
+    opts = opts_of(cfg)
+    assert opts.hits_per_item == 0
+    g = gpu_render(ci, "bf16x3", sc, o, d, opts)
+    r = g["renderer"]
+    assert g["stats"]["hits_per_item"] == 64        # untuned default
+    t, to, td = g["dev"]
+    grad = torch.full((len(o), 3), 1.0 / len(o), device="cuda")
+    chosen = r.autotune(t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
+    assert chosen in (16, 32, 64)
+    _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    assert r.stats(ws)["hits_per_item"] == chosen
+    # another workload (ray count) is not covered by the choice
+    _, _, _, ws2 = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to[:640], td[:640])
+    assert r.stats(ws2)["hits_per_item"] == 64
+    # an explicit size wins
+    r2 = Renderer(r.spec, dataclasses.replace(opts, hits_per_item=16))
+    _, _, _, ws3 = r2.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    assert r2.stats(ws3)["hits_per_item"] == 16

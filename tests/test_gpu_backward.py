@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import synth
-from gpu_cases import (RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle_opts, oracle_render,
+from gpu_cases import (gpu_render, gradient_mask, opts_of, oracle_model, oracle_opts, oracle_render,
                        ray_nused, scene, spec_of, to_dev, view_rays)
 
 pytestmark = pytest.mark.gpu
@@ -28,23 +28,18 @@ def _grads(ci, precision, w, h, with_trans=False, t_stop=None):
     g_ft = (rng.standard_normal((R, cf)) / R).astype(np.float32) if cf > 0 else None
     g = gpu_render(ci, precision, sc, o, d, opts)
     # a termination cut on a neighbouring sample (threshold crossing within
-    # rounding) and a ReLU gate within rounding of its switching point are
-    # discrete decisions either side may take the other way: such rays carry
-    # no upstream gradient on either side
-    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True)
-    same = ray_nused(g) == ref_fwd["n_used"]
-    clear = ref_fwd["relu_margin"] >= RELU_AMBIGUOUS[precision]
-    print(f"rays with a different cut sample: {int((~same).sum())} of {R}; "
-          f"with a ReLU gate within rounding: {int((~clear).sum())}")
-    keep = same & clear
-    assert keep.sum() >= R // 4
+    # rounding) and a ReLU gate within rounding of its switching point (in the
+    # form's own arithmetic) are discrete decisions either side may take the
+    # other way: such rays carry no upstream gradient on either side
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True, precision=precision)
+    keep = gradient_mask(ray_nused(g), ref_fwd, precision, R)
     g_rgb[~keep] = 0.0
     if g_tr is not None:
         g_tr[~keep] = 0.0
     if g_ft is not None:
         g_ft[~keep] = 0.0
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
-                                            oracle_model(cfg), oracle_opts(opts), grad_rgb=g_rgb,
+                                            oracle_model(cfg), oracle_opts(opts, precision), grad_rgb=g_rgb,
                                             grad_trans=g_tr, grad_feat=g_ft)
     t, to, td = g["dev"]
     gt = None if g_tr is None else torch.from_numpy(g_tr).cuda()
@@ -102,10 +97,8 @@ def test_autograd_function_mse_matches_direct_backward():
     # rays whose cut or ReLU gates are decided within rounding are masked out of the loss
     _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
     off, _, _, nused = r.hits(ws, R)
-    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True)
-    keep = ((ray_nused({"ray_off": off, "hit_nused": nused}) == ref_fwd["n_used"])
-            & (ref_fwd["relu_margin"] >= RELU_AMBIGUOUS["fp32"]))
-    assert keep.sum() >= R // 2
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True, precision="fp32")
+    keep = gradient_mask(ray_nused({"ray_off": off, "hit_nused": nused}), ref_fwd, "fp32", R)
     mask = torch.from_numpy(keep.astype(np.float32)).cuda()[:, None]
     params = {k: t[k].clone().requires_grad_(True) for k in KEYS}
     rgb, trans, feat = render(r, params["center"], params["scale"], params["quat"], params["mlp"], to, td)
@@ -139,8 +132,12 @@ def test_full_size_gradient_of_sampled_rays(ci, precision):
     opts = opts_of(cfg)
     g = gpu_render(ci, precision, sc, o, d, opts)
     idx = np.sort(np.random.default_rng(78).choice(len(o), 256, replace=False))
-    ref_fwd = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx, margins=True)
-    keep = (ray_nused(g)[idx] == ref_fwd["n_used"]) & (ref_fwd["relu_margin"] >= RELU_AMBIGUOUS[precision])
+    ref_fwd = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx, margins=True, precision=precision)
+    keep = gradient_mask(ray_nused(g)[idx], ref_fwd, precision, len(idx))
+    # hit lists of the sampled rays, bit-exact
+    for n, i in enumerate(idx):
+        np.testing.assert_array_equal(g["prim"][g["ray_off"][i]:g["ray_off"][i + 1]],
+                                      ref_fwd["prim"][ref_fwd["ray_off"][n]:ref_fwd["ray_off"][n + 1]])
     rng = np.random.default_rng(1000 * ci + 5)
     g_sub = rng.standard_normal((len(idx), 3)) / len(idx)
     g_sub[~keep] = 0.0
@@ -160,7 +157,7 @@ def test_full_size_gradient_of_sampled_rays(ci, precision):
                                  None if g_ft is None else torch.from_numpy(g_ft).cuda())
     got = dict(zip(KEYS, [x.cpu().numpy() for x in out]))
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o[idx].astype(np.float64), d[idx].astype(np.float64),
-                                            oracle_model(cfg), oracle_opts(opts),
+                                            oracle_model(cfg), oracle_opts(opts, precision),
                                             grad_rgb=g_rgb[idx].astype(np.float64),
                                             grad_feat=None if g_ft is None else g_ft[idx].astype(np.float64),
                                             ray_ids=idx)

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import synth
-from gpu_cases import (RELU_AMBIGUOUS, compare_rgb, gpu_render, oracle_model, oracle_opts, oracle_render,
+from gpu_cases import (compare_rgb, gpu_render, gradient_mask, oracle_model, oracle_opts, oracle_render,
                        ray_nused, scene)
 
 pytestmark = pytest.mark.gpu
@@ -43,7 +43,7 @@ def test_clipped_chords_background_midpoints(precision, t_stop):
     sc, o, d = _rays_from_inside(ci, 600, seed=31)
     opts = _opts(t_stop)
     g = gpu_render(ci, precision, sc, o, d, opts)
-    ref = oracle_render(ci, sc, o, d, opts, margins=True)
+    ref = oracle_render(ci, sc, o, d, opts, margins=True, precision=precision)
     np.testing.assert_array_equal(g["ray_off"], ref["ray_off"])
     np.testing.assert_array_equal(g["prim"], ref["prim"])
     c = compare_rgb(g, ref, TOL[precision], opts.t_stop)
@@ -55,8 +55,7 @@ def test_clipped_chords_background_midpoints(precision, t_stop):
     assert c["max_err"] <= TOL[precision]
     assert c["cut_mismatch_err"] <= opts.t_stop + TOL[precision]
     # gradients, rays with a cut or gate decided within rounding left out
-    same = ray_nused(g) == ref["n_used"]
-    keep = same & (ref["relu_margin"] >= RELU_AMBIGUOUS[precision])
+    keep = gradient_mask(ray_nused(g), ref, precision, len(o))
     g_rgb = (np.random.default_rng(32).standard_normal((len(o), 3)) / len(o)).astype(np.float32)
     g_rgb[~keep] = 0.0
     t, to, td = g["dev"]
@@ -64,7 +63,7 @@ def test_clipped_chords_background_midpoints(precision, t_stop):
                                  torch.from_numpy(g_rgb).cuda())
     got = dict(zip(KEYS, [x.cpu().numpy() for x in out]))
     _, _, _, grads, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
-                                              oracle_model(synth.CONFIGS[ci]), oracle_opts(opts),
+                                              oracle_model(synth.CONFIGS[ci]), oracle_opts(opts, precision),
                                               grad_rgb=g_rgb)
     for k in KEYS:
         err = float(np.abs(got[k] - grads[k]).max() / max(np.abs(grads[k]).max(), 1e-30))

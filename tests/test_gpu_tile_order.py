@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import synth
-from gpu_cases import (RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle_opts, oracle_render,
+from gpu_cases import (MASK_MAX, RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle_opts, oracle_render,
                        ray_nused, scene, spec_of, to_dev, view_rays)
 
 pytestmark = pytest.mark.gpu
@@ -100,15 +100,16 @@ def test_tile_order_gradients_match_oracle(ci, w, h, precision, tol):
     R = len(o)
     g_rgb = (np.random.default_rng(1000 * ci + 8).standard_normal((R, 3)) / R).astype(np.float32)
     g = gpu_render(ci, precision, sc, o, d, opts)
-    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True)
+    ref_fwd = oracle_render(ci, sc, o, d, opts, margins=True, precision=precision)
     same = check_order(g, ref_fwd, tile_keys(sc, o, d))
-    # rays whose order, cut or ReLU gates are decided within rounding carry no
-    # upstream gradient on either side
+    # rays whose order, cut or ReLU gates (in the form's arithmetic) are
+    # decided within rounding carry no upstream gradient on either side
     keep = same & (ray_nused(g) == ref_fwd["n_used"]) & (ref_fwd["relu_margin"] >= RELU_AMBIGUOUS[precision])
-    assert keep.sum() >= R // 4
+    print(f"rays left out: {R - int(keep.sum())} of {R}")
+    assert R - keep.sum() <= MASK_MAX * R
     g_rgb[~keep] = 0.0
     _, _, _, ref, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64), oracle_model(cfg),
-                                            oracle_opts(opts), grad_rgb=g_rgb)
+                                            oracle_opts(opts, precision), grad_rgb=g_rgb)
     t, to, td = g["dev"]
     got = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
                                  torch.from_numpy(g_rgb).cuda())

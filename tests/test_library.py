@@ -42,10 +42,16 @@ def test_status_strings_and_param_count(lib):
     assert b"workspace" in lib.msplat_status_string(2)
     import synth
     for cfg in synth.CONFIGS:
-        if cfg.primitive != "chord":
-            continue
-        spec = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim)
+        spec = NetSpec(cfg.num_prims, cfg.pe_freqs, cfg.hidden_width, cfg.hidden_layers, cfg.out_dim,
+                       primitive=cfg.primitive)
         assert lib.msplat_num_params(ctypes.byref(spec.c())) == synth.num_params(cfg)
+        out = ctypes.c_uint64()
+        assert lib.msplat_workspace_size(ctypes.byref(spec.c()), 1000, 1000, ctypes.byref(out)) == _lib.MSPLAT_OK
+    # the contact-point primitive: the paper's 72-32-32-4 network, 12 L inputs
+    assert lib.msplat_num_params(ctypes.byref(NetSpec(4, 6, 32, 2, 4, primitive="contact").c())) == \
+        72 * 32 + 32 + 32 * 32 + 32 + 32 * 4 + 4
+    bad_kind = _lib.Model(8, 6, 32, 2, 4, 0, 7)
+    assert lib.msplat_num_params(ctypes.byref(bad_kind)) == 0
 
 
 def test_host_argument_checks(lib):

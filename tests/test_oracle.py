@@ -815,3 +815,107 @@ def test_slot_feature_gradients_match_central_differences():
             np.testing.assert_allclose(grads[key].reshape(-1)[idx], fd, rtol=1e-5, atol=1e-9)
             checked += 1
     assert checked == 10
+
+
+# ---------------------------------------------------------------------------
+# ReLU gates taken in the kernel's bfloat16 forms (oracle.gate_preacts)
+# ---------------------------------------------------------------------------
+
+class _Dims:
+    """A network shape for the gate tests: layer_dims only."""
+
+    def __init__(self, *dims):
+        self.dims = dims
+
+    def layer_dims(self):
+        return [(self.dims[i], self.dims[i + 1]) for i in range(len(self.dims) - 1)]
+
+
+def test_bf16_rounding_by_hand():
+    # bfloat16 has 8 significant bits: the spacing above 1 is 2^-7
+    vals = [1 + 2 ** -8,            # halfway between 1 and 1 + 2^-7: ties to the even 1
+            1 + 3 * 2 ** -8,        # halfway between 1 + 2^-7 and 1 + 2^-6: ties to the even 1 + 2^-6
+            1 + 2 ** -8 + 2 ** -20,  # just above halfway: up
+            -(2 + 2 ** -6),         # exact (spacing 2^-6 above 2)
+            3.0 * 2 ** -130,        # a subnormal with bits only above the low 16: kept
+            2.0 ** -140]            # a subnormal whose bits all lie in the low 16: rounded to 0
+    want = [1.0, 1 + 2 ** -6, 1 + 2 ** -7, -(2 + 2 ** -6), 3.0 * 2 ** -130, 0.0]
+    got = oracle.bf16_round(np.array(vals))
+    np.testing.assert_array_equal(got, want)
+    # and the library's own conversion agrees on random float32 values
+    x = np.random.default_rng(4).standard_normal(5000).astype(np.float32) * 10.0 ** np.random.default_rng(5).integers(-6, 6, 5000)
+    np.testing.assert_array_equal(oracle.bf16_round(x), torch.from_numpy(x).bfloat16().double().numpy())
+
+
+def test_split_pairs_carry_sixteen_bits():
+    x = np.random.default_rng(6).standard_normal(5000).astype(np.float32).astype(np.float64)
+    hi, lo = oracle.split_bf16(x)
+    assert np.all(np.abs(hi + lo - x) <= 2.0 ** -16 * np.abs(x))
+    # a value with at most 16 significant bits is carried exactly
+    y = np.array([1 + 2 ** -9 + 2 ** -15, -3.0 * (1 + 2 ** -12)])
+    hi, lo = oracle.split_bf16(y)
+    np.testing.assert_array_equal(hi + lo, y)
+
+
+def test_gate_taken_in_the_kernel_form_by_hand():
+    """w = 1 + 2^-9 + 2^-20 splits to (1, 2^-9) and rounds to 1; with x = 1 and
+    first-layer bias -(1 + 2^-9) (split (-1, -2^-9), rounded -1) the FP64
+    pre-activation is 2^-20 > 0 but both bfloat16 forms see exactly 0: the gate
+    is closed there, open in FP64."""
+    m = _Dims(1, 1, 1)
+    w0, b0, w1, b1 = 1 + 2 ** -9 + 2 ** -20, -(1 + 2 ** -9), 1.0, 0.0
+    theta = torch.tensor([w0, b0, w1, b1], dtype=torch.float64)
+    x = torch.ones((1, 1), dtype=torch.float64)
+    for form in ("bf16", "bf16x3"):
+        z, = oracle.gate_preacts(theta, x, m, form)
+        assert z[0, 0] == 0.0
+    # the FP64 branch passes the 2^-20, the kernel-form branch nothing, and the
+    # gradient follows the branch: d out / d w0 = w1 x on the open branch, 0 closed
+    for form, val, gw in (("fp64", 2.0 ** -20, 1.0), ("bf16x3", 0.0, 0.0)):
+        th = theta.clone().requires_grad_(True)
+        out = oracle.mlp_apply(th, x, m, gate_form=form)
+        assert float(out) == val
+        out.sum().backward()
+        assert float(th.grad[0]) == gw
+    # a hidden layer's bias is a float32 value added as it is: z = 1 * 1 + b1
+    m2 = _Dims(1, 1, 1, 1)
+    b1 = -(1 + 2 ** -12)                       # not a bfloat16 value
+    th2 = torch.tensor([1.0, 0.0, 1.0, b1, 1.0, 0.0], dtype=torch.float64)
+    z0, z1 = oracle.gate_preacts(th2, x, m2, "bf16")
+    assert z0[0, 0] == 1.0 and z1[0, 0] == -(2.0 ** -12)
+
+
+def test_gates_match_fp64_away_from_zero_and_exactly_on_bf16_operands():
+    rng = np.random.default_rng(8)
+    m = _Dims(5, 16, 16, 4)
+    n = sum(i * o + o for i, o in m.layer_dims())
+    # operands that bfloat16 holds exactly (multiples of 2^-6 in [-2, 2]) and
+    # sums exact in float64: the emulated pre-activations equal FP64's
+    theta = rng.integers(-128, 129, n) / 64.0
+    x = rng.integers(-128, 129, (50, 5)) / 64.0
+    zs_fp = []
+    h = x
+    off = 0
+    for li, (fi, fo) in enumerate(m.layer_dims()[:-1]):
+        w = theta[off:off + fi * fo].reshape(fo, fi)
+        off += fi * fo
+        b = theta[off:off + fo]
+        off += fo
+        z = h @ w.T + b
+        zs_fp.append(z)
+        h = np.maximum(z, 0)
+    # (layer 2 inputs are sums of products of such values: exact in bf16x3 pairs
+    # only while they keep 16 significant bits, so compare the first layer exactly)
+    for form in ("bf16", "bf16x3"):
+        zs = oracle.gate_preacts(torch.from_numpy(theta), torch.from_numpy(x), m, form)
+        np.testing.assert_array_equal(zs[0], zs_fp[0])
+    # random operands: the split form's pre-activations stay within 2^-15 of the
+    # scale sum |w||x| of FP64, so every gate farther than that agrees
+    theta = rng.standard_normal(n) * 0.5
+    x = rng.standard_normal((400, 5))
+    zs = oracle.gate_preacts(torch.from_numpy(theta), torch.from_numpy(x), m, "bf16x3")
+    w0 = theta[:80].reshape(16, 5)
+    b0 = theta[80:96]
+    z0 = x @ w0.T + b0
+    scale = np.abs(x) @ np.abs(w0).T + np.abs(b0)
+    assert np.all(np.abs(zs[0] - z0) <= 2.0 ** -15 * scale)
