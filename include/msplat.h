@@ -189,6 +189,27 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* model, const mspl
                           void* ws, uint64_t ws_bytes, uint64_t* need_bytes, void* stream);
 
 /*
+ * msplat_render_forward for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same render, with the workspace taken from a device array
+ * the library holds, MSPLAT_NOALLOC_SCRATCH_BYTES (256 MiB) on every device
+ * it runs on, until the process ends.  The call allocates nothing; the caller
+ * still passes inputs and outputs.  It returns MSPLAT_E_CAPACITY (and the
+ * bytes the render needs in *need_bytes, which may be NULL) when the render
+ * needs more than the array holds.  Every call on a device shares that
+ * device's array, and calls of it that overlap on one device race (as calls
+ * that share a workspace do): serialise them.  The workspace is internal, so
+ * a backward, msplat_get_stats and msplat_debug_hits need a forward into a
+ * caller workspace (msplat_render_forward).
+ */
+#define MSPLAT_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int msplat_render_forward_noalloc(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
+                                  const float* center, const float* scale, const float* quat,
+                                  const float* mlp, const float* ray_o, const float* ray_d,
+                                  int64_t num_rays, float* rgb, float* trans, float* feat,
+                                  uint64_t* need_bytes, void* stream);
+
+/*
  * Backward of the forward call that last wrote `ws` with the same arguments
  * (same network shape and precision, ray count and workspace size; a call
  * that differs in any of them returns MSPLAT_E_STATE before launching work).

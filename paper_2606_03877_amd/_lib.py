@@ -64,6 +64,12 @@ EXPORTS = {
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
+    "msplat_render_forward_noalloc": (ctypes.c_int, [
+        ctypes.c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts),
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]),
     "msplat_render_backward": (ctypes.c_int, [
         ctypes.c_void_p, ctypes.POINTER(Model), ctypes.POINTER(Opts),
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,

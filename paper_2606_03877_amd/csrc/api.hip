@@ -38,8 +38,15 @@ struct TuneEntry {
 };
 constexpr int kTuneSlots = 32;
 
+// The workspace of msplat_render_forward_noalloc: a device array of the
+// library's own (each device holds its copy until the process ends).  Host
+// code never uses this name as an address: msplat_create looks up the
+// array's address on its device and keeps it in the context.
+static __device__ __align__(256) uint8_t scratch[MSPLAT_NOALLOC_SCRATCH_BYTES];
+
 struct msplat_ctx {
   int device;
+  void* scratch_ptr = nullptr;   // this device's scratch array
   bool profiling = false;
   TuneEntry tuned[kTuneSlots];
   int num_tuned = 0;
@@ -295,6 +302,11 @@ int msplat_create(int device, msplat_ctx** out) {
   DeviceGuard dg(device);
   msplat_ctx* c = new msplat_ctx();
   c->device = device;
+  // the scratch array's address on this device (the device is current)
+  if (hipGetSymbolAddress(&c->scratch_ptr, HIP_SYMBOL(scratch)) != hipSuccess || !c->scratch_ptr) {
+    delete c;
+    return MSPLAT_E_HIP;
+  }
   c->last_ws = nullptr;
   c->last_items = -1;
   c->last_hits = -1;
@@ -430,6 +442,18 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   ctx->last_shape = n;
   ctx->last_hpi = ws.hits_per_item;
   return MSPLAT_OK;
+}
+
+int msplat_render_forward_noalloc(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o,
+                                  const float* center, const float* scale, const float* quat, const float* mlp,
+                                  const float* ray_o, const float* ray_d, int64_t R, float* rgb, float* trans,
+                                  float* feat, uint64_t* need_bytes, void* stream) {
+  if (!ctx || !ctx->scratch_ptr) return MSPLAT_E_INVALID;
+  // every launch of the forward clears what it reads before writing it (the
+  // counters, per-primitive counts and the first ray offset), so the array's
+  // contents from an earlier call do not matter
+  return msplat_render_forward(ctx, m, o, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat,
+                               ctx->scratch_ptr, MSPLAT_NOALLOC_SCRATCH_BYTES, need_bytes, stream);
 }
 
 // slot-feature arguments of a backward (null when it carries none)
