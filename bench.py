@@ -90,6 +90,13 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     from paper_2606_03877_amd import render, msplat_profile_enable, msplat_profile_read
     r, opts = setup(cfg, precision, order=order)
     leaf = {k: v.clone().requires_grad_(True) for k, v in prm.items()}
+    # the work-item size for this network and workload, chosen by the
+    # library's autotuner before anything is timed (forward and backward of
+    # the MSE step's upstream gradient)
+    with torch.no_grad():
+        rgb0 = r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)[0]
+    hpi = r.autotune(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd,
+                     (2.0 / rgb0.numel()) * (rgb0 - target) if train else None)
 
     def step():
         for v in leaf.values():
@@ -138,6 +145,7 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     hits = r.hits(ws, R)[:2] if want_hits else None
     return {
         "hits": hits,
+        "hits_per_item": hpi,
         "fwdbwd_ms": 1e3 * (t1 - t0) / steps if train else None,
         "fwd_ms": 1e3 * (f1 - f0) / steps,
         "fwdbwd_rays_per_s": R * steps / (t1 - t0) if train else None,
@@ -594,7 +602,8 @@ def main():
         "config": {"workload": workload_name(cfg),
                    "rays": R, "hits": int(st["num_hits"]), "samples": int(st["num_samples"]),
                    "terminated_rays": int(st["num_terminated"]),
-                   "mlp_precision": "bf16 hi+lo operand pairs (3 products), fp32 accumulate"},
+                   "mlp_precision": "bf16 hi+lo operand pairs (3 products), fp32 accumulate",
+                   "hits_per_item": int(st["hits_per_item"])},
         "fwd_rays_per_s": b["fwd_rays_per_s"],
         "fwdbwd_rays_per_s": b["fwdbwd_rays_per_s"],
         "rgb_max_err_vs_fp64": errs,
@@ -610,7 +619,7 @@ def main():
     out["legs"] = {}
     for k, v in legs.items():
         e = {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
-             "fwd_ms": v["fwd_ms"]}
+             "fwd_ms": v["fwd_ms"], "autotuned_hits_per_item": v["hits_per_item"]}
         if v["fwdbwd_ms"] is not None:
             e.update({"fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"], "fwdbwd_ms": v["fwdbwd_ms"]})
         else:
