@@ -1129,42 +1129,92 @@ __global__ __launch_bounds__(256) void hit_record_kernel(const float* __restrict
 // optical depth kept as a double-float (compensated) sum
 __device__ __forceinline__ float depth_total(float hi, float lo, float x) { return hi + (lo + x); }
 
-__global__ __launch_bounds__(256) void composite_kernel(Workspace ws, int64_t R, msplat_opts opt,
-                                                        float* __restrict__ rgb,
-                                                        float* __restrict__ trans,
-                                                        float* __restrict__ feat, int cf) {
-  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
-  int64_t a = ws.ray_off[ray], b = ws.ray_off[ray + 1];
-  int64_t H = ws.hit_cap;
+// The compositor and its adjoint run one thread per ray, 256 rays per
+// workgroup.  The hits of a workgroup's rays form one contiguous range of
+// slots, [ray_off[r0], ray_off[r0 + 256]); it is staged through LDS in chunks
+// with coalesced loads and stores, and each thread walks its own ray's hits
+// there in order.  (Walking them in global memory, each step of a wave
+// touches a new cache line of every hit array, and with thousands of waves in
+// flight the lines are evicted before the neighbouring rays' steps reuse
+// them: about five times the hit bytes came from HBM.)
+constexpr int kCompRays = 256;
+
+// slots per chunk: the LDS footprint is chunk x (words per slot) x 4 bytes
+__host__ __device__ constexpr int comp_chunk(int words) { return words <= 12 ? 1024 : 512; }
+
+__global__ __launch_bounds__(kCompRays) void composite_kernel(Workspace ws, int64_t R, msplat_opts opt,
+                                                               float* __restrict__ rgb,
+                                                               float* __restrict__ trans,
+                                                               float* __restrict__ feat, int cf) {
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  const int nc = 3 + cf;
+  const int C = comp_chunk(5 + nc);
+  // in: optical depth, sample count, colour and feature sums; out: optical
+  // depth before the hit (hi, lo), composited count
+  float* s_tau = sm;
+  int32_t* s_k = reinterpret_cast<int32_t*>(sm + C);
+  float* s_c = sm + 2 * C;
+  float* s_sbh = s_c + nc * C;
+  float* s_sbl = s_sbh + C;
+  int32_t* s_nu = reinterpret_cast<int32_t*>(s_sbl + C);
+  const int64_t r0 = (int64_t)blockIdx.x * kCompRays;
+  const int64_t ray = r0 + threadIdx.x;
+  const bool act = ray < R;
+  const int64_t h0 = ws.ray_off[r0];
+  const int64_t h1 = ws.ray_off[min(r0 + kCompRays, R)];
+  const int64_t a = act ? ws.ray_off[ray] : h1, b = act ? ws.ray_off[ray + 1] : h1;
+  const int64_t H = ws.hit_cap;
   float c0 = 0.f, c1 = 0.f, c2 = 0.f;
   float f[kMaxOut - 4];
   for (int k = 0; k < kMaxOut - 4; ++k) f[k] = 0.f;
   float shi = 0.f, slo = 0.f;
   bool stopped = false;
-  for (int64_t j = a; j < b; ++j) {
-    if (stopped) {
-      ws.hit_nused[j] = 0;
-      continue;
+  for (int64_t cb = h0; cb < h1; cb += C) {
+    const int cn = (int)min((int64_t)C, h1 - cb);
+    for (int i = threadIdx.x; i < cn; i += kCompRays) {
+      s_tau[i] = ws.hit_tau[cb + i];
+      s_k[i] = ws.hit_k[cb + i];
+      for (int c = 0; c < nc; ++c) s_c[c * C + i] = ws.hit_cloc[c * H + cb + i];
     }
-    ws.hit_sb_hi[j] = shi;
-    ws.hit_sb_lo[j] = slo;
-    float tau = ws.hit_tau[j];
-    float tb = __expf(-(shi + slo));
-    if (opt.t_stop > 0.f && __expf(-depth_total(shi, slo, tau)) < opt.t_stop) {
-      ws.hit_nused[j] = -1;     // cut inside this hit: resolved per sample by the fixup pass
-      stopped = true;
-      continue;
+    __syncthreads();
+    const int j0 = (int)(max(a, cb) - cb), j1 = (int)(min(b, cb + cn) - cb);
+    for (int j = j0; j < j1; ++j) {
+      if (stopped) {
+        s_nu[j] = 0;
+        continue;
+      }
+      s_sbh[j] = shi;
+      s_sbl[j] = slo;
+      const float tau = s_tau[j];
+      const float tb = __expf(-(shi + slo));
+      if (opt.t_stop > 0.f && __expf(-depth_total(shi, slo, tau)) < opt.t_stop) {
+        s_nu[j] = -1;     // cut inside this hit: resolved per sample by the fixup pass
+        stopped = true;
+        continue;
+      }
+      s_nu[j] = s_k[j] & kKMask;
+      c0 = __builtin_fmaf(tb, s_c[0 * C + j], c0);
+      c1 = __builtin_fmaf(tb, s_c[1 * C + j], c1);
+      c2 = __builtin_fmaf(tb, s_c[2 * C + j], c2);
+      for (int k = 0; k < cf; ++k) f[k] = __builtin_fmaf(tb, s_c[(3 + k) * C + j], f[k]);
+      df sm2 = two_sum(shi, tau);
+      slo += sm2.lo;
+      shi = sm2.hi;
     }
-    ws.hit_nused[j] = ws.hit_k[j] & kKMask;
-    c0 = __builtin_fmaf(tb, ws.hit_cloc[0 * H + j], c0);
-    c1 = __builtin_fmaf(tb, ws.hit_cloc[1 * H + j], c1);
-    c2 = __builtin_fmaf(tb, ws.hit_cloc[2 * H + j], c2);
-    for (int k = 0; k < cf; ++k) f[k] = __builtin_fmaf(tb, ws.hit_cloc[(3 + k) * H + j], f[k]);
-    df s = two_sum(shi, tau);
-    slo += s.lo;
-    shi = s.hi;
+    __syncthreads();
+    // (the optical depth before a hit is written where the walk reached it:
+    // every hit with a non-zero composited count)
+    for (int i = threadIdx.x; i < cn; i += kCompRays) {
+      const int nu = s_nu[i];
+      ws.hit_nused[cb + i] = nu;
+      if (nu != 0) {
+        ws.hit_sb_hi[cb + i] = s_sbh[i];
+        ws.hit_sb_lo[cb + i] = s_sbl[i];
+      }
+    }
+    __syncthreads();
   }
+  if (!act) return;
   float t = __expf(-(shi + slo));
   if (stopped) {
     // partial sums; the fixup pass adds the cut hit and the background
@@ -1182,35 +1232,92 @@ __global__ __launch_bounds__(256) void composite_kernel(Workspace ws, int64_t R,
   for (int k = 0; k < cf; ++k) feat[ray * cf + k] = f[k];
 }
 
-// per-ray adjoint: transmittance before each hit and g . (what follows it)
-__global__ __launch_bounds__(256) void composite_adjoint_kernel(
+// LDS words per slot of the adjoint: in: composited count, optical depth
+// before the hit (hi, lo), colour (and, with a feature gradient, feature)
+// sums, (with slot features) the slot product and optical depth; out: three
+// backward scalars
+__host__ __device__ constexpr int adj_words(int nc_read, bool slot) { return 3 + nc_read + (slot ? 2 : 0) + 3; }
+
+// per-ray adjoint: transmittance before each hit and g . (what follows it);
+// the chunks are walked from the last to the first
+__global__ __launch_bounds__(kCompRays) void composite_adjoint_kernel(
     Workspace ws, int64_t R, msplat_opts opt, const float* __restrict__ grad_rgb,
     const float* __restrict__ grad_trans, const float* __restrict__ grad_feat, int cf,
     const float* __restrict__ trans) {
-  int64_t ray = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ray >= R) return;
-  int64_t a = ws.ray_off[ray], b = ws.ray_off[ray + 1];
-  int64_t H = ws.hit_cap;
-  float g0 = grad_rgb[3 * ray], g1 = grad_rgb[3 * ray + 1], g2 = grad_rgb[3 * ray + 2];
-  float tf = trans[ray];
+  extern __shared__ __attribute__((aligned(16))) float sm[];
+  const int ncr = 3 + (grad_feat ? cf : 0);   // colour (and feature) sums read
+  const bool slot = ws.slot_on != 0;
+  const int C = comp_chunk(adj_words(ncr, slot));
+  int32_t* s_nu = reinterpret_cast<int32_t*>(sm);
+  float* s_sbh = sm + C;
+  float* s_sbl = s_sbh + C;
+  float* s_c = s_sbl + C;
+  float* s_q = s_c + ncr * C;           // (slot features only)
+  float* s_tau = s_q + (slot ? C : 0);
+  float* s_gsa = s_tau + (slot ? C : 0);
+  float* s_tb = s_gsa + C;
+  float* s_gt = s_tb + C;
+  const int64_t r0 = (int64_t)blockIdx.x * kCompRays;
+  const int64_t ray = r0 + threadIdx.x;
+  const bool act = ray < R;
+  const int64_t h0 = ws.ray_off[r0];
+  const int64_t h1 = ws.ray_off[min(r0 + kCompRays, R)];
+  const int64_t a = act ? ws.ray_off[ray] : h1, b = act ? ws.ray_off[ray + 1] : h1;
+  const int64_t H = ws.hit_cap;
+  float g0 = 0.f, g1 = 0.f, g2 = 0.f, tf = 0.f, gt = 0.f;
+  if (act) {
+    g0 = grad_rgb[3 * ray];
+    g1 = grad_rgb[3 * ray + 1];
+    g2 = grad_rgb[3 * ray + 2];
+    tf = trans[ray];
+    gt = grad_trans ? grad_trans[ray] : 0.f;
+  }
   // d(rgb)/d(tau_k) = T_{k+1} c_k - sum_{j>k} w_j c_j - T_final bg, and
   // d(T_final)/d(tau_k) = -T_final: the suffix starts with T_final (g.bg + g_T)
-  float gt = grad_trans ? grad_trans[ray] : 0.f;
   // suffix sum over the later hits, kept compensated (double-float)
   df acc = df_from(tf * (g0 * opt.background[0] + g1 * opt.background[1] + g2 * opt.background[2] + gt));
-  for (int64_t j = b - 1; j >= a; --j) {
-    if (ws.hit_nused[j] <= 0) continue;
-    ws.hit_gsa[j] = acc.hi + acc.lo;
-    float tb = __expf(-(ws.hit_sb_hi[j] + ws.hit_sb_lo[j]));
-    float gc = g0 * ws.hit_cloc[0 * H + j] + g1 * ws.hit_cloc[1 * H + j] + g2 * ws.hit_cloc[2 * H + j];
-    if (grad_feat)
-      for (int k = 0; k < cf; ++k) gc += grad_feat[ray * cf + k] * ws.hit_cloc[(3 + k) * H + j];
-    // slot features: a colour channel constant over the hit, composited with
-    // the hit's opacity 1 - exp(-tau), whose upstream product is q
-    if (ws.slot_on) gc += ws.hit_q[j] * -expm1f(-ws.hit_tau[j]);
-    ws.hit_tb[j] = tb;
-    ws.hit_gtot[j] = tb * gc;
-    acc = df_add(acc, two_prod(tb, gc));
+  const int64_t nchunks = (h1 - h0 + C - 1) / C;
+  for (int64_t ci = nchunks - 1; ci >= 0; --ci) {
+    const int64_t cb = h0 + ci * C;
+    const int cn = (int)min((int64_t)C, h1 - cb);
+    for (int i = threadIdx.x; i < cn; i += kCompRays) {
+      const int nu = ws.hit_nused[cb + i];
+      s_nu[i] = nu;
+      if (nu > 0) {
+        s_sbh[i] = ws.hit_sb_hi[cb + i];
+        s_sbl[i] = ws.hit_sb_lo[cb + i];
+        for (int c = 0; c < ncr; ++c) s_c[c * C + i] = ws.hit_cloc[c * H + cb + i];
+        if (slot) {
+          s_q[i] = ws.hit_q[cb + i];
+          s_tau[i] = ws.hit_tau[cb + i];
+        }
+      }
+    }
+    __syncthreads();
+    const int j0 = (int)(max(a, cb) - cb), j1 = (int)(min(b, cb + cn) - cb);
+    for (int j = j1 - 1; j >= j0; --j) {
+      if (s_nu[j] <= 0) continue;
+      s_gsa[j] = acc.hi + acc.lo;
+      const float tb = __expf(-(s_sbh[j] + s_sbl[j]));
+      float gc = g0 * s_c[0 * C + j] + g1 * s_c[1 * C + j] + g2 * s_c[2 * C + j];
+      if (grad_feat)
+        for (int k = 0; k < cf; ++k) gc += grad_feat[ray * cf + k] * s_c[(3 + k) * C + j];
+      // slot features: a colour channel constant over the hit, composited with
+      // the hit's opacity 1 - exp(-tau), whose upstream product is q
+      if (slot) gc += s_q[j] * -expm1f(-s_tau[j]);
+      s_tb[j] = tb;
+      s_gt[j] = tb * gc;
+      acc = df_add(acc, two_prod(tb, gc));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cn; i += kCompRays) {
+      if (s_nu[i] > 0) {
+        ws.hit_gsa[cb + i] = s_gsa[i];
+        ws.hit_tb[cb + i] = s_tb[i];
+        ws.hit_gtot[cb + i] = s_gt[i];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1500,8 +1607,10 @@ hipError_t launch_hit_records(const Workspace& ws, const float* ray_o, const flo
 hipError_t launch_composite(const Workspace& ws, int64_t R, const msplat_opts& o, float* rgb,
                             float* trans, float* feat, int cf, hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, ws, R, o,
-                     rgb, trans, feat, cf);
+  const int words = 5 + 3 + cf;
+  const size_t lds = (size_t)comp_chunk(words) * words * 4;
+  hipLaunchKernelGGL(composite_kernel, dim3((unsigned)((R + kCompRays - 1) / kCompRays)), dim3(kCompRays), lds, s,
+                     ws, R, o, rgb, trans, feat, cf);
   return hipGetLastError();
 }
 
@@ -1510,8 +1619,10 @@ hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat
                                     const float* grad_feat, int cf, const float* trans,
                                     hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(composite_adjoint_kernel, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, s, ws,
-                     R, o, grad_rgb, grad_trans, grad_feat, cf, trans);
+  const int words = adj_words(3 + (grad_feat ? cf : 0), ws.slot_on != 0);
+  const size_t lds = (size_t)comp_chunk(words) * words * 4;
+  hipLaunchKernelGGL(composite_adjoint_kernel, dim3((unsigned)((R + kCompRays - 1) / kCompRays)), dim3(kCompRays),
+                     lds, s, ws, R, o, grad_rgb, grad_trans, grad_feat, cf, trans);
   return hipGetLastError();
 }
 
