@@ -95,8 +95,8 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     # the MSE step's upstream gradient)
     with torch.no_grad():
         rgb0 = r.forward(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd)[0]
-    hpi = r.autotune(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd,
-                     (2.0 / rgb0.numel()) * (rgb0 - target) if train else None)
+    tuned = r.autotune(prm["center"], prm["scale"], prm["quat"], prm["mlp"], ro, rd,
+                       (2.0 / rgb0.numel()) * (rgb0 - target) if train else None)
 
     def step():
         for v in leaf.values():
@@ -145,7 +145,8 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     hits = r.hits(ws, R)[:2] if want_hits else None
     return {
         "hits": hits,
-        "hits_per_item": hpi,
+        "hits_per_item": tuned["hits_per_item"],
+        "bwd_items_per_group": tuned["bwd_items_per_group"],
         "fwdbwd_ms": 1e3 * (t1 - t0) / steps if train else None,
         "fwd_ms": 1e3 * (f1 - f0) / steps,
         "fwdbwd_rays_per_s": R * steps / (t1 - t0) if train else None,
@@ -620,6 +621,8 @@ def main():
     for k, v in legs.items():
         e = {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
              "fwd_ms": v["fwd_ms"], "autotuned_hits_per_item": v["hits_per_item"]}
+        if v["bwd_items_per_group"]:
+            e["autotuned_bwd_items_per_group"] = v["bwd_items_per_group"]
         if v["fwdbwd_ms"] is not None:
             e.update({"fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"], "fwdbwd_ms": v["fwdbwd_ms"]})
         else:

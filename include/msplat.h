@@ -129,6 +129,14 @@ typedef struct msplat_opts {
   int32_t hits_per_item;    /* hits of one primitive per work item of the network
                                kernels: 16, 32 or 64; 0 = the choice msplat_autotune
                                recorded for this network and workload (64 if none) */
+  int32_t bwd_items_per_group; /* one workgroup of the backward network kernel takes
+                               the hits of this many consecutive work items of one
+                               primitive (at most 64 hits per wave of the kernel),
+                               deals them to its waves in one balanced deal and
+                               keeps the primitive's weight-gradient sums in
+                               registers across them: 1, 2, 4 or 8; 0 = the choice
+                               msplat_autotune recorded, else the most that leave at
+                               least 2048 workgroups */
 } msplat_opts;
 
 /* Counters filled by the forward pass (read with msplat_get_stats). */
@@ -141,6 +149,8 @@ typedef struct msplat_stats {
   int64_t num_fallbacks;      /* hit tests decided in double-float arithmetic */
   float min_abs_g;            /* smallest |1 - |p_c|^2| seen among tested pairs */
   int32_t hits_per_item;      /* work-item size the network kernels ran with */
+  int32_t bwd_items_per_group; /* work items per workgroup of the context's last
+                                 backward (0 before the first) */
 } msplat_stats;
 
 typedef struct msplat_ctx msplat_ctx;
@@ -284,17 +294,21 @@ int msplat_profile_read(msplat_ctx* ctx, int max_stages, const char** names, dou
  * arguments once per candidate size (64, 32, 16), times each on `stream`
  * with HIP events, records the fastest for this context, network and
  * workload (ray count, primitive count and sample options) and writes it to
- * *chosen.  Later calls with opts->hits_per_item == 0 and the same network
- * and workload use it.  Arguments as for msplat_render_forward and
- * msplat_render_backward; every output buffer is overwritten (with the last
- * candidate's results) and ws is left as a forward of the last candidate
- * wrote it.  Synchronises `stream`.
+ * *chosen.  With grad_rgb it then runs the forward at that size and times
+ * the backward alone with 1, 2, 4 and 8 work items per workgroup, records
+ * the fastest beside it and writes it to *chosen_group (if not NULL; 0
+ * without grad_rgb).  Later calls with opts->hits_per_item == 0 (and
+ * opts->bwd_items_per_group == 0) and the same network and workload use
+ * them.  Arguments as for msplat_render_forward and msplat_render_backward;
+ * every output buffer is overwritten (with the last candidate's results)
+ * and ws is left as the last forward wrote it.  Synchronises `stream`.
  */
 int msplat_autotune(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
                     const float* center, const float* scale, const float* quat, const float* mlp,
                     const float* ray_o, const float* ray_d, int64_t num_rays, float* rgb, float* trans,
                     float* feat, const float* grad_rgb, void* ws, uint64_t ws_bytes, float* g_center,
-                    float* g_scale, float* g_quat, float* g_mlp, int32_t* chosen, void* stream);
+                    float* g_scale, float* g_quat, float* g_mlp, int32_t* chosen, int32_t* chosen_group,
+                    void* stream);
 
 /* Counters of the last forward that used `ws` (synchronises `stream`). */
 int msplat_get_stats(msplat_ctx* ctx, const void* ws, uint64_t ws_bytes, msplat_stats* out,

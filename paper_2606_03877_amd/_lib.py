@@ -41,14 +41,16 @@ class Opts(ctypes.Structure):
                 ("samples_max", ctypes.c_int32), ("samples_per_unit", ctypes.c_float),
                 ("t_stop", ctypes.c_float), ("jitter", ctypes.c_int32),
                 ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3),
-                ("order", ctypes.c_int32), ("hits_per_item", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("hits_per_item", ctypes.c_int32),
+                ("bwd_items_per_group", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("num_rays", ctypes.c_int64), ("num_hits", ctypes.c_int64),
                 ("num_samples", ctypes.c_int64), ("num_work_items", ctypes.c_int64),
                 ("num_terminated", ctypes.c_int64), ("num_fallbacks", ctypes.c_int64),
-                ("min_abs_g", ctypes.c_float), ("hits_per_item", ctypes.c_int32)]
+                ("min_abs_g", ctypes.c_float), ("hits_per_item", ctypes.c_int32),
+                ("bwd_items_per_group", ctypes.c_int32)]
 
 
 EXPORTS = {
@@ -94,7 +96,7 @@ EXPORTS = {
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_uint64,
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-        ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
+        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]),
     "msplat_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "msplat_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                            ctypes.POINTER(ctypes.c_char_p),

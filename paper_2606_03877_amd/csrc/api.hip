@@ -35,6 +35,7 @@ struct TuneEntry {
   int32_t samples_fixed, samples_min, samples_max, order;
   float samples_per_unit;
   int32_t hits_per_item;
+  int32_t bwd_group;   // backward work items per workgroup; 0 = not tuned
 };
 constexpr int kTuneSlots = 32;
 
@@ -60,6 +61,7 @@ struct msplat_ctx {
   uint64_t last_bytes;
   NetShape last_shape;
   int32_t last_hpi;
+  int32_t last_bwd_group = 0;   // work items per workgroup of the last backward
 };
 
 namespace {
@@ -108,6 +110,7 @@ uint64_t layout(const NetShape& n, int64_t R, int64_t hcap, uint8_t* base, Works
   ws.prim_off = (int32_t*)take((uint64_t)(P + 1) * 4);
   ws.prim_cursor = (int32_t*)take((uint64_t)P * 4);
   ws.wi_off = (int32_t*)take((uint64_t)(P + 1) * 4);
+  ws.gw_off = (int32_t*)take((uint64_t)(P + 1) * 4);
   ws.geo_grad = (float*)take((uint64_t)P * 12 * 4);
   ws.ray_off = (int32_t*)take((uint64_t)(R + 1) * 4);
   int64_t nb = (R + 1023) / 1024;
@@ -236,6 +239,8 @@ bool opts_ok(const msplat_opts* o) {
   if (o->order != 0 && o->order != 1) return false;
   if (o->hits_per_item != 0 && o->hits_per_item != 16 && o->hits_per_item != 32 && o->hits_per_item != 64)
     return false;
+  const int32_t g = o->bwd_items_per_group;
+  if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8) return false;
   return true;
 }
 
@@ -252,6 +257,17 @@ int32_t hits_per_item_of(const msplat_ctx* c, const NetShape& n, int64_t R, cons
   for (int i = 0; i < c->num_tuned; ++i)
     if (tune_match(c->tuned[i], n, R, o)) return c->tuned[i].hits_per_item;
   return kHitsPerItem;
+}
+
+// backward work items per workgroup: the option, else the recorded choice,
+// else the most (up to 8) that leave at least 2048 workgroups (eight per CU)
+int32_t bwd_group_of(const msplat_ctx* c, const NetShape& n, int64_t R, const msplat_opts& o, int64_t items) {
+  if (o.bwd_items_per_group) return o.bwd_items_per_group;
+  for (int i = 0; i < c->num_tuned; ++i)
+    if (tune_match(c->tuned[i], n, R, o) && c->tuned[i].bwd_group) return c->tuned[i].bwd_group;
+  int32_t g = 1;
+  while (g < 8 && items >= (int64_t)2048 * 2 * g) g *= 2;
+  return g;
 }
 
 // the options a call runs with: the contact-point primitive has one
@@ -542,9 +558,10 @@ static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_op
   STAGE(ctx, ST_COMP_ADJ, s,
         launch_composite_adjoint(ws, R, *o, grad_rgb, grad_trans, cf > 0 ? grad_feat : nullptr, cf,
                                  ws.ray_tf, s));
+  const int32_t group = bwd_group_of(ctx, n, R, *o, items);
   STAGE(ctx, ST_MLP_BWD, s,
-        launch_mlp_backward(n, ws, *o, (int)items, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr,
-                            g_mlp, s));
+        launch_mlp_backward(n, ws, *o, nh, group, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr, g_mlp, s));
+  ctx->last_bwd_group = group;
   if (sa)
     STAGE(ctx, ST_SLOT_BWD_PRIMS, s,
           launch_slot_backward_prims(ws, n.P, (int)items, sa->slots, sa->C, sa->grad_slot, ray_d, sa->g_slots,
@@ -598,7 +615,7 @@ int msplat_autotune(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o
                     const float* scale, const float* quat, const float* mlp, const float* ray_o, const float* ray_d,
                     int64_t R, float* rgb, float* trans, float* feat, const float* grad_rgb, void* wsp,
                     uint64_t ws_bytes, float* g_center, float* g_scale, float* g_quat, float* g_mlp,
-                    int32_t* chosen, void* stream) {
+                    int32_t* chosen, int32_t* chosen_group, void* stream) {
   NetShape n;
   if (!ctx || !chosen || !shape_of(m, &n) || !opts_ok(o)) return MSPLAT_E_INVALID;
   if (grad_rgb && (!g_center || !g_scale || !g_quat || !g_mlp)) return MSPLAT_E_INVALID;
@@ -611,42 +628,72 @@ int msplat_autotune(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o
     (void)hipEventDestroy(ev[0]);
     return MSPLAT_E_HIP;
   }
+  auto fwd = [&](const msplat_opts& oc) {
+    return msplat_render_forward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, wsp,
+                                 ws_bytes, nullptr, stream);
+  };
+  auto bwd = [&](const msplat_opts& oc) {
+    return msplat_render_backward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, grad_rgb, nullptr,
+                                  nullptr, wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, stream);
+  };
+  // runs `step` twice (the first run warms up) and times the second
+  auto timed = [&](auto step, float* ms) {
+    int st = step();
+    if (st == MSPLAT_OK && hipEventRecord(ev[0], s) != hipSuccess) st = MSPLAT_E_HIP;
+    if (st == MSPLAT_OK) st = step();
+    if (st == MSPLAT_OK && hipEventRecord(ev[1], s) != hipSuccess) st = MSPLAT_E_HIP;
+    if (st == MSPLAT_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(ms, ev[0], ev[1]) != hipSuccess))
+      st = MSPLAT_E_HIP;
+    return st;
+  };
   const int32_t cand[3] = {64, 32, 16};
-  int32_t best = 0;
+  int32_t best = 0, best_group = 0;
   float best_ms = 0.f;
   int st = MSPLAT_OK;
   for (int c = 0; c < 3 && st == MSPLAT_OK; ++c) {
     msplat_opts oc = *o;
     oc.hits_per_item = cand[c];
-    for (int rep = 0; rep < 2 && st == MSPLAT_OK; ++rep) {   // the first run warms up
-      if (rep == 1 && hipEventRecord(ev[0], s) != hipSuccess) st = MSPLAT_E_HIP;
-      if (st == MSPLAT_OK)
-        st = msplat_render_forward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, rgb, trans, feat, wsp,
-                                   ws_bytes, nullptr, stream);
-      if (st == MSPLAT_OK && grad_rgb)
-        st = msplat_render_backward(ctx, m, &oc, center, scale, quat, mlp, ray_o, ray_d, R, grad_rgb, nullptr,
-                                    nullptr, wsp, ws_bytes, g_center, g_scale, g_quat, g_mlp, stream);
-      if (st == MSPLAT_OK && rep == 1 && hipEventRecord(ev[1], s) != hipSuccess) st = MSPLAT_E_HIP;
-    }
     float ms = 0.f;
-    if (st == MSPLAT_OK && (hipEventSynchronize(ev[1]) != hipSuccess ||
-                            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
-      st = MSPLAT_E_HIP;
+    st = timed([&] {
+      int r = fwd(oc);
+      return (r == MSPLAT_OK && grad_rgb) ? bwd(oc) : r;
+    }, &ms);
     if (st == MSPLAT_OK && (best == 0 || ms < best_ms)) {
       best = cand[c];
       best_ms = ms;
     }
   }
+  if (st == MSPLAT_OK && grad_rgb && o->bwd_items_per_group == 0) {
+    msplat_opts oc = *o;
+    oc.hits_per_item = best;
+    st = fwd(oc);
+    const int32_t gcand[4] = {1, 2, 4, 8};
+    float gbest_ms = 0.f;
+    for (int c = 0; c < 4 && st == MSPLAT_OK; ++c) {
+      oc.bwd_items_per_group = gcand[c];
+      float ms = 0.f;
+      st = timed([&] { return bwd(oc); }, &ms);
+      if (st == MSPLAT_OK && (best_group == 0 || ms < gbest_ms)) {
+        best_group = gcand[c];
+        gbest_ms = ms;
+      }
+    }
+  } else if (grad_rgb) {
+    best_group = o->bwd_items_per_group;
+  }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
   if (st != MSPLAT_OK) return st;
-  TuneEntry e{n, R, key.samples_fixed, key.samples_min, key.samples_max, key.order, key.samples_per_unit, best};
+  TuneEntry e{n, R, key.samples_fixed, key.samples_min, key.samples_max, key.order, key.samples_per_unit, best,
+              best_group};
   int slot = -1;
   for (int i = 0; i < ctx->num_tuned; ++i)
     if (tune_match(ctx->tuned[i], n, R, key)) slot = i;
   if (slot < 0) slot = ctx->num_tuned < kTuneSlots ? ctx->num_tuned++ : kTuneSlots - 1;
   ctx->tuned[slot] = e;
   *chosen = best;
+  if (chosen_group) *chosen_group = best_group;
   return MSPLAT_OK;
 }
 
@@ -669,6 +716,7 @@ int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat
   std::memcpy(&mg, &c.min_abs_g_bits, 4);
   out->min_abs_g = mg;
   out->hits_per_item = c.hits_per_item;
+  out->bwd_items_per_group = ctx->last_bwd_group;
   (void)ws_bytes;
   return MSPLAT_OK;
 }

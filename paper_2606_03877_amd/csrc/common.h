@@ -60,6 +60,7 @@ struct Workspace {
   int32_t* prim_off;     // [P+1]
   int32_t* prim_cursor;  // [P]
   int32_t* wi_off;       // [P+1] work-item offsets
+  int32_t* gw_off;       // [P+1] backward: offsets of each primitive's workgroups
   float* geo_grad;       // [P, 12] accumulated dL/dM (9) and M^T-free dL/dv (3)
   int32_t* ray_off;      // [R+1] (counts, then exclusive offsets)
   int32_t* scan_tmp;     // scan block sums
@@ -285,8 +286,10 @@ hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const mspl
                               int num_items, int mode, float* rgb, float* trans, float* feat,
                               hipStream_t s);
 // mlp_bwd.hip
+// (group >= 1: a workgroup takes the hits of that many work items of one
+// primitive, at most 64 per wave of the kernel)
 hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o,
-                               int num_items, const float* ray_d, const float* grad_rgb,
+                               int64_t num_hits, int group, const float* ray_d, const float* grad_rgb,
                                const float* grad_feat, float* g_mlp, hipStream_t s);
 
 // f64.hip

@@ -226,14 +226,22 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
 #pragma unroll
   for (int r = 0; r < N::OUT_SLOTS; ++r) cr_q[r] = 0.f;
 
+  int lb = 0;   // (scalar) lane of the hit holding the block's first column
   for (int b = 0; b < nblk; ++b) {
     const int x = 32 * b + col;
     const bool valid = x < ns;
     // the hit of this column: the last of the wave's hits whose samples
-    // start at or before it (hit records read from lanes into scalar registers)
-    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
-    for (int l = 1; l < c; ++l) {
+    // start at or before it (hit records read from lanes into scalar
+    // registers).  The hits sit in lanes 0..c-1 in sample order: the cursor
+    // lb moves to the hit holding the block's first column, then the hits
+    // starting inside the block are taken.
+    const int x0 = 32 * b;
+    while (lb + 1 < c && __builtin_amdgcn_readlane(my_off, lb + 1) <= x0) ++lb;
+    int hit = __builtin_amdgcn_readlane(my_hit, lb), K = __builtin_amdgcn_readlane(my_k, lb);
+    int hoff = __builtin_amdgcn_readlane(my_off, lb);
+    for (int l = lb + 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
+      if (ol >= x0 + 32) break;
       if (ol <= x) {
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);

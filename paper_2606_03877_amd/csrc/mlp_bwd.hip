@@ -318,6 +318,7 @@ struct BwdArgs {
   msplat_opts opt;
   int P;
   int n_params;
+  int ghits;   // hits per workgroup (a run of one primitive's list), <= 64 per wave
   const float* ray_d;
   const float* grad_rgb;
   const float* grad_feat;
@@ -527,32 +528,62 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   const int col = lane % 32;
   const int g = lane / 32;
   const int colx = 32 * q + col;
-  const int wi = blockIdx.x;
-  const int p = find_prim(ws.wi_off, args.P, wi);
-  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * ws.hits_per_item;
-  const int nh = min(ws.hits_per_item, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
+  const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
+  // The workgroup takes a run of up to args.ghits consecutive hits of one
+  // primitive's list (the hits of `group` work items of the forward, at most
+  // 64 per wave): the weights are staged once, the hits are dealt to the
+  // waves in one balanced deal, and the weight-gradient sums stay in
+  // registers until they are added to the global gradient at the end.
+  constexpr int NW = B::NW;
+  static_assert(64 * NW <= 512, "hit indices of a workgroup fit 9 bits");
+  const int bid = blockIdx.x;
+  if (bid >= ws.gw_off[args.P]) return;   // (the grid is an upper bound)
+  const int p = find_prim(ws.gw_off, args.P, bid);
+  const int first = ws.prim_off[p] + (bid - ws.gw_off[p]) * args.ghits;
+  const int nh = min(args.ghits, ws.prim_off[p + 1] - first);
   const uint8_t* wglb = ws.wpack + (int64_t)p * ws.wpack_bytes;
-  const uint8_t* wts = wglb;
   if constexpr (!B::GW) {
-    // packed bytes [SKIP, total) go to LDS at W_OFF; wts is the (LDS) base
-    // that the packed offsets of the staged sections are taken from
+    // packed bytes [SKIP, total) go to LDS at W_OFF (read after the
+    // barriers below)
     const uint4* src = reinterpret_cast<const uint4*>(wglb + B::SKIP);
     uint4* dst = reinterpret_cast<uint4*>(lds + B::W_OFF);
     for (int i = threadIdx.x; i < (N::total_bytes() - B::SKIP) / 16; i += blockDim.x) dst[i] = src[i];
-    wts = lds + B::W_OFF - B::SKIP;   // read after the barrier below
   }
+  // wts: the base that the packed offsets of the weights are taken from (LDS
+  // for the staged sections); wts0: where the first layer's forward operands
+  // are read
+  const uint8_t* wts = B::GW ? wglb : lds + B::W_OFF - B::SKIP;
   const uint8_t* wts0 = B::G0 ? wglb : wts;
-  static_assert(kHitsPerItem <= 64, "one item's hits fit the lanes of a wave");
-  int item_hit = 0, item_k = 0;
-  if (lane < nh) {
-    item_hit = ws.phit[first + lane];
-    item_k = ws.hit_nused[item_hit] > 0 ? (ws.hit_k[item_hit] & kKMask) : 0;
+  // ---- deal: wave q sorts the keys (samples, index) of hits 64q..64q+63 of
+  // the run, largest first; rank r of that list goes to wave
+  // (snake(r) + q) mod NW, snake(r) running 0..NW-1 and back over each row
+  // of NW ranks; each wave sorts what it received (its hits in lanes
+  // 0..c-1).  The sample counts of the waves then differ by about one hit's.
+  {
+    const int idx = 64 * q + lane;
+    int key = -1;
+    if (idx < nh) {
+      const int h = ws.phit[first + idx];
+      const int kk = ws.hit_nused[h] > 0 ? (ws.hit_k[h] & kKMask) : 0;
+      key = (kk << 9) | (511 - idx);
+    }
+    key = wave_sort_desc(key, lane);
+    reinterpret_cast<int*>(lds + B::XH_OFF)[idx] = key;   // (the exchange planes are free here)
   }
-  int my_k;
-  const int my_li = deal_hits<B::NW>(lane < nh ? (item_k << 7) | (127 - lane) : -1, q, lane, nh, my_k);
-  const int my_hit = __shfl(item_hit, my_li < 0 ? 0 : my_li, 64);
-  const int c = __popcll(__ballot(my_li >= 0));   // (the wave's slots in use form a prefix)
+  __syncthreads();
+  int my_li, my_k;
+  {
+    constexpr int PER = 64 / NW;   // keys a wave takes from each wave's list
+    const int qc = lane / PER, j = lane % PER;
+    const int sp = (q - qc + NW) % NW;
+    const int r = j * NW + ((j & 1) ? NW - 1 - sp : sp);
+    const int key = wave_sort_desc(reinterpret_cast<const int*>(lds + B::XH_OFF)[64 * qc + r], lane);
+    my_li = key < 0 ? -1 : 511 - (key & 511);
+    my_k = key < 0 ? 0 : key >> 9;
+  }
+  const int my_hit = my_li < 0 ? 0 : ws.phit[first + my_li];
+  const int c = __popcll(__ballot(my_li >= 0));   // (the wave's hits fill lanes 0..c-1)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
   const int ns = __builtin_amdgcn_readlane(incl, 63);
@@ -560,8 +591,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   if (lane == 0) rounds_s[q] = nblk;
   __syncthreads();
   int rounds = 0;
-  for (int i = 0; i < B::NW; ++i) rounds = max(rounds, rounds_s[i]);
-  const uint32_t seed_hash = pcg_hash(args.opt.jitter_seed);
+  for (int i = 0; i < NW; ++i) rounds = max(rounds, rounds_s[i]);
   f32x4 dacc[B::tiles(LO, HI)];
 #pragma unroll
   for (int i = 0; i < B::tiles(LO, HI); ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -570,15 +600,22 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
 #pragma unroll
   for (int i = 0; i < 9; ++i) cr_geo[i] = 0.f;
 
+  int lb = 0;   // (scalar) lane of the hit holding the block's first column
   for (int b = 0; b < rounds; ++b) {
     const int x = 32 * b + col;
     const bool valid = x < ns;
     // the hit of this column: the last of the wave's hits whose samples
-    // start at or before it (hit records read from lanes into scalar registers)
-    int hit = __builtin_amdgcn_readlane(my_hit, 0), K = __builtin_amdgcn_readlane(my_k, 0), hoff = 0;
-    int hli = __builtin_amdgcn_readlane(my_li, 0);
-    for (int l = 1; l < c; ++l) {
+    // start at or before it (hit records read from lanes into scalar
+    // registers).  The hits sit in lanes 0..c-1 in sample order: the
+    // cursor lb moves to the hit holding the block's first column, then the
+    // hits starting inside the block are taken.
+    const int x0 = 32 * b;
+    while (lb + 1 < c && __builtin_amdgcn_readlane(my_off, lb + 1) <= x0) ++lb;
+    int hit = __builtin_amdgcn_readlane(my_hit, lb), K = __builtin_amdgcn_readlane(my_k, lb);
+    int hoff = __builtin_amdgcn_readlane(my_off, lb), hli = __builtin_amdgcn_readlane(my_li, lb);
+    for (int l = lb + 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
+      if (ol >= x0 + 32) break;
       if (ol <= x) {
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);
@@ -727,10 +764,35 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   flush_range<N, LO, LO, HI>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
 }
 
+// offsets of each primitive's backward workgroups: primitive i's hits
+// [prim_off[i], prim_off[i+1]) in runs of ghits (one workgroup)
+__global__ __launch_bounds__(256) void group_scan_kernel(const int32_t* __restrict__ prim_off, int P, int ghits,
+                                                         int32_t* __restrict__ gw_off) {
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < P; base += 256) {
+    const int i = base + threadIdx.x;
+    const int32_t n = i < P ? (prim_off[i + 1] - prim_off[i] + ghits - 1) / ghits : 0;
+    const int incl = wave_incl_scan(n);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int o = carry;
+    for (int k = 0; k < w; ++k) o += wsum[k];
+    if (i < P) gw_off[i] = incl - n + o;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = o + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gw_off[P] = carry;
+}
+
 }  // namespace
 
 template <class N, int LO, int HI>
-static hipError_t bwd_pass(const BwdArgs& a, int items, hipStream_t s) {
+static hipError_t bwd_pass(const BwdArgs& a, int64_t groups, hipStream_t s) {
   size_t lds = Bwd<N>::LDS;
   static bool attr = false;
   if (!attr) {
@@ -739,61 +801,71 @@ static hipError_t bwd_pass(const BwdArgs& a, int items, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((mlp_backward_kernel<N, LO, HI>), dim3(items), dim3(64 * Bwd<N>::NW), lds, s, a);
+  hipLaunchKernelGGL((mlp_backward_kernel<N, LO, HI>), dim3((unsigned)groups), dim3(64 * Bwd<N>::NW), lds, s, a);
   return hipGetLastError();
 }
 
 // wide networks: passes over ranges of WSPAN layers, from layer LO up
 template <class N, int LO>
-static hipError_t wide_passes(const BwdArgs& a, int items, hipStream_t s) {
+static hipError_t wide_passes(const BwdArgs& a, int64_t groups, hipStream_t s) {
   constexpr int HI = LO + N::WSPAN - 1 < N::NL - 1 ? LO + N::WSPAN - 1 : N::NL - 1;
-  hipError_t e = bwd_pass<N, LO, HI>(a, items, s);
+  hipError_t e = bwd_pass<N, LO, HI>(a, groups, s);
   if constexpr (HI + 1 < N::NL) {
-    if (e == hipSuccess) return wide_passes<N, HI + 1>(a, items, s);
+    if (e == hipSuccess) return wide_passes<N, HI + 1>(a, groups, s);
   }
   return e;
 }
 
 template <class N>
-static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int items, int P, int n_params,
-                           const float* ray_d, const float* grad_rgb, const float* grad_feat,
+static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int64_t num_hits, int group, int P,
+                           int n_params, const float* ray_d, const float* grad_rgb, const float* grad_feat,
                            float* g_mlp, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  BwdArgs a{ws, o, P, n_params, ray_d, grad_rgb, grad_feat, g_mlp};
+  if (num_hits <= 0) return hipSuccess;
+  if (group < 1 || ws.hits_per_item < 1) return hipErrorInvalidValue;
+  // a workgroup's run: `group` work items of the forward, at most 64 hits per wave
+  const int ghits = min(group * ws.hits_per_item, 64 * Bwd<N>::NW);
+  BwdArgs a{ws, o, P, n_params, ghits, ray_d, grad_rgb, grad_feat, g_mlp};
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_off, P, ghits,
+                     ws.gw_off);
+  // at most ceil(hits / ghits) runs plus one partial run per primitive; the
+  // workgroups past the last run return at once
+  const int64_t groups = (num_hits + ghits - 1) / ghits + P;
   if constexpr (N::WIDE) {
-    return wide_passes<N, 0>(a, items, s);
+    return wide_passes<N, 0>(a, groups, s);
   } else if constexpr (N::PASSES) {
     // the upper half of the layers, then the lower half with the geometry
     constexpr int M = N::NL / 2;
-    hipError_t e = bwd_pass<N, M, N::NL - 1>(a, items, s);
-    return e != hipSuccess ? e : bwd_pass<N, 0, M - 1>(a, items, s);
+    hipError_t e = bwd_pass<N, M, N::NL - 1>(a, groups, s);
+    return e != hipSuccess ? e : bwd_pass<N, 0, M - 1>(a, groups, s);
   } else {
-    return bwd_pass<N, 0, N::NL - 1>(a, items, s);
+    return bwd_pass<N, 0, N::NL - 1>(a, groups, s);
   }
 }
 
 hipError_t MSPLAT_TU_FN(launch_mlp_backward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
-                                             int items, const float* ray_d, const float* grad_rgb,
-                                             const float* grad_feat, float* g_mlp, hipStream_t s) {
+                                             int64_t num_hits, int group, const float* ray_d,
+                                             const float* grad_rgb, const float* grad_feat, float* g_mlp,
+                                             hipStream_t s) {
 #define X(L_, W_, D_, O_, P_, K_)                                                                   \
   MSPLAT_MATCH(L_, W_, D_, O_, P_, K_)                                                              \
-  return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, items, n.P, n.n_params, ray_d, grad_rgb, \
-                                                  grad_feat, g_mlp, s);
+  return bwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, num_hits, group, n.P, n.n_params, ray_d, \
+                                                      grad_rgb, grad_feat, g_mlp, s);
   MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
 #ifndef MSPLAT_WIDE_TU
-hipError_t launch_mlp_backward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                                    const float* ray_d, const float* grad_rgb, const float* grad_feat,
-                                    float* g_mlp, hipStream_t s);
+hipError_t launch_mlp_backward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o,
+                                    int64_t num_hits, int group, const float* ray_d, const float* grad_rgb,
+                                    const float* grad_feat, float* g_mlp, hipStream_t s);
 
-hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                               const float* ray_d, const float* grad_rgb, const float* grad_feat,
+hipError_t launch_mlp_backward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int64_t num_hits,
+                               int group, const float* ray_d, const float* grad_rgb, const float* grad_feat,
                                float* g_mlp, hipStream_t s) {
-  return wide_net(n.W) ? launch_mlp_backward_wide(n, ws, o, items, ray_d, grad_rgb, grad_feat, g_mlp, s)
-                       : launch_mlp_backward_narrow(n, ws, o, items, ray_d, grad_rgb, grad_feat, g_mlp, s);
+  return wide_net(n.W)
+             ? launch_mlp_backward_wide(n, ws, o, num_hits, group, ray_d, grad_rgb, grad_feat, g_mlp, s)
+             : launch_mlp_backward_narrow(n, ws, o, num_hits, group, ray_d, grad_rgb, grad_feat, g_mlp, s);
 }
 #endif
 

@@ -432,17 +432,8 @@ __device__ __forceinline__ float col_below(float v, int col) {
   return (col & 15) ? a : (col ? b : 0.f);
 }
 
-// The hits of a work item dealt to its NW waves so that the waves' sample
-// counts balance (a workgroup lasts as long as its busiest wave).  Lane
-// l < nh brings key (k_l << 7) | (127 - l), k_l its hit's sample count, other
-// lanes -1; the keys are sorted in descending order across the wave
-// (bitonic network: distinct keys, item-local index in the low bits), and
-// sorted position r goes to wave w, slot s with r = NW s + w for even s and
-// NW s + NW - 1 - w for odd s (snake order).  Returns the item-local index
-// of the hit in slot `lane` of wave `w` (-1: no hit) and its count in k.
-template <int NW>
-__device__ __forceinline__ int deal_hits(int key, int w, int lane, int nh, int& k) {
-  int v = key;
+// bitonic sort of one value per lane over the wave, largest in lane 0
+__device__ __forceinline__ int wave_sort_desc(int v, int lane) {
 #pragma unroll
   for (int kk = 2; kk <= 64; kk <<= 1) {
 #pragma unroll
@@ -452,6 +443,20 @@ __device__ __forceinline__ int deal_hits(int key, int w, int lane, int nh, int& 
       v = keep_max ? max(v, o) : min(v, o);
     }
   }
+  return v;
+}
+
+// The hits of a work item dealt to its NW waves so that the waves' sample
+// counts balance (a workgroup lasts as long as its busiest wave).  Lane
+// l < nh brings key (k_l << 7) | (127 - l), k_l its hit's sample count, other
+// lanes -1; the keys are sorted in descending order across the wave
+// (distinct keys, item-local index in the low bits), and sorted position r
+// goes to wave w, slot s with r = NW s + w for even s and NW s + NW - 1 - w
+// for odd s (snake order).  Returns the item-local index of the hit in slot
+// `lane` of wave `w` (-1: no hit) and its count in k.
+template <int NW>
+__device__ __forceinline__ int deal_hits(int key, int w, int lane, int nh, int& k) {
+  const int v = wave_sort_desc(key, lane);
   const int r = NW * lane + ((lane & 1) ? NW - 1 - w : w);
   const int got = __shfl(v, r < 64 ? r : 63, 64);
   if (r >= nh) {

@@ -56,12 +56,14 @@ class RenderOpts:
     background: Sequence[float] = (0.0, 0.0, 0.0)
     order: int = 0   # 0: each ray's own contact depth; 1: tile order (packet virtual ray)
     hits_per_item: int = 0   # work-item size of the network kernels: 16, 32, 64; 0 = autotuned (64 untuned)
+    bwd_items_per_group: int = 0   # backward work items per workgroup: 1, 2, 4, 8; 0 = autotuned (else a rule)
 
     def c(self) -> _lib.Opts:
         bg = (ctypes.c_float * 3)(*[float(b) for b in self.background])
         return _lib.Opts(self.samples_fixed, self.samples_min, self.samples_max,
                          float(self.samples_per_unit), float(self.t_stop), self.jitter,
-                         self.jitter_seed & 0xFFFFFFFF, bg, self.order, self.hits_per_item)
+                         self.jitter_seed & 0xFFFFFFFF, bg, self.order, self.hits_per_item,
+                         self.bwd_items_per_group)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -145,13 +147,15 @@ def msplat_get_stats(ctx: Context, ws: torch.Tensor, stream=None) -> dict:
 
 def msplat_autotune(ctx: Context, spec: NetSpec, opts: RenderOpts, center, scale, quat, mlp, ray_o, ray_d,
                     rgb, trans, feat, grad_rgb, ws, g_center, g_scale, g_quat, g_mlp, stream=None):
-    """Returns (status, chosen hits per work item)."""
+    """Returns (status, chosen hits per work item, chosen backward work items per workgroup)."""
     chosen = ctypes.c_int32(0)
+    chosen_group = ctypes.c_int32(0)
     st = ctx.lib.msplat_autotune(
         ctx.handle, ctypes.byref(spec.c()), ctypes.byref(opts.c()), _p(center), _p(scale), _p(quat), _p(mlp),
         _p(ray_o), _p(ray_d), int(ray_o.shape[0]), _p(rgb), _p(trans), _p(feat), _p(grad_rgb), _p(ws), ws.numel(),
-        _p(g_center), _p(g_scale), _p(g_quat), _p(g_mlp), ctypes.byref(chosen), _stream(stream))
-    return st, int(chosen.value)
+        _p(g_center), _p(g_scale), _p(g_quat), _p(g_mlp), ctypes.byref(chosen), ctypes.byref(chosen_group),
+        _stream(stream))
+    return st, int(chosen.value), int(chosen_group.value)
 
 
 def msplat_profile_enable(ctx: Context, enable: bool = True) -> None:
@@ -328,10 +332,12 @@ class Renderer:
             raise MsplatError(st, "msplat_render_backward_slots")
         return tuple(g)
 
-    def autotune(self, center, scale, quat, mlp, ray_o, ray_d, grad_rgb=None) -> int:
+    def autotune(self, center, scale, quat, mlp, ray_o, ray_d, grad_rgb=None) -> dict:
         """Time the work-item sizes on this workload (forward, and backward
-        with ``grad_rgb``); later renders of it with hits_per_item = 0 use the
-        fastest.  Returns the chosen size."""
+        with ``grad_rgb``; then, with ``grad_rgb``, the backward's work items
+        per workgroup); later renders of it with hits_per_item = 0 (and
+        bwd_items_per_group = 0) use the fastest.  Returns the choices:
+        {"hits_per_item", "bwd_items_per_group" (0 without grad_rgb)}."""
         self.check_inputs(center, scale, quat, mlp, ray_o, ray_d)
         R = ray_o.shape[0]
         P = self.spec.num_prims
@@ -342,11 +348,11 @@ class Renderer:
         if grad_rgb is not None:
             grad_rgb = grad_rgb.contiguous().float()
             _check(grad_rgb, "grad_rgb", (R, 3))
-        st, chosen = msplat_autotune(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o, ray_d, rgb,
-                                     trans, feat, grad_rgb, ws, *g)
+        st, chosen, group = msplat_autotune(self.ctx, self.spec, self.opts, center, scale, quat, mlp, ray_o,
+                                            ray_d, rgb, trans, feat, grad_rgb, ws, *g)
         if st != _lib.MSPLAT_OK:
             raise MsplatError(st, "msplat_autotune")
-        return chosen
+        return {"hits_per_item": chosen, "bwd_items_per_group": group}
 
     def stats(self, ws) -> dict:
         return msplat_get_stats(self.ctx, ws)

@@ -1,7 +1,9 @@
 """The work-item autotuner: every work-item size the network kernels can run
-with (16, 32, 64 hits of one primitive per workgroup) renders and
+with (16, 32, 64 hits of one primitive per workgroup) and every number of
+work items a backward workgroup takes in turn (1, 2, 4, 8; with 16-hit items
+and 8 per workgroup, many workgroups span two or more primitives) renders and
 differentiates within the tolerances of the FP64 oracle, and the tuner's
-choice is recorded and used."""
+choices are recorded and used."""
 import dataclasses
 
 import numpy as np
@@ -19,14 +21,14 @@ KEYS = ("center", "scale", "quat", "mlp")
 TOL = {"fp32": 1e-5, "bf16x3": 2e-3}
 
 
-@pytest.mark.parametrize("hpi", [16, 32, 64])
+@pytest.mark.parametrize("hpi,group", [(16, 1), (32, 2), (64, 4), (16, 8)])
 @pytest.mark.parametrize("ci,w,h,precision", [(1, 64, 50, "bf16x3"), (4, 44, 40, "bf16x3"), (4, 44, 40, "fp32"),
                                               (3, 40, 30, "bf16x3")])
-def test_every_work_item_size_matches_oracle(hpi, ci, w, h, precision):
+def test_every_work_item_size_matches_oracle(hpi, group, ci, w, h, precision):
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
     o, d = view_rays(ci, w, h)
-    opts = dataclasses.replace(opts_of(cfg), hits_per_item=hpi)
+    opts = dataclasses.replace(opts_of(cfg), hits_per_item=hpi, bwd_items_per_group=group)
     R = len(o)
     g = gpu_render(ci, precision, sc, o, d, opts)
     assert g["stats"]["hits_per_item"] == hpi
@@ -48,9 +50,10 @@ def test_every_work_item_size_matches_oracle(hpi, ci, w, h, precision):
     out = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
                                  torch.from_numpy(g_rgb).cuda(), None,
                                  None if g_ft is None else torch.from_numpy(g_ft).cuda())
+    assert g["renderer"].stats(g["ws"])["bwd_items_per_group"] == group
     for k, v in zip(KEYS, out):
         rel = float(np.abs(v.cpu().numpy() - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
-        print(f"config {ci} {precision} {hpi} hits per item {k}: {rel:.2e}")
+        print(f"config {ci} {precision} {hpi} hits per item, {group} per group {k}: {rel:.2e}")
         assert rel <= TOL[precision], k
 
 
@@ -68,13 +71,37 @@ def test_autotune_records_and_uses_its_choice():
     t, to, td = g["dev"]
     grad = torch.full((len(o), 3), 1.0 / len(o), device="cuda")
     chosen = r.autotune(t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
-    assert chosen in (16, 32, 64)
+    assert chosen["hits_per_item"] in (16, 32, 64)
+    assert chosen["bwd_items_per_group"] in (1, 2, 4, 8)
     _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
-    assert r.stats(ws)["hits_per_item"] == chosen
+    assert r.stats(ws)["hits_per_item"] == chosen["hits_per_item"]
+    r.backward(ws, t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
+    assert r.stats(ws)["bwd_items_per_group"] == chosen["bwd_items_per_group"]
     # another workload (ray count) is not covered by the choice
     _, _, _, ws2 = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to[:640], td[:640])
     assert r.stats(ws2)["hits_per_item"] == 64
     # an explicit size wins
-    r2 = Renderer(r.spec, dataclasses.replace(opts, hits_per_item=16))
+    r2 = Renderer(r.spec, dataclasses.replace(opts, hits_per_item=16, bwd_items_per_group=2))
     _, _, _, ws3 = r2.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
     assert r2.stats(ws3)["hits_per_item"] == 16
+    r2.backward(ws3, t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
+    assert r2.stats(ws3)["bwd_items_per_group"] == 2
+
+
+@pytest.mark.parametrize("field,value", [("hits_per_item", 48), ("bwd_items_per_group", 3),
+                                         ("bwd_items_per_group", 16)])
+def test_work_item_options_are_validated(field, value):
+    from paper_2606_03877_amd import Renderer, msplat_render_forward, _lib
+    from gpu_cases import spec_of, to_dev
+    ci = 0
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    o, d = view_rays(ci, 16, 8)
+    r = Renderer(spec_of(cfg, "fp32"), dataclasses.replace(opts_of(cfg), **{field: value}))
+    t, to, td = to_dev(sc, o, d)
+    ws = r.new_workspace(len(o))
+    rgb = torch.empty((len(o), 3), device="cuda")
+    trans = torch.empty((len(o),), device="cuda")
+    st, _ = msplat_render_forward(r.ctx, r.spec, r.opts, t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                  rgb, trans, None, ws)
+    assert st == _lib.MSPLAT_E_INVALID
