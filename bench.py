@@ -146,7 +146,7 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
     return {
         "hits": hits,
         "hits_per_item": tuned["hits_per_item"],
-        "bwd_items_per_group": tuned["bwd_items_per_group"],
+        "items_per_group": tuned["items_per_group"],
         "fwdbwd_ms": 1e3 * (t1 - t0) / steps if train else None,
         "fwd_ms": 1e3 * (f1 - f0) / steps,
         "fwdbwd_rays_per_s": R * steps / (t1 - t0) if train else None,
@@ -604,7 +604,7 @@ def main():
                    "rays": R, "hits": int(st["num_hits"]), "samples": int(st["num_samples"]),
                    "terminated_rays": int(st["num_terminated"]),
                    "mlp_precision": "bf16 hi+lo operand pairs (3 products), fp32 accumulate",
-                   "hits_per_item": int(st["hits_per_item"])},
+                   "hits_per_item": int(st["hits_per_item"]), "items_per_group": int(st["items_per_group"])},
         "fwd_rays_per_s": b["fwd_rays_per_s"],
         "fwdbwd_rays_per_s": b["fwdbwd_rays_per_s"],
         "rgb_max_err_vs_fp64": errs,
@@ -621,8 +621,8 @@ def main():
     for k, v in legs.items():
         e = {"fwd_rays_per_s": v["fwd_rays_per_s"], "fwd_samples_per_s": v["fwd_rays_per_s"] / R * st["num_samples"],
              "fwd_ms": v["fwd_ms"], "autotuned_hits_per_item": v["hits_per_item"]}
-        if v["bwd_items_per_group"]:
-            e["autotuned_bwd_items_per_group"] = v["bwd_items_per_group"]
+        if v["items_per_group"]:
+            e["autotuned_items_per_group"] = v["items_per_group"]
         if v["fwdbwd_ms"] is not None:
             e.update({"fwdbwd_rays_per_s": v["fwdbwd_rays_per_s"], "fwdbwd_ms": v["fwdbwd_ms"]})
         else:

@@ -129,12 +129,13 @@ typedef struct msplat_opts {
   int32_t hits_per_item;    /* hits of one primitive per work item of the network
                                kernels: 16, 32 or 64; 0 = the choice msplat_autotune
                                recorded for this network and workload (64 if none) */
-  int32_t bwd_items_per_group; /* one workgroup of the backward network kernel takes
-                               the hits of this many consecutive work items of one
-                               primitive (at most 64 hits per wave of the kernel),
-                               deals them to its waves in one balanced deal and
-                               keeps the primitive's weight-gradient sums in
-                               registers across them: 1, 2, 4 or 8; 0 = the choice
+  int32_t items_per_group;  /* one workgroup of the network kernels (forward and
+                               backward) takes the hits of this many consecutive
+                               work items of one primitive (at most 64 hits per wave
+                               of the kernel), deals them to its waves in one
+                               balanced deal, stages the primitive's weights once and
+                               (backward) keeps its weight-gradient sums in registers
+                               across them: 1, 2, 4 or 8; 0 = the choice
                                msplat_autotune recorded, else the most that leave at
                                least 2048 workgroups */
 } msplat_opts;
@@ -149,8 +150,7 @@ typedef struct msplat_stats {
   int64_t num_fallbacks;      /* hit tests decided in double-float arithmetic */
   float min_abs_g;            /* smallest |1 - |p_c|^2| seen among tested pairs */
   int32_t hits_per_item;      /* work-item size the network kernels ran with */
-  int32_t bwd_items_per_group; /* work items per workgroup of the context's last
-                                 backward (0 before the first) */
+  int32_t items_per_group;    /* work items per workgroup the forward ran with */
 } msplat_stats;
 
 typedef struct msplat_ctx msplat_ctx;
@@ -288,20 +288,20 @@ int msplat_profile_read(msplat_ctx* ctx, int max_stages, const char** names, dou
 /*
  * Work-item autotuner (an implementation choice, not part of the method).
  * The network kernels take the hits of one primitive in work items of
- * hits_per_item hits, one workgroup each; the best size depends on the
- * network and on the workload's hit and sample counts.  This call runs the
+ * hits_per_item hits, items_per_group of them per workgroup; the best sizes
+ * depend on the network and on the workload's hit and sample counts.  This call runs the
  * forward (and, when grad_rgb is not NULL, the backward) of the given
  * arguments once per candidate size (64, 32, 16), times each on `stream`
  * with HIP events, records the fastest for this context, network and
  * workload (ray count, primitive count and sample options) and writes it to
- * *chosen.  With grad_rgb it then runs the forward at that size and times
- * the backward alone with 1, 2, 4 and 8 work items per workgroup, records
- * the fastest beside it and writes it to *chosen_group (if not NULL; 0
- * without grad_rgb).  Later calls with opts->hits_per_item == 0 (and
- * opts->bwd_items_per_group == 0) and the same network and workload use
- * them.  Arguments as for msplat_render_forward and msplat_render_backward;
- * every output buffer is overwritten (with the last candidate's results)
- * and ws is left as the last forward wrote it.  Synchronises `stream`.
+ * *chosen.  Unless opts->items_per_group is set, it then runs the same calls
+ * at that size with 1, 2, 4 and 8 work items per workgroup, records the
+ * fastest beside it and writes it to *chosen_group (if not NULL).  Later
+ * calls with opts->hits_per_item == 0 (and opts->items_per_group == 0) and
+ * the same network and workload use them.  Arguments as for
+ * msplat_render_forward and msplat_render_backward; every output buffer is
+ * overwritten (with the last candidate's results) and ws is left as the
+ * last forward wrote it.  Synchronises `stream`.
  */
 int msplat_autotune(msplat_ctx* ctx, const msplat_model* model, const msplat_opts* opts,
                     const float* center, const float* scale, const float* quat, const float* mlp,

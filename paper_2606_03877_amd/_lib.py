@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("t_stop", ctypes.c_float), ("jitter", ctypes.c_int32),
                 ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3),
                 ("order", ctypes.c_int32), ("hits_per_item", ctypes.c_int32),
-                ("bwd_items_per_group", ctypes.c_int32)]
+                ("items_per_group", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
                 ("num_samples", ctypes.c_int64), ("num_work_items", ctypes.c_int64),
                 ("num_terminated", ctypes.c_int64), ("num_fallbacks", ctypes.c_int64),
                 ("min_abs_g", ctypes.c_float), ("hits_per_item", ctypes.c_int32),
-                ("bwd_items_per_group", ctypes.c_int32)]
+                ("items_per_group", ctypes.c_int32)]
 
 
 EXPORTS = {

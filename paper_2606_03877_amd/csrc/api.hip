@@ -35,7 +35,7 @@ struct TuneEntry {
   int32_t samples_fixed, samples_min, samples_max, order;
   float samples_per_unit;
   int32_t hits_per_item;
-  int32_t bwd_group;   // backward work items per workgroup; 0 = not tuned
+  int32_t group;   // work items per workgroup of the network kernels; 0 = not tuned
 };
 constexpr int kTuneSlots = 32;
 
@@ -61,7 +61,7 @@ struct msplat_ctx {
   uint64_t last_bytes;
   NetShape last_shape;
   int32_t last_hpi;
-  int32_t last_bwd_group = 0;   // work items per workgroup of the last backward
+  int32_t last_group = 0;   // work items per workgroup of the last forward
 };
 
 namespace {
@@ -239,7 +239,7 @@ bool opts_ok(const msplat_opts* o) {
   if (o->order != 0 && o->order != 1) return false;
   if (o->hits_per_item != 0 && o->hits_per_item != 16 && o->hits_per_item != 32 && o->hits_per_item != 64)
     return false;
-  const int32_t g = o->bwd_items_per_group;
+  const int32_t g = o->items_per_group;
   if (g != 0 && g != 1 && g != 2 && g != 4 && g != 8) return false;
   return true;
 }
@@ -259,12 +259,13 @@ int32_t hits_per_item_of(const msplat_ctx* c, const NetShape& n, int64_t R, cons
   return kHitsPerItem;
 }
 
-// backward work items per workgroup: the option, else the recorded choice,
-// else the most (up to 8) that leave at least 2048 workgroups (eight per CU)
-int32_t bwd_group_of(const msplat_ctx* c, const NetShape& n, int64_t R, const msplat_opts& o, int64_t items) {
-  if (o.bwd_items_per_group) return o.bwd_items_per_group;
+// work items per workgroup of the network kernels: the option, else the
+// recorded choice, else the most (up to 8) that leave at least 2048
+// workgroups (eight per CU)
+int32_t group_of(const msplat_ctx* c, const NetShape& n, int64_t R, const msplat_opts& o, int64_t items) {
+  if (o.items_per_group) return o.items_per_group;
   for (int i = 0; i < c->num_tuned; ++i)
-    if (tune_match(c->tuned[i], n, R, o) && c->tuned[i].bwd_group) return c->tuned[i].bwd_group;
+    if (tune_match(c->tuned[i], n, R, o) && c->tuned[i].group) return c->tuned[i].group;
   int32_t g = 1;
   while (g < 8 && items >= (int64_t)2048 * 2 * g) g *= 2;
   return g;
@@ -446,10 +447,11 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   if (need_bytes) *need_bytes = layout(n, R, nh, nullptr, nullptr) + 32 * kAlign;
   STAGE(ctx, ST_BIN_FILL, s, launch_bin_fill(ws, ray_o, ray_d, center, scale, quat, R, n.P, *o, n.kind, s));
   STAGE(ctx, ST_HIT_REC, s, launch_hit_records(ws, ray_o, ray_d, nh, n.kind, s));
-  STAGE(ctx, ST_MLP_FWD, s, launch_mlp_forward(n, ws, *o, (int)items, 0, rgb, trans, feat, s));
+  const int32_t group = group_of(ctx, n, R, *o, items);
+  STAGE(ctx, ST_MLP_FWD, s, launch_mlp_forward(n, ws, *o, nh, group, 0, rgb, trans, feat, s));
   STAGE(ctx, ST_COMPOSITE, s, launch_composite(ws, R, *o, rgb, trans, feat, cf, s));
   if (o->t_stop > 0.f)
-    STAGE(ctx, ST_MLP_FIXUP, s, launch_mlp_forward(n, ws, *o, (int)items, 1, rgb, trans, feat, s));
+    STAGE(ctx, ST_MLP_FIXUP, s, launch_mlp_forward(n, ws, *o, nh, group, 1, rgb, trans, feat, s));
   ctx->last_ws = wsp;
   ctx->last_items = items;
   ctx->last_hits = nh;
@@ -457,6 +459,7 @@ int msplat_render_forward(msplat_ctx* ctx, const msplat_model* m, const msplat_o
   ctx->last_bytes = ws_bytes;
   ctx->last_shape = n;
   ctx->last_hpi = ws.hits_per_item;
+  ctx->last_group = group;
   return MSPLAT_OK;
 }
 
@@ -558,10 +561,9 @@ static int backward_impl(msplat_ctx* ctx, const msplat_model* m, const msplat_op
   STAGE(ctx, ST_COMP_ADJ, s,
         launch_composite_adjoint(ws, R, *o, grad_rgb, grad_trans, cf > 0 ? grad_feat : nullptr, cf,
                                  ws.ray_tf, s));
-  const int32_t group = bwd_group_of(ctx, n, R, *o, items);
+  const int32_t group = group_of(ctx, n, R, *o, items);
   STAGE(ctx, ST_MLP_BWD, s,
         launch_mlp_backward(n, ws, *o, nh, group, ray_d, grad_rgb, cf > 0 ? grad_feat : nullptr, g_mlp, s));
-  ctx->last_bwd_group = group;
   if (sa)
     STAGE(ctx, ST_SLOT_BWD_PRIMS, s,
           launch_slot_backward_prims(ws, n.P, (int)items, sa->slots, sa->C, sa->grad_slot, ray_d, sa->g_slots,
@@ -664,23 +666,25 @@ int msplat_autotune(msplat_ctx* ctx, const msplat_model* m, const msplat_opts* o
       best_ms = ms;
     }
   }
-  if (st == MSPLAT_OK && grad_rgb && o->bwd_items_per_group == 0) {
+  if (st == MSPLAT_OK && o->items_per_group == 0) {
     msplat_opts oc = *o;
     oc.hits_per_item = best;
-    st = fwd(oc);
     const int32_t gcand[4] = {1, 2, 4, 8};
     float gbest_ms = 0.f;
     for (int c = 0; c < 4 && st == MSPLAT_OK; ++c) {
-      oc.bwd_items_per_group = gcand[c];
+      oc.items_per_group = gcand[c];
       float ms = 0.f;
-      st = timed([&] { return bwd(oc); }, &ms);
+      st = timed([&] {
+        int r = fwd(oc);
+        return (r == MSPLAT_OK && grad_rgb) ? bwd(oc) : r;
+      }, &ms);
       if (st == MSPLAT_OK && (best_group == 0 || ms < gbest_ms)) {
         best_group = gcand[c];
         gbest_ms = ms;
       }
     }
-  } else if (grad_rgb) {
-    best_group = o->bwd_items_per_group;
+  } else {
+    best_group = o->items_per_group;
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
@@ -716,7 +720,7 @@ int msplat_get_stats(msplat_ctx* ctx, const void* wsp, uint64_t ws_bytes, msplat
   std::memcpy(&mg, &c.min_abs_g_bits, 4);
   out->min_abs_g = mg;
   out->hits_per_item = c.hits_per_item;
-  out->bwd_items_per_group = ctx->last_bwd_group;
+  out->items_per_group = ctx->last_group;
   (void)ws_bytes;
   return MSPLAT_OK;
 }

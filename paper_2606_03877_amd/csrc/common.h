@@ -255,6 +255,9 @@ hipError_t launch_bin_fill(const Workspace& ws, const float* ray_o, const float*
                            int64_t R, int P, const msplat_opts& o, int kind, hipStream_t s);
 hipError_t launch_hit_records(const Workspace& ws, const float* ray_o, const float* ray_d, int64_t num_hits,
                               int kind, hipStream_t s);
+// offsets of each primitive's runs of ghits hits (the workgroups of the
+// network kernels) into ws.gw_off
+hipError_t launch_group_scan(const Workspace& ws, int P, int ghits, hipStream_t s);
 hipError_t launch_composite(const Workspace& ws, int64_t R, const msplat_opts& o, float* rgb,
                             float* trans, float* feat, int cf, hipStream_t s);
 hipError_t launch_composite_adjoint(const Workspace& ws, int64_t R, const msplat_opts& o,
@@ -282,8 +285,10 @@ bool mlp_supported(const NetShape& n);
 int64_t mlp_wpack_bytes(const NetShape& n);
 hipError_t launch_pack_weights(const NetShape& n, const Workspace& ws, const float* mlp,
                                hipStream_t s);
+// (group >= 1: a workgroup takes the hits of that many work items of one
+// primitive, at most 64 per wave of the kernel)
 hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const msplat_opts& o,
-                              int num_items, int mode, float* rgb, float* trans, float* feat,
+                              int64_t num_hits, int group, int mode, float* rgb, float* trans, float* feat,
                               hipStream_t s);
 // mlp_bwd.hip
 // (group >= 1: a workgroup takes the hits of that many work items of one

@@ -503,6 +503,31 @@ __global__ __launch_bounds__(256) void prim_scan_kernel(const int32_t* __restric
   }
 }
 
+// offsets of each primitive's workgroups in the network kernels: primitive
+// i's hits [prim_off[i], prim_off[i+1]) in runs of ghits (one workgroup)
+__global__ __launch_bounds__(256) void group_scan_kernel(const int32_t* __restrict__ prim_off, int P, int ghits,
+                                                         int32_t* __restrict__ gw_off) {
+  __shared__ int32_t wsum[4];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < P; base += 256) {
+    const int i = base + threadIdx.x;
+    const int32_t n = i < P ? (prim_off[i + 1] - prim_off[i] + ghits - 1) / ghits : 0;
+    const int incl = wave_incl_scan(n);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int o = carry;
+    for (int k = 0; k < w; ++k) o += wsum[k];
+    if (i < P) gw_off[i] = incl - n + o;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = o + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gw_off[P] = carry;
+}
+
 // ----------------------------------------------------------- tile order --
 
 // contact depth of a primitive along the packet's virtual ray (vo, vd): the
@@ -1601,6 +1626,13 @@ hipError_t launch_hit_records(const Workspace& ws, const float* ray_o, const flo
   else
     hipLaunchKernelGGL(hit_record_kernel<false>, grid, dim3(256), 0, s, ray_o, ray_d, (const float*)ws.geo, ws,
                        num_hits);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_scan(const Workspace& ws, int P, int ghits, hipStream_t s) {
+  if (ghits < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_off, P, ghits,
+                     ws.gw_off);
   return hipGetLastError();
 }
 

@@ -119,8 +119,12 @@ __device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, 
   Act<N, rup(N::ENC_KS, N::KGRP)> B0;
   enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
+  // matrix-core stretch: issue ahead of the other waves' vector work
+  __builtin_amdgcn_s_setprio(1);
   layer_fwd<N, 0, N::ENC_KS, LAYOUT>(wb, wlo, lane, B0, acc);
-  return hidden_chain<N, 1, LAYOUT>(wb, wlo, lane, acc);
+  const f32x16 o = hidden_chain<N, 1, LAYOUT>(wb, wlo, lane, acc);
+  __builtin_amdgcn_s_setprio(0);
+  return o;
 }
 
 // How the forward kernel reads a primitive's operands: 1, all staged in LDS
@@ -134,7 +138,7 @@ constexpr int fwd_stage() {
   return N::fwd_bytes() <= kFwdLdsMax ? 1 : ((N::SPLIT && N::fwd_hi_bytes() <= kFwdLdsMax) ? 2 : 0);
 }
 template <class N>
-constexpr int fwd_lds_bytes() {
+constexpr int fwd_staged_bytes() {
   return fwd_stage<N>() == 1 ? N::fwd_bytes() : (fwd_stage<N>() == 2 ? N::fwd_hi_bytes() : 0);
 }
 
@@ -145,6 +149,7 @@ struct FwdArgs {
   msplat_opts opt;
   int mode;           // 0: all hits, hit-local sums; 1: fixup of cut hits
   int P;
+  int ghits;          // hits per workgroup (a run of one primitive's list), <= 64 per wave
   float* rgb;
   float* trans;
   float* feat;
@@ -159,6 +164,11 @@ constexpr int fwd_waves() { return N::WIDE ? 4 : 8; }
 // workgroups of eight; wide networks take the whole register file)
 template <class N>
 constexpr int fwd_min_waves() { return N::WIDE ? 1 : 4; }
+// LDS: the staged operands, then the deal table (64 ints per wave)
+template <class N>
+constexpr int fwd_deal_off() { return (fwd_staged_bytes<N>() + 15) / 16 * 16; }
+template <class N>
+constexpr int fwd_lds_bytes() { return fwd_deal_off<N>() + 256 * fwd_waves<N>(); }
 
 template <class N>
 __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_forward_kernel(FwdArgs args) {
@@ -168,10 +178,12 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
   const int wv = threadIdx.x / 64;
   const int col = lane % 32;
   const int g = lane / 32;
-  const int wi = blockIdx.x;
-  const int p = find_prim(ws.wi_off, args.P, wi);
-  const int first = ws.prim_off[p] + (wi - ws.wi_off[p]) * ws.hits_per_item;
-  const int nh = min(ws.hits_per_item, ws.prim_off[p + 1] - first);
+  // a run of up to args.ghits consecutive hits of one primitive's list
+  const int bid = blockIdx.x;
+  if (bid >= ws.gw_off[args.P]) return;   // (the grid is an upper bound)
+  const int p = find_prim(ws.gw_off, args.P, bid);
+  const int first = ws.prim_off[p] + (bid - ws.gw_off[p]) * args.ghits;
+  const int nh = min(args.ghits, ws.prim_off[p + 1] - first);
   const int64_t H = ws.hit_cap;
   if (args.mode == 1) {
     int flag = 0;
@@ -201,19 +213,22 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     __syncthreads();
     wts = lds;
   }
-  // this wave's hits
+  // this wave's hits: the run dealt to the waves (the fixup takes the cut
+  // hits only)
   constexpr int NWF = fwd_waves<N>();
-  static_assert(kHitsPerItem <= 64, "one item's hits fit the lanes of a wave");
-  int item_hit = 0, item_k = 0;
-  if (lane < nh) {
-    item_hit = ws.phit[first + lane];
-    int kk = ws.hit_k[item_hit] & kKMask;
-    item_k = (args.mode == 0 || ws.hit_nused[item_hit] == -1) ? kk : 0;
+  int my_k, li;
+  {
+    const int idx = 64 * wv + lane;
+    int key = -1;
+    if (idx < nh) {
+      const int h = ws.phit[first + idx];
+      const int kk = ws.hit_k[h] & kKMask;
+      key = ((args.mode == 0 || ws.hit_nused[h] == -1 ? kk : 0) << 9) | (511 - idx);
+    }
+    li = deal_run<NWF>(key, reinterpret_cast<int*>(lds + fwd_deal_off<N>()), wv, lane, my_k);
   }
-  int my_k;
-  const int li = deal_hits<NWF>(lane < nh ? (item_k << 7) | (127 - lane) : -1, wv, lane, nh, my_k);
-  const int my_hit = __shfl(item_hit, li < 0 ? 0 : li, 64);
-  const int c = __popcll(__ballot(li >= 0));   // (the wave's slots in use form a prefix)
+  const int my_hit = li < 0 ? 0 : ws.phit[first + li];
+  const int c = __popcll(__ballot(li >= 0));   // (the wave's hits fill lanes 0..c-1)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
   const int ns = __builtin_amdgcn_readlane(incl, 63);
@@ -367,10 +382,18 @@ static hipError_t pack_impl(const Workspace& ws, const float* mlp, int P, hipStr
 }
 
 template <class N>
-static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items, int mode, int P,
-                           float* rgb, float* trans, float* feat, hipStream_t s) {
-  if (items <= 0) return hipSuccess;
-  FwdArgs a{ws, o, mode, P, rgb, trans, feat};
+static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int64_t num_hits, int group, int mode,
+                           int P, float* rgb, float* trans, float* feat, hipStream_t s) {
+  if (num_hits <= 0) return hipSuccess;
+  if (group < 1 || ws.hits_per_item < 1) return hipErrorInvalidValue;
+  static_assert(fwd_lds_bytes<N>() <= kFwdLdsMax, "LDS budget of one workgroup");
+  // a workgroup's run: `group` work items, at most 64 hits per wave
+  const int ghits = min(group * ws.hits_per_item, 64 * fwd_waves<N>());
+  FwdArgs a{ws, o, mode, P, ghits, rgb, trans, feat};
+  if (mode == 0) {   // (the fixup pass reuses the offsets of the full pass)
+    hipError_t e = launch_group_scan(ws, P, ghits, s);
+    if (e != hipSuccess) return e;
+  }
   size_t lds = fwd_lds_bytes<N>();
   if (lds > 64 * 1024) {
     static bool attr = false;   // (per network type)
@@ -381,7 +404,10 @@ static hipError_t fwd_impl(const Workspace& ws, const msplat_opts& o, int items,
       attr = true;
     }
   }
-  hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3(items), dim3(64 * fwd_waves<N>()), lds, s, a);
+  // at most ceil(hits / ghits) runs plus one partial run per primitive; the
+  // workgroups past the last run return at once
+  const int64_t groups = (num_hits + ghits - 1) / ghits + P;
+  hipLaunchKernelGGL(mlp_forward_kernel<N>, dim3((unsigned)groups), dim3(64 * fwd_waves<N>()), lds, s, a);
   return hipGetLastError();
 }
 
@@ -401,20 +427,21 @@ int64_t mlp_wpack_bytes(const NetShape& n) {
 }
 
 hipError_t launch_pack_weights_wide(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s);
-hipError_t launch_mlp_forward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                                   int mode, float* rgb, float* trans, float* feat, hipStream_t s);
+hipError_t launch_mlp_forward_wide(const NetShape& n, const Workspace& ws, const msplat_opts& o, int64_t num_hits,
+                                   int group, int mode, float* rgb, float* trans, float* feat, hipStream_t s);
 hipError_t launch_pack_weights_narrow(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s);
-hipError_t launch_mlp_forward_narrow(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                                     int mode, float* rgb, float* trans, float* feat, hipStream_t s);
+hipError_t launch_mlp_forward_narrow(const NetShape& n, const Workspace& ws, const msplat_opts& o,
+                                     int64_t num_hits, int group, int mode, float* rgb, float* trans, float* feat,
+                                     hipStream_t s);
 
 hipError_t launch_pack_weights(const NetShape& n, const Workspace& ws, const float* mlp, hipStream_t s) {
   return wide_net(n.W) ? launch_pack_weights_wide(n, ws, mlp, s) : launch_pack_weights_narrow(n, ws, mlp, s);
 }
 
-hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int items,
-                              int mode, float* rgb, float* trans, float* feat, hipStream_t s) {
-  return wide_net(n.W) ? launch_mlp_forward_wide(n, ws, o, items, mode, rgb, trans, feat, s)
-                       : launch_mlp_forward_narrow(n, ws, o, items, mode, rgb, trans, feat, s);
+hipError_t launch_mlp_forward(const NetShape& n, const Workspace& ws, const msplat_opts& o, int64_t num_hits,
+                              int group, int mode, float* rgb, float* trans, float* feat, hipStream_t s) {
+  return wide_net(n.W) ? launch_mlp_forward_wide(n, ws, o, num_hits, group, mode, rgb, trans, feat, s)
+                       : launch_mlp_forward_narrow(n, ws, o, num_hits, group, mode, rgb, trans, feat, s);
 }
 #endif
 
@@ -427,10 +454,11 @@ hipError_t MSPLAT_TU_FN(launch_pack_weights)(const NetShape& n, const Workspace&
 }
 
 hipError_t MSPLAT_TU_FN(launch_mlp_forward)(const NetShape& n, const Workspace& ws, const msplat_opts& o,
-                                            int items, int mode, float* rgb, float* trans, float* feat,
-                                            hipStream_t s) {
-#define X(L_, W_, D_, O_, P_, K_) \
-  MSPLAT_MATCH(L_, W_, D_, O_, P_, K_) return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, items, mode, n.P, rgb, trans, feat, s);
+                                            int64_t num_hits, int group, int mode, float* rgb, float* trans,
+                                            float* feat, hipStream_t s) {
+#define X(L_, W_, D_, O_, P_, K_)                                                                     \
+  MSPLAT_MATCH(L_, W_, D_, O_, P_, K_)                                                                \
+  return fwd_impl<MSPLAT_NET(L_, W_, D_, O_, P_, K_)>(ws, o, num_hits, group, mode, n.P, rgb, trans, feat, s);
   MSPLAT_TU_NETS(X)
 #undef X
   return hipErrorInvalidValue;

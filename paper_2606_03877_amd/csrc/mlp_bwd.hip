@@ -411,10 +411,13 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, c
     encode_input<N>(ph, pl, dd, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
+    // matrix-core stretch: issue ahead of the other wave's vector work
+    __builtin_amdgcn_s_setprio(1);
     layer_fwd_from<N, 0, N::ENC_KS>(wb0, wb0, lane, a0, acc, first);
   }
   f32x16 out;
   chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);
+  __builtin_amdgcn_s_setprio(0);
   return out;
 }
 
@@ -462,12 +465,14 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   }
   // transposed product for the next delta (or the input gradient), overlapping the exchange
   f32x16 da[N::brb(J)];
+  __builtin_amdgcn_s_setprio(1);
   if constexpr (DOWN || J == 0) layer_bwd<N, J>(wb, lane, Bd, da);
   if constexpr (DW) {
     __syncthreads();
     dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(LO, J), q, lane);
     __syncthreads();
   }
+  __builtin_amdgcn_s_setprio(0);
   if constexpr (DOWN) {
     // relu': the layer input a_J = relu(z_{J-1}) is positive where z_{J-1} is
     f32x16 dzn[N::RBH];
@@ -536,7 +541,6 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   // waves in one balanced deal, and the weight-gradient sums stay in
   // registers until they are added to the global gradient at the end.
   constexpr int NW = B::NW;
-  static_assert(64 * NW <= 512, "hit indices of a workgroup fit 9 bits");
   const int bid = blockIdx.x;
   if (bid >= ws.gw_off[args.P]) return;   // (the grid is an upper bound)
   const int p = find_prim(ws.gw_off, args.P, bid);
@@ -555,11 +559,9 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   // are read
   const uint8_t* wts = B::GW ? wglb : lds + B::W_OFF - B::SKIP;
   const uint8_t* wts0 = B::G0 ? wglb : wts;
-  // ---- deal: wave q sorts the keys (samples, index) of hits 64q..64q+63 of
-  // the run, largest first; rank r of that list goes to wave
-  // (snake(r) + q) mod NW, snake(r) running 0..NW-1 and back over each row
-  // of NW ranks; each wave sorts what it received (its hits in lanes
-  // 0..c-1).  The sample counts of the waves then differ by about one hit's.
+  // ---- deal the run's hits to the waves (the exchange planes are free here)
+  int my_k;
+  int my_li;
   {
     const int idx = 64 * q + lane;
     int key = -1;
@@ -568,19 +570,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
       const int kk = ws.hit_nused[h] > 0 ? (ws.hit_k[h] & kKMask) : 0;
       key = (kk << 9) | (511 - idx);
     }
-    key = wave_sort_desc(key, lane);
-    reinterpret_cast<int*>(lds + B::XH_OFF)[idx] = key;   // (the exchange planes are free here)
-  }
-  __syncthreads();
-  int my_li, my_k;
-  {
-    constexpr int PER = 64 / NW;   // keys a wave takes from each wave's list
-    const int qc = lane / PER, j = lane % PER;
-    const int sp = (q - qc + NW) % NW;
-    const int r = j * NW + ((j & 1) ? NW - 1 - sp : sp);
-    const int key = wave_sort_desc(reinterpret_cast<const int*>(lds + B::XH_OFF)[64 * qc + r], lane);
-    my_li = key < 0 ? -1 : 511 - (key & 511);
-    my_k = key < 0 ? 0 : key >> 9;
+    my_li = deal_run<NW>(key, reinterpret_cast<int*>(lds + B::XH_OFF), q, lane, my_k);
   }
   const int my_hit = my_li < 0 ? 0 : ws.phit[first + my_li];
   const int c = __popcll(__ballot(my_li >= 0));   // (the wave's hits fill lanes 0..c-1)
@@ -596,9 +586,9 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
 #pragma unroll
   for (int i = 0; i < B::tiles(LO, HI); ++i) dacc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
   // carries of the hit-local scans from block to block
-  float cr_tau = 0.f, cr_P = 0.f, cr_geo[9];
+  float cr_tau = 0.f, cr_P = 0.f, cr_geo[7];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) cr_geo[i] = 0.f;
+  for (int i = 0; i < 7; ++i) cr_geo[i] = 0.f;
 
   int lb = 0;   // (scalar) lane of the hit holding the block's first column
   for (int b = 0; b < rounds; ++b) {
@@ -642,8 +632,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
       for (int r = 0; r < 3; ++r) gr[r] = args.grad_rgb[3 * ray + r];
     }
     float ph[3], pl[3], dd[3];
-    const float sk = sample_input<N>(ws, hit, k, u, ph, pl, dd);
-    const float om = ((float)k + u) / (float)K;
+    sample_input<N>(ws, hit, k, u, ph, pl, dd);
     const bool last = valid && k == K - 1;
     Keep<N, LO, HI> kp;
     f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lane, ph, pl, dd, kp);
@@ -719,74 +708,60 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     if (!valid) dp[0] = dp[1] = dp[2] = 0.f;
 
     // ---- per-hit geometry sums ----
-    // (contact-point primitive: one sample per hit, dL/d(delta) and
-    // dL/d(optical-depth factor) only)
-    float gv[9];
-    if constexpr (N::CONTACT) {
-      gv[0] = dp[0];
-      gv[1] = dp[1];
-      gv[2] = dp[2];
-      gv[3] = gv[4] = gv[5] = gv[6] = gv[7] = 0.f;
-      gv[8] = dts;
-    } else {
-      float ee[3];
+    // Scanned over each hit's samples: dL/dp (3), (k + u) dL/dp (3) and the
+    // optical-depth factor's adjoint (1); the contact-point primitive (one
+    // sample per hit) needs dL/d(delta) and that factor only.  The other
+    // sums the geometry adjoint takes follow per hit, e being fixed per hit:
+    // with s_k = s_a + (k + u) Delta and dL/ds_k = e . dL/dp,
+    //   sum s_k dL/dp = s_a sum dL/dp + Delta sum (k + u) dL/dp,
+    //   sum dL/ds_k = e . sum dL/dp,
+    //   sum omega_k dL/ds_k = e . sum (k + u) dL/dp / K.
+    constexpr int NS = N::CONTACT ? 4 : 7;
+    float sv[NS];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) ee[a] = ws.hit_e[a * H + hit];
-      const float dtk = dp[0] * ee[0] + dp[1] * ee[1] + dp[2] * ee[2];
-      gv[0] = dp[0];
-      gv[1] = dp[1];
-      gv[2] = dp[2];
-      gv[3] = sk * dp[0];
-      gv[4] = sk * dp[1];
-      gv[5] = sk * dp[2];
-      gv[6] = dtk;
-      gv[7] = om * dtk;
-      gv[8] = dts;
+    for (int a = 0; a < 3; ++a) sv[a] = dp[a];
+    if constexpr (!N::CONTACT) {
+      const float ku = (float)k + u;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sv[3 + a] = ku * dp[a];
     }
+    sv[NS - 1] = dts;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      gv[i] = sc.incl(gv[i]);
-      if (!sc.seen_head) gv[i] += cr_geo[i];
+    for (int i = 0; i < NS; ++i) {
+      sv[i] = sc.incl(sv[i]);
+      if (!sc.seen_head) sv[i] += cr_geo[i];
     }
     // the lane of the hit's last sample leaves the hit's sums; the chain to
     // the primitive's frame runs per hit in a kernel of its own
     if (last && g == 0) {
       const int pos = first + hli;   // the hit's entry in the grouped list
+      float gv[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gv[a] = sv[a];
+      if constexpr (N::CONTACT) {
+        gv[3] = gv[4] = gv[5] = gv[6] = gv[7] = 0.f;
+      } else {
+        const float sa = ws.hit_sa[hit];
+        float ee[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          ee[a] = ws.hit_e[a * H + hit];
+          gv[3 + a] = sa * sv[a] + dlt * sv[3 + a];
+        }
+        gv[6] = ee[0] * sv[0] + ee[1] * sv[1] + ee[2] * sv[2];
+        gv[7] = (ee[0] * sv[3] + ee[1] * sv[4] + ee[2] * sv[5]) / (float)K;
+      }
+      gv[8] = sv[NS - 1];
 #pragma unroll
       for (int i = 0; i < 9; ++i) ws.hit_gv[i * H + pos] = gv[i];
     }
     // carries of the geometry scans
 #pragma unroll
-    for (int i = 0; i < 9; ++i) cr_geo[i] = col31_same(gv[i]);
+    for (int i = 0; i < NS; ++i) cr_geo[i] = col31_same(sv[i]);
   }
 
   // ---- flush the weight-gradient strips ----
   flush_range<N, LO, LO, HI>(dacc, args.g_mlp + (int64_t)p * args.n_params, q, lane);
-}
-
-// offsets of each primitive's backward workgroups: primitive i's hits
-// [prim_off[i], prim_off[i+1]) in runs of ghits (one workgroup)
-__global__ __launch_bounds__(256) void group_scan_kernel(const int32_t* __restrict__ prim_off, int P, int ghits,
-                                                         int32_t* __restrict__ gw_off) {
-  __shared__ int32_t wsum[4];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int base = 0; base < P; base += 256) {
-    const int i = base + threadIdx.x;
-    const int32_t n = i < P ? (prim_off[i + 1] - prim_off[i] + ghits - 1) / ghits : 0;
-    const int incl = wave_incl_scan(n);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    int o = carry;
-    for (int k = 0; k < w; ++k) o += wsum[k];
-    if (i < P) gw_off[i] = incl - n + o;
-    __syncthreads();
-    if (threadIdx.x == 255) carry = o + incl;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) gw_off[P] = carry;
 }
 
 }  // namespace
@@ -825,8 +800,8 @@ static hipError_t bwd_impl(const Workspace& ws, const msplat_opts& o, int64_t nu
   // a workgroup's run: `group` work items of the forward, at most 64 hits per wave
   const int ghits = min(group * ws.hits_per_item, 64 * Bwd<N>::NW);
   BwdArgs a{ws, o, P, n_params, ghits, ray_d, grad_rgb, grad_feat, g_mlp};
-  hipLaunchKernelGGL(group_scan_kernel, dim3(1), dim3(256), 0, s, (const int32_t*)ws.prim_off, P, ghits,
-                     ws.gw_off);
+  hipError_t e = launch_group_scan(ws, P, ghits, s);
+  if (e != hipSuccess) return e;
   // at most ceil(hits / ghits) runs plus one partial run per primitive; the
   // workgroups past the last run return at once
   const int64_t groups = (num_hits + ghits - 1) / ghits + P;

@@ -446,25 +446,28 @@ __device__ __forceinline__ int wave_sort_desc(int v, int lane) {
   return v;
 }
 
-// The hits of a work item dealt to its NW waves so that the waves' sample
-// counts balance (a workgroup lasts as long as its busiest wave).  Lane
-// l < nh brings key (k_l << 7) | (127 - l), k_l its hit's sample count, other
-// lanes -1; the keys are sorted in descending order across the wave
-// (distinct keys, item-local index in the low bits), and sorted position r
-// goes to wave w, slot s with r = NW s + w for even s and NW s + NW - 1 - w
-// for odd s (snake order).  Returns the item-local index of the hit in slot
-// `lane` of wave `w` (-1: no hit) and its count in k.
+// A run of up to 64 NW hits dealt to the NW waves of a workgroup so that the
+// waves' sample counts balance (a workgroup lasts as long as its busiest
+// wave).  Thread (wave w, lane l) brings the key of run hit i = 64 w + l:
+// (k_i << 9) | (511 - i), k_i its sample count, or -1 past the run.  Wave w
+// sorts its 64 keys, largest first; rank r of that list goes to wave
+// (snake(r) + w) mod NW, snake(r) running 0..NW-1 and back over each row of
+// NW ranks; the table `tab` (64 NW ints of LDS) carries them; each wave
+// sorts what it received.  Returns the run index of the hit in lane `lane`
+// of wave `w` (-1: none; the hits fill lanes 0..c-1) and its count in k.
+// Every thread of the workgroup calls it (it holds a barrier).
 template <int NW>
-__device__ __forceinline__ int deal_hits(int key, int w, int lane, int nh, int& k) {
-  const int v = wave_sort_desc(key, lane);
-  const int r = NW * lane + ((lane & 1) ? NW - 1 - w : w);
-  const int got = __shfl(v, r < 64 ? r : 63, 64);
-  if (r >= nh) {
-    k = 0;
-    return -1;
-  }
-  k = got >> 7;
-  return 127 - (got & 127);
+__device__ __forceinline__ int deal_run(int key, int* tab, int w, int lane, int& k) {
+  static_assert(64 * NW <= 512, "run indices fit 9 bits");
+  tab[64 * w + lane] = wave_sort_desc(key, lane);
+  __syncthreads();
+  constexpr int PER = 64 / NW;   // keys a wave takes from each wave's list
+  const int qc = lane / PER, j = lane % PER;
+  const int sp = (w - qc + NW) % NW;
+  const int r = j * NW + ((j & 1) ? NW - 1 - sp : sp);
+  const int got = wave_sort_desc(tab[64 * qc + r], lane);
+  k = got < 0 ? 0 : got >> 9;
+  return got < 0 ? -1 : 511 - (got & 511);
 }
 
 __device__ __forceinline__ int find_prim(const int32_t* __restrict__ wi_off, int P, int wi) {

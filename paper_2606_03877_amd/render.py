@@ -56,14 +56,14 @@ class RenderOpts:
     background: Sequence[float] = (0.0, 0.0, 0.0)
     order: int = 0   # 0: each ray's own contact depth; 1: tile order (packet virtual ray)
     hits_per_item: int = 0   # work-item size of the network kernels: 16, 32, 64; 0 = autotuned (64 untuned)
-    bwd_items_per_group: int = 0   # backward work items per workgroup: 1, 2, 4, 8; 0 = autotuned (else a rule)
+    items_per_group: int = 0   # work items per workgroup of the network kernels: 1, 2, 4, 8; 0 = autotuned (else a rule)
 
     def c(self) -> _lib.Opts:
         bg = (ctypes.c_float * 3)(*[float(b) for b in self.background])
         return _lib.Opts(self.samples_fixed, self.samples_min, self.samples_max,
                          float(self.samples_per_unit), float(self.t_stop), self.jitter,
                          self.jitter_seed & 0xFFFFFFFF, bg, self.order, self.hits_per_item,
-                         self.bwd_items_per_group)
+                         self.items_per_group)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -334,10 +334,9 @@ class Renderer:
 
     def autotune(self, center, scale, quat, mlp, ray_o, ray_d, grad_rgb=None) -> dict:
         """Time the work-item sizes on this workload (forward, and backward
-        with ``grad_rgb``; then, with ``grad_rgb``, the backward's work items
-        per workgroup); later renders of it with hits_per_item = 0 (and
-        bwd_items_per_group = 0) use the fastest.  Returns the choices:
-        {"hits_per_item", "bwd_items_per_group" (0 without grad_rgb)}."""
+        with ``grad_rgb``), then the work items per workgroup; later renders
+        of it with hits_per_item = 0 (and items_per_group = 0) use the
+        fastest.  Returns the choices: {"hits_per_item", "items_per_group"}."""
         self.check_inputs(center, scale, quat, mlp, ray_o, ray_d)
         R = ray_o.shape[0]
         P = self.spec.num_prims
@@ -352,7 +351,7 @@ class Renderer:
                                             ray_d, rgb, trans, feat, grad_rgb, ws, *g)
         if st != _lib.MSPLAT_OK:
             raise MsplatError(st, "msplat_autotune")
-        return {"hits_per_item": chosen, "bwd_items_per_group": group}
+        return {"hits_per_item": chosen, "items_per_group": group}
 
     def stats(self, ws) -> dict:
         return msplat_get_stats(self.ctx, ws)

@@ -1,8 +1,8 @@
 """The work-item autotuner: every work-item size the network kernels can run
-with (16, 32, 64 hits of one primitive per workgroup) and every number of
-work items a backward workgroup takes in turn (1, 2, 4, 8; with 16-hit items
-and 8 per workgroup, many workgroups span two or more primitives) renders and
-differentiates within the tolerances of the FP64 oracle, and the tuner's
+with (16, 32, 64 hits of one primitive) and every number of work items a
+workgroup of the forward and backward network kernels takes (1, 2, 4, 8: a
+run of up to 512 hits of one primitive, dealt to the waves at once) renders
+and differentiates within the tolerances of the FP64 oracle, and the tuner's
 choices are recorded and used."""
 import dataclasses
 
@@ -21,14 +21,21 @@ KEYS = ("center", "scale", "quat", "mlp")
 TOL = {"fp32": 1e-5, "bf16x3": 2e-3}
 
 
-@pytest.mark.parametrize("hpi,group", [(16, 1), (32, 2), (64, 4), (16, 8)])
-@pytest.mark.parametrize("ci,w,h,precision", [(1, 64, 50, "bf16x3"), (4, 44, 40, "bf16x3"), (4, 44, 40, "fp32"),
-                                              (3, 40, 30, "bf16x3")])
-def test_every_work_item_size_matches_oracle(hpi, group, ci, w, h, precision):
+# (hits per item, items per workgroup) per case: every size of each knob, on
+# each network width and precision; 16 x 8 puts two or more primitives'
+# hits in most workgroups, and 64 x 4 in FP32 (two waves) is cut to the
+# 128 hits its workgroup holds
+CASES = [(1, 64, 50, "bf16x3", 16, 8), (1, 64, 50, "bf16x3", 64, 1), (4, 44, 40, "bf16x3", 32, 2),
+         (4, 44, 40, "bf16x3", 64, 8), (4, 44, 40, "fp32", 16, 1), (4, 44, 40, "fp32", 64, 4),
+         (3, 40, 30, "bf16x3", 16, 8), (3, 40, 30, "bf16x3", 32, 4)]
+
+
+@pytest.mark.parametrize("ci,w,h,precision,hpi,group", CASES)
+def test_every_work_item_size_matches_oracle(ci, w, h, precision, hpi, group):
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
     o, d = view_rays(ci, w, h)
-    opts = dataclasses.replace(opts_of(cfg), hits_per_item=hpi, bwd_items_per_group=group)
+    opts = dataclasses.replace(opts_of(cfg), hits_per_item=hpi, items_per_group=group)
     R = len(o)
     g = gpu_render(ci, precision, sc, o, d, opts)
     assert g["stats"]["hits_per_item"] == hpi
@@ -50,7 +57,7 @@ def test_every_work_item_size_matches_oracle(hpi, group, ci, w, h, precision):
     out = g["renderer"].backward(g["ws"], t["center"], t["scale"], t["quat"], t["mlp"], to, td,
                                  torch.from_numpy(g_rgb).cuda(), None,
                                  None if g_ft is None else torch.from_numpy(g_ft).cuda())
-    assert g["renderer"].stats(g["ws"])["bwd_items_per_group"] == group
+    assert g["stats"]["items_per_group"] == group
     for k, v in zip(KEYS, out):
         rel = float(np.abs(v.cpu().numpy() - ref[k]).max() / max(np.abs(ref[k]).max(), 1e-30))
         print(f"config {ci} {precision} {hpi} hits per item, {group} per group {k}: {rel:.2e}")
@@ -72,24 +79,22 @@ def test_autotune_records_and_uses_its_choice():
     grad = torch.full((len(o), 3), 1.0 / len(o), device="cuda")
     chosen = r.autotune(t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
     assert chosen["hits_per_item"] in (16, 32, 64)
-    assert chosen["bwd_items_per_group"] in (1, 2, 4, 8)
+    assert chosen["items_per_group"] in (1, 2, 4, 8)
     _, _, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
     assert r.stats(ws)["hits_per_item"] == chosen["hits_per_item"]
-    r.backward(ws, t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
-    assert r.stats(ws)["bwd_items_per_group"] == chosen["bwd_items_per_group"]
+    assert r.stats(ws)["items_per_group"] == chosen["items_per_group"]
     # another workload (ray count) is not covered by the choice
     _, _, _, ws2 = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to[:640], td[:640])
     assert r.stats(ws2)["hits_per_item"] == 64
     # an explicit size wins
-    r2 = Renderer(r.spec, dataclasses.replace(opts, hits_per_item=16, bwd_items_per_group=2))
+    r2 = Renderer(r.spec, dataclasses.replace(opts, hits_per_item=16, items_per_group=2))
     _, _, _, ws3 = r2.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
     assert r2.stats(ws3)["hits_per_item"] == 16
-    r2.backward(ws3, t["center"], t["scale"], t["quat"], t["mlp"], to, td, grad)
-    assert r2.stats(ws3)["bwd_items_per_group"] == 2
+    assert r2.stats(ws3)["items_per_group"] == 2
 
 
-@pytest.mark.parametrize("field,value", [("hits_per_item", 48), ("bwd_items_per_group", 3),
-                                         ("bwd_items_per_group", 16)])
+@pytest.mark.parametrize("field,value", [("hits_per_item", 48), ("items_per_group", 3),
+                                         ("items_per_group", 16)])
 def test_work_item_options_are_validated(field, value):
     from paper_2606_03877_amd import Renderer, msplat_render_forward, _lib
     from gpu_cases import spec_of, to_dev
