@@ -228,6 +228,13 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     li = deal_run<NWF>(key, reinterpret_cast<int*>(lds + fwd_deal_off<N>()), wv, lane, my_k);
   }
   const int my_hit = li < 0 ? 0 : ws.phit[first + li];
+  // the hit's ray and its slot along the ray (for the sample offsets), read
+  // once here rather than per block
+  int my_ray = 0, my_slot = 0;
+  if (li >= 0) {
+    my_ray = ws.hit_ray[my_hit];
+    my_slot = my_hit - ws.ray_off[my_ray];
+  }
   const int c = __popcll(__ballot(li >= 0));   // (the wave's hits fill lanes 0..c-1)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
@@ -254,6 +261,7 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
     while (lb + 1 < c && __builtin_amdgcn_readlane(my_off, lb + 1) <= x0) ++lb;
     int hit = __builtin_amdgcn_readlane(my_hit, lb), K = __builtin_amdgcn_readlane(my_k, lb);
     int hoff = __builtin_amdgcn_readlane(my_off, lb);
+    int ray = __builtin_amdgcn_readlane(my_ray, lb), slot = __builtin_amdgcn_readlane(my_slot, lb);
     for (int l = lb + 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
       if (ol >= x0 + 32) break;
@@ -261,13 +269,14 @@ __global__ __launch_bounds__(64 * fwd_waves<N>(), fwd_min_waves<N>()) void mlp_f
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);
         hoff = ol;
+        ray = __builtin_amdgcn_readlane(my_ray, l);
+        slot = __builtin_amdgcn_readlane(my_slot, l);
       }
     }
     const int k = valid ? x - hoff : 0;
     // sample position in the primitive's frame: p = p_c + (t_k - t_c) e
-    const int ray = ws.hit_ray[hit];
     float u = 0.5f;
-    if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
+    if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)slot, (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
     float ph[3], pl[3], dd[3];
     sample_input<N>(ws, hit, k, u, ph, pl, dd);

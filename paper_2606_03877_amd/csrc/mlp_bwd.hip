@@ -573,6 +573,13 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     my_li = deal_run<NW>(key, reinterpret_cast<int*>(lds + B::XH_OFF), q, lane, my_k);
   }
   const int my_hit = my_li < 0 ? 0 : ws.phit[first + my_li];
+  // the hit's ray and its slot along the ray (for the sample offsets), read
+  // once here rather than per block
+  int my_ray = 0, my_slot = 0;
+  if (my_li >= 0) {
+    my_ray = ws.hit_ray[my_hit];
+    my_slot = my_hit - ws.ray_off[my_ray];
+  }
   const int c = __popcll(__ballot(my_li >= 0));   // (the wave's hits fill lanes 0..c-1)
   int incl = wave_incl_scan(my_k);
   int my_off = incl - my_k;
@@ -603,6 +610,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     while (lb + 1 < c && __builtin_amdgcn_readlane(my_off, lb + 1) <= x0) ++lb;
     int hit = __builtin_amdgcn_readlane(my_hit, lb), K = __builtin_amdgcn_readlane(my_k, lb);
     int hoff = __builtin_amdgcn_readlane(my_off, lb), hli = __builtin_amdgcn_readlane(my_li, lb);
+    int ray = __builtin_amdgcn_readlane(my_ray, lb), slot = __builtin_amdgcn_readlane(my_slot, lb);
     for (int l = lb + 1; l < c; ++l) {
       const int ol = __builtin_amdgcn_readlane(my_off, l);
       if (ol >= x0 + 32) break;
@@ -610,13 +618,14 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
         hit = __builtin_amdgcn_readlane(my_hit, l);
         K = __builtin_amdgcn_readlane(my_k, l);
         hoff = ol;
+        ray = __builtin_amdgcn_readlane(my_ray, l);
+        slot = __builtin_amdgcn_readlane(my_slot, l);
         hli = __builtin_amdgcn_readlane(my_li, l);
       }
     }
     const int k = valid ? x - hoff : 0;
-    const int ray = ws.hit_ray[hit];
     float u = 0.5f;
-    if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)(hit - ws.ray_off[ray]), (uint32_t)k);
+    if (args.opt.jitter) u = sample_offset(seed_hash, (uint32_t)ray, (uint32_t)slot, (uint32_t)k);
     const float dlt = ws.hit_dlt[hit];
     // the hit's compositing records and the ray's upstream gradient are
     // loaded before the recompute so that their latency overlaps it
