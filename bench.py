@@ -142,7 +142,10 @@ def run_leg(cfg, precision, prm, ro, rd, target, steps, warmup, profile=True, or
         f1 = time.perf_counter()
     stats = r.stats(ws)
     R = ro.shape[0]
-    hits = r.hits(ws, R)[:2] if want_hits else None
+    hits = None
+    if want_hits:
+        off, prim, _, nused = r.hits(ws, R)
+        hits = (off, prim, int(np.clip(nused, 0, None).sum()))
     return {
         "hits": hits,
         "hits_per_item": tuned["hits_per_item"],
@@ -548,7 +551,7 @@ def main():
               file=sys.stderr, flush=True)
         diff = (tl["rgb"] - legs[MAIN]["rgb"]).float()
         mse = float((diff ** 2).mean())
-        (eo, ep), (to_, tp) = legs[MAIN]["hits"], tl["hits"]
+        (eo, ep, _), (to_, tp, _) = legs[MAIN]["hits"], tl["hits"]
         assert np.array_equal(eo, to_)
         moved = np.zeros(R, bool)
         dh = np.nonzero(ep != tp)[0]
@@ -565,6 +568,13 @@ def main():
 
     b = legs[MAIN]
     st = b["stats"]
+    # early termination: the network runs every scheduled sample (the cut is
+    # placed afterwards); the samples past the cut are the work it gives up
+    early = None
+    if b["hits"] is not None:
+        early = {"terminated_rays": int(st["num_terminated"]), "samples_scheduled": int(st["num_samples"]),
+                 "samples_composited": b["hits"][2],
+                 "fraction_past_the_cut": 1.0 - b["hits"][2] / max(1, int(st["num_samples"]))}
     roof = mfma_roofline(cfg, b, wkey, MAIN)
     hbm = hbm_rooflines(cfg, b, wkey, MAIN)
 
@@ -616,6 +626,7 @@ def main():
         "slot_features": slots,
         "config1_800x800": nested,
         "contact_primitive": contact,
+        "early_termination": early,
     }
     out["legs"] = {}
     for k, v in legs.items():

@@ -138,6 +138,16 @@ typedef struct msplat_opts {
                                across them: 1, 2, 4 or 8; 0 = the choice
                                msplat_autotune recorded, else the most that leave at
                                least 2048 workgroups */
+  const float* tile_rays;   /* order 1 only (else MSPLAT_E_INVALID): NULL, or device
+                               memory [ceil(num_rays / 64)][6] holding, per packet of
+                               64 consecutive rays, the virtual ray its hits are
+                               ordered along -- origin xyz, direction xyz (non-zero;
+                               only its direction matters) -- such as the ray
+                               through the centre of the packet's 8x8 pixel tile, as
+                               the paper orders a tile (Sec. 3.3, after Eq. 2).  NULL
+                               takes the mean origin and normalised direction sum
+                               described above.  Read by the forward only; owned by
+                               the caller */
 } msplat_opts;
 
 /* Counters filled by the forward pass (read with msplat_get_stats). */

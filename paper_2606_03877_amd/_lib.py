@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("t_stop", ctypes.c_float), ("jitter", ctypes.c_int32),
                 ("jitter_seed", ctypes.c_uint32), ("background", ctypes.c_float * 3),
                 ("order", ctypes.c_int32), ("hits_per_item", ctypes.c_int32),
-                ("items_per_group", ctypes.c_int32)]
+                ("items_per_group", ctypes.c_int32), ("tile_rays", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):

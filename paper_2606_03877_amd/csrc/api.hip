@@ -237,6 +237,7 @@ bool opts_ok(const msplat_opts* o) {
   }
   if (!(o->t_stop >= 0.f && o->t_stop < 1.f)) return false;
   if (o->order != 0 && o->order != 1) return false;
+  if (o->tile_rays && o->order != 1) return false;
   if (o->hits_per_item != 0 && o->hits_per_item != 16 && o->hits_per_item != 32 && o->hits_per_item != 64)
     return false;
   const int32_t g = o->items_per_group;

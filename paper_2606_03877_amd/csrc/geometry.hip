@@ -857,6 +857,12 @@ __global__ __launch_bounds__(256) void bin_fill_kernel(
   float3 o = valid ? ld3(ray_o, ray) : make_float3(0.f, 0.f, 0.f);
   float3 d = valid ? ld3(ray_d, ray) : make_float3(0.f, 0.f, 1.f);
   Cone cone = packet_cone(valid, o, d);
+  if (TILE && opt.tile_rays) {
+    // the caller's virtual ray of this packet (the ray through its tile's centre)
+    const float* v = opt.tile_rays + 6 * packet;
+    cone.vo = make_float3(v[0], v[1], v[2]);
+    cone.vd = make_float3(v[3], v[4], v[5]);
+  }
   const int64_t H = ws.hit_cap;
   int64_t off = valid ? ws.ray_off[ray] : 0;
   const int64_t last = min(packet * kWave + kWave, R);

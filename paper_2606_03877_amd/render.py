@@ -57,13 +57,17 @@ class RenderOpts:
     order: int = 0   # 0: each ray's own contact depth; 1: tile order (packet virtual ray)
     hits_per_item: int = 0   # work-item size of the network kernels: 16, 32, 64; 0 = autotuned (64 untuned)
     items_per_group: int = 0   # work items per workgroup of the network kernels: 1, 2, 4, 8; 0 = autotuned (else a rule)
+    # order 1: optional [ceil(R / 64), 6] float32 device tensor, per 64-ray packet the virtual ray (origin,
+    # direction) its hits are ordered along (e.g. through its 8x8 tile's centre); None = mean origin and
+    # normalised direction sum
+    tile_rays: Optional[torch.Tensor] = None
 
     def c(self) -> _lib.Opts:
         bg = (ctypes.c_float * 3)(*[float(b) for b in self.background])
         return _lib.Opts(self.samples_fixed, self.samples_min, self.samples_max,
                          float(self.samples_per_unit), float(self.t_stop), self.jitter,
                          self.jitter_seed & 0xFFFFFFFF, bg, self.order, self.hits_per_item,
-                         self.items_per_group)
+                         self.items_per_group, None if self.tile_rays is None else self.tile_rays.data_ptr())
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -244,6 +248,8 @@ class Renderer:
         R = ray_o.shape[0]
         _check(ray_o, "ray_o", (R, 3))
         _check(ray_d, "ray_d", (R, 3))
+        if self.opts.tile_rays is not None:
+            _check(self.opts.tile_rays, "tile_rays", ((R + 63) // 64, 6))
 
     def forward(self, center, scale, quat, mlp, ray_o, ray_d, ws: Optional[torch.Tensor] = None):
         """Returns (rgb [R,3], trans [R], feat [R,C] or None, workspace)."""

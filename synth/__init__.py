@@ -223,6 +223,28 @@ def camera_rays(cam: dict, tiled: bool = True) -> Tuple[np.ndarray, np.ndarray, 
     return o, np.ascontiguousarray(d, dtype=np.float32), pix
 
 
+def packet_tile_rays(cam: dict, packet: int = 64) -> np.ndarray:
+    """Per packet of ``packet`` consecutive rays of the camera's tile-ordered
+    rays: the ray from the eye through the centre of the packet's pixel
+    bounding box on the image plane -- for an 8x8 tile (view sides multiples
+    of 8), the tile's centre.  Returns float32 [n_packets, 6] (origin xyz,
+    unit direction xyz)."""
+    n = cam["width"] * cam["height"]
+    pix = tile_order(cam["width"], cam["height"])
+    out = np.empty(((n + packet - 1) // packet, 6), np.float64)
+    for k, s in enumerate(range(0, n, packet)):
+        p = pix[s:s + packet]
+        y, x = p // cam["width"], p % cam["width"]
+        xc = 0.5 * (x.min() + x.max() + 1)   # (pixel i spans [i, i + 1))
+        yc = 0.5 * (y.min() + y.max() + 1)
+        u = (xc - 0.5 * cam["width"]) / cam["focal"]
+        v = (yc - 0.5 * cam["height"]) / cam["focal"]
+        d = cam["fwd"] + u * cam["right"] - v * cam["up"]
+        out[k, :3] = cam["eye"]
+        out[k, 3:] = d / np.linalg.norm(d)
+    return out.astype(np.float32)
+
+
 def make_rays(cfg: Config, seed: Optional[int] = None):
     """Rays of the configuration: full frames of every view, tile-ordered, or
     (batch_rays > 0) a uniform random batch over (view, pixel) with

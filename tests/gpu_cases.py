@@ -57,12 +57,16 @@ def scene(ci):
     return synth.make_scene(synth.CONFIGS[ci])
 
 
-def view_rays(ci, width, height, seed=None):
-    """Rays of one (ragged if asked) view drawn like the configuration's cameras."""
+def view_camera(ci, width, height, seed=None):
+    """The camera of view_rays."""
     cfg = synth.CONFIGS[ci]
     rng = np.random.default_rng(1000 * ci + 1 if seed is None else seed)
-    cam = synth.make_camera(rng, width, height, cfg.camera_radius, cfg.fov_deg)
-    o, d, _ = synth.camera_rays(cam)
+    return synth.make_camera(rng, width, height, cfg.camera_radius, cfg.fov_deg)
+
+
+def view_rays(ci, width, height, seed=None):
+    """Rays of one (ragged if asked) view drawn like the configuration's cameras."""
+    o, d, _ = synth.camera_rays(view_camera(ci, width, height, seed))
     return o, d
 
 

@@ -10,7 +10,7 @@ import torch
 import oracle
 import synth
 from gpu_cases import (MASK_MAX, RELU_AMBIGUOUS, gpu_render, opts_of, oracle_model, oracle_opts, oracle_render,
-                       ray_nused, scene, spec_of, to_dev, view_rays)
+                       ray_nused, scene, spec_of, to_dev, view_camera, view_rays)
 
 pytestmark = pytest.mark.gpu
 
@@ -200,3 +200,49 @@ def test_order_option_is_validated():
                                    t64["mlp"], to.double(), td.double(), rgb.double(), trans.double(), None,
                                    w64)
     assert st[0] == _lib.MSPLAT_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("ci,w,h", [(1, 64, 64), (4, 96, 72)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 2e-3)])
+def test_caller_tile_rays(ci, w, h, precision, tol):
+    """Tile order along caller-supplied virtual rays: the ray through each 8x8
+    tile's centre, as the paper orders a tile."""
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    cam = view_camera(ci, w, h)
+    o, d, _ = synth.camera_rays(cam)
+    tr = synth.packet_tile_rays(cam)
+    rep = np.repeat(np.arange(len(tr)), 64)[:len(o)]
+    centre = (tr[rep, :3].astype(np.float64), tr[rep, 3:].astype(np.float64))
+    opts = dataclasses.replace(opts_of(cfg, order=1), tile_rays=torch.from_numpy(tr).cuda())
+    ref = oracle_render(ci, sc, o, d, opts, centre=centre)
+    g = gpu_render(ci, precision, sc, o, d, opts)
+    same = check_order(g, ref, tile_keys(sc, o, d, centre=centre))
+    ok = same & (ray_nused(g) == ref["n_used"])
+    err = float(np.abs(g["rgb"] - ref["rgb"])[ok].max())
+    default = oracle_render(ci, sc, o, d, opts_of(cfg, order=1))
+    moved = int(sum(not np.array_equal(ref["prim"][ref["ray_off"][r]:ref["ray_off"][r + 1]],
+                                       default["prim"][default["ray_off"][r]:default["ray_off"][r + 1]])
+                    for r in range(len(o))))
+    print(f"config {ci} {precision}: rgb err {err:.3g} over {int(ok.sum())} rays; rays ordered otherwise "
+          f"than along the default virtual rays {moved}")
+    assert ok.sum() >= len(o) - max(2, len(o) // 500)
+    assert err <= tol
+
+
+def test_tile_rays_need_tile_order():
+    from paper_2606_03877_amd import Renderer, msplat_render_forward, _lib
+    ci = 0
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    cam = view_camera(ci, 16, 8)
+    o, d, _ = synth.camera_rays(cam)
+    tr = torch.from_numpy(synth.packet_tile_rays(cam)).cuda()
+    r = Renderer(spec_of(cfg, "fp32"), dataclasses.replace(opts_of(cfg, order=0), tile_rays=tr))
+    t, to, td = to_dev(sc, o, d)
+    ws = r.new_workspace(len(o))
+    rgb = torch.empty((len(o), 3), device="cuda")
+    trans = torch.empty((len(o),), device="cuda")
+    st, _ = msplat_render_forward(r.ctx, r.spec, r.opts, t["center"], t["scale"], t["quat"], t["mlp"], to, td,
+                                  rgb, trans, None, ws)
+    assert st == _lib.MSPLAT_E_INVALID
