@@ -120,10 +120,10 @@ __device__ __forceinline__ f32x16 forward_block(const uint8_t* __restrict__ wb, 
   enc_to_B<N>(ev, B0);
   f32x16 acc[N::RBH];
   // matrix-core stretch: issue ahead of the other waves' vector work
-  __builtin_amdgcn_s_setprio(1);
+  mfma_priority<N, 1>();
   layer_fwd<N, 0, N::ENC_KS, LAYOUT>(wb, wlo, lane, B0, acc);
   const f32x16 o = hidden_chain<N, 1, LAYOUT>(wb, wlo, lane, acc);
-  __builtin_amdgcn_s_setprio(0);
+  mfma_priority<N, 0>();
   return o;
 }
 

@@ -412,12 +412,12 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, c
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
     // matrix-core stretch: issue ahead of the other wave's vector work
-    __builtin_amdgcn_s_setprio(1);
+    mfma_priority<N, 1>();
     layer_fwd_from<N, 0, N::ENC_KS>(wb0, wb0, lane, a0, acc, first);
   }
   f32x16 out;
   chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);
-  __builtin_amdgcn_s_setprio(0);
+  mfma_priority<N, 0>();
   return out;
 }
 
@@ -465,14 +465,14 @@ __device__ __forceinline__ void chain_back(uint8_t* __restrict__ lds, const uint
   }
   // transposed product for the next delta (or the input gradient), overlapping the exchange
   f32x16 da[N::brb(J)];
-  __builtin_amdgcn_s_setprio(1);
+  mfma_priority<N, 1>();
   if constexpr (DOWN || J == 0) layer_bwd<N, J>(wb, lane, Bd, da);
   if constexpr (DW) {
     __syncthreads();
     dw_tiles<N, J>(lds, dacc + Bwd<N>::toff(LO, J), q, lane);
     __syncthreads();
   }
-  __builtin_amdgcn_s_setprio(0);
+  mfma_priority<N, 0>();
   if constexpr (DOWN) {
     // relu': the layer input a_J = relu(z_{J-1}) is positive where z_{J-1} is
     f32x16 dzn[N::RBH];

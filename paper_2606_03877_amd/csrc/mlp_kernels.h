@@ -432,6 +432,14 @@ __device__ __forceinline__ float col_below(float v, int col) {
   return (col & 15) ? a : (col ? b : 0.f);
 }
 
+// wave priority over a matrix-core stretch: raised, the wave's matrix
+// instructions issue ahead of the other waves' vector work on its SIMD.
+// Wide networks run one wave per SIMD, where it only lengthens live ranges.
+template <class N, int P>
+__device__ __forceinline__ void mfma_priority() {
+  if constexpr (!N::WIDE) __builtin_amdgcn_s_setprio(P);
+}
+
 // bitonic sort of one value per lane over the wave, largest in lane 0
 __device__ __forceinline__ int wave_sort_desc(int v, int lane) {
 #pragma unroll
