@@ -1,10 +1,11 @@
 // Grouped per-primitive MLP kernels (Sec. 3.2 network, Sec. 3.3 compositing).
 //
-// Hits are grouped by primitive; one workgroup takes up to hits_per_item hits
-// of one primitive, stages that primitive's packed weights in LDS once (wide
-// networks read them from L2), and its waves (eight; four for wide networks)
-// each walk the samples of their hits (dealt by sample count) in blocks of 32
-// samples (matrix columns).  Per block: positional encoding straight
+// Hits are grouped by primitive; one workgroup takes a run of consecutive
+// hits of one primitive's list (items_per_group work items of hits_per_item
+// hits, at most 64 per wave), stages that primitive's packed weights in LDS
+// once (wide networks read them from L2), and its waves (eight; four for
+// wide networks) each walk the samples of their hits (dealt by sample count)
+// in blocks of 32 samples (matrix columns).  Per block: positional encoding straight
 // into the B operand, the layer chain on the matrix cores with activations
 // kept in registers, then the output activations and the hit-local front-to-
 // back compositing (segmented scans across the block's columns, carried from

@@ -2,9 +2,10 @@
 // the sample geometry (the paper prints no backward; this is the exact
 // derivative of the forward in mlp.hip with the discrete decisions fixed).
 //
-// Work decomposition is the forward's: one workgroup per group of up to
-// hits_per_item hits of one primitive, its operands (forward and transposed)
-// staged in LDS, each wave walking its hits' samples in 32-column blocks.
+// Work decomposition as in the forward: one workgroup per run of up to 64
+// hits per wave of one primitive's list, its operands (forward and
+// transposed) staged in LDS, the run dealt to the waves by sample count,
+// each wave walking its hits' samples in 32-column blocks.
 // Per block the wave
 //   1. recomputes the network, keeping the hi parts of the layer inputs in
 //      registers (nothing is stored to memory between forward and backward);
