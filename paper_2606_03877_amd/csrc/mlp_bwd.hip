@@ -759,7 +759,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
           gv[3 + a] = sa * sv[a] + dlt * sv[3 + a];
         }
         gv[6] = ee[0] * sv[0] + ee[1] * sv[1] + ee[2] * sv[2];
-        gv[7] = (ee[0] * sv[3] + ee[1] * sv[4] + ee[2] * sv[5]) / (float)K;
+        gv[7] = (ee[0] * sv[3] + ee[1] * sv[4] + ee[2] * sv[5]) * __builtin_amdgcn_rcpf((float)K);
       }
       gv[8] = sv[NS - 1];
 #pragma unroll

@@ -221,9 +221,16 @@ __device__ __forceinline__ uint4 lds16(const uint8_t* p) { return *reinterpret_c
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 __device__ __forceinline__ f32x4 as_f32x4(uint4 v) { return __builtin_bit_cast(f32x4, v); }
 
-__device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
+// Output activations.  The reciprocal is the hardware one (1 ulp): an IEEE
+// division costs about ten vector instructions per call.  log(1 + e) for
+// e = exp(-|x|) in (0, 1] is the hardware logarithm of 1 + e, or the series
+// e - e^2/2 below 1e-4, where forming 1 + e loses the low bits of e (the
+// absolute error stays below 1e-7 either way).
+__device__ __forceinline__ float sigmoidf_(float x) { return __builtin_amdgcn_rcpf(1.f + __expf(-x)); }
 __device__ __forceinline__ float softplusf_(float x) {
-  return fmaxf(x, 0.f) + log1pf(__expf(-fabsf(x)));
+  const float e = __expf(-fabsf(x));
+  const float l = e < 1e-4f ? e * (1.f - 0.5f * e) : __logf(1.f + e);
+  return fmaxf(x, 0.f) + l;
 }
 
 }  // namespace msplat
