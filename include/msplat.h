@@ -142,7 +142,7 @@ typedef struct msplat_opts {
                                memory [ceil(num_rays / 64)][6] holding, per packet of
                                64 consecutive rays, the virtual ray its hits are
                                ordered along -- origin xyz, direction xyz (non-zero;
-                               only its direction matters) -- such as the ray
+                               its length does not matter) -- such as the ray
                                through the centre of the packet's 8x8 pixel tile, as
                                the paper orders a tile (Sec. 3.3, after Eq. 2).  NULL
                                takes the mean origin and normalised direction sum
@@ -155,7 +155,8 @@ typedef struct msplat_stats {
   int64_t num_rays;
   int64_t num_hits;           /* ray/primitive intersections */
   int64_t num_samples;        /* network evaluations scheduled */
-  int64_t num_work_items;     /* primitive-grouped launches of the MLP kernel */
+  int64_t num_work_items;     /* primitive-grouped work items of hits_per_item hits
+                                 (a workgroup takes items_per_group of them) */
   int64_t num_terminated;     /* rays that stopped early */
   int64_t num_fallbacks;      /* hit tests decided in double-float arithmetic */
   float min_abs_g;            /* smallest |1 - |p_c|^2| seen among tested pairs */
