@@ -110,3 +110,23 @@ def test_work_item_options_are_validated(field, value):
     st, _ = msplat_render_forward(r.ctx, r.spec, r.opts, t["center"], t["scale"], t["quat"], t["mlp"], to, td,
                                   rgb, trans, None, ws)
     assert st == _lib.MSPLAT_E_INVALID
+
+
+@pytest.mark.parametrize("ci,w,h", [(1, 800, 800), (2, 0, 0)])
+def test_untuned_items_per_group_rule(ci, w, h):
+    """Without a recorded choice a workgroup takes the most work items (up to
+    8) that leave at least 2048 workgroups."""
+    cfg = synth.CONFIGS[ci]
+    sc = scene(ci)
+    if cfg.batch_rays:
+        o, d, _ = synth.make_rays(cfg)
+    else:
+        o, d = view_rays(ci, w, h)
+    g = gpu_render(ci, "bf16x3", sc, o, d, opts_of(cfg))
+    st = g["stats"]
+    items = int(st["num_work_items"])
+    want = 1
+    while want < 8 and items >= 2048 * 2 * want:
+        want *= 2
+    print(f"config {ci}: {items} work items, {st['items_per_group']} per workgroup")
+    assert st["items_per_group"] == want
