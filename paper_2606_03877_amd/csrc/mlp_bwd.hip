@@ -184,6 +184,73 @@ __device__ __forceinline__ void publish_delta(uint8_t* __restrict__ lds, const f
   }
 }
 
+// bfloat16 forms: accumulate one unit of dW_J (and db_J) over the round, row
+// tile rt (wave-uniform) by the column tiles [C0, C0 + CPG).  C0 is a
+// compile-time constant, so which tiles are inputs, which one is the bias
+// (ones) and which lie past the layer is fixed per instantiation: no branch
+// inside the k-step loop, every LDS address the lane's offset plus constants.
+template <class N, int J, int C0>
+__device__ __forceinline__ void dw_unit(const uint8_t* __restrict__ lds, f32x4* __restrict__ acc, int rt,
+                                        int lane) {
+  using B = Bwd<N>;
+  constexpr int CPG = B::CPG(J);
+  const int r16 = lane % 16, kg = lane / 16;
+  const int lo16 = r16 * B::XSP + 8 * kg;
+  const __bf16* pd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF) + 16 * rt * B::XSP + lo16;
+  const __bf16* pdl = reinterpret_cast<const __bf16*>(lds + B::XDL_OFF) + 16 * rt * B::XSP + lo16;
+  const __bf16* px = reinterpret_cast<const __bf16*>(lds + B::XH_OFF) + 16 * C0 * B::XSP + lo16;
+  const __bf16* pxl = reinterpret_cast<const __bf16*>(lds + B::XHL_OFF) + 16 * C0 * B::XSP + lo16;
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
+  // operands of one 32-sample k-step: delta row strip (hi, lo) and the
+  // unit's input tiles; the next k-step's are requested before this one's
+  // products
+  struct KOps {
+    bf16x8 a, al, b[CPG], bl[B::DWX ? CPG : 1];
+  };
+  auto load = [&](int kk, KOps& o) {
+    o.a = *reinterpret_cast<const bf16x8*>(pd + 32 * kk);
+    if constexpr (B::DWS) o.al = *reinterpret_cast<const bf16x8*>(pdl + 32 * kk);
+#pragma unroll
+    for (int c = 0; c < CPG; ++c) {
+      if (C0 + c >= B::CT(J)) continue;
+      o.b[c] = *reinterpret_cast<const bf16x8*>(px + 16 * c * B::XSP + 32 * kk);
+      if constexpr (B::DWX) o.bl[c] = *reinterpret_cast<const bf16x8*>(pxl + 16 * c * B::XSP + 32 * kk);
+    }
+  };
+  KOps ko[2];
+  load(0, ko[0]);
+#pragma unroll
+  for (int kk = 0; kk < B::XS / 32; ++kk) {
+    if (kk + 1 < B::XS / 32) load(kk + 1, ko[(kk + 1) & 1]);
+    const KOps& o = ko[kk & 1];
+#pragma unroll
+    for (int c = 0; c < CPG; ++c) {
+      if (C0 + c < B::CT(J)) {
+        acc[c] = mfma16(o.a, o.b[c], acc[c]);
+        if constexpr (B::DWS) acc[c] = mfma16(o.al, o.b[c], acc[c]);
+        if constexpr (B::DWX) acc[c] = mfma16(o.a, o.bl[c], acc[c]);
+      } else if (C0 + c < B::CTB(J)) {
+        // bias tile: the row sums of delta (lo: delta_lo x 1)
+        acc[c] = mfma16(o.a, ones, acc[c]);
+        if constexpr (B::DWS) acc[c] = mfma16(o.al, ones, acc[c]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// the unit's column group cg (wave-uniform) selects the instantiation
+template <class N, int J, int CG0>
+__device__ __forceinline__ void dw_unit_of(const uint8_t* __restrict__ lds, f32x4* __restrict__ acc, int rt,
+                                           int cg, int lane) {
+  if constexpr (CG0 < Bwd<N>::CG(J)) {
+    if (cg == CG0) dw_unit<N, J, CG0 * Bwd<N>::CPG(J)>(lds, acc, rt, lane);
+    else dw_unit_of<N, J, CG0 + 1>(lds, acc, rt, cg, lane);
+  }
+}
+
 // accumulate this wave's units of dW_J (and db_J) over the round: unit u =
 // q + i NW is row tile u % RT and column tiles [CPG (u / RT), +CPG)
 template <class N, int J>
@@ -195,56 +262,11 @@ __device__ __forceinline__ void dw_tiles(const uint8_t* __restrict__ lds, f32x4*
   for (int i = 0; i < B::OWN(J); ++i) {
     const int u = q + i * B::NW;
     if (u >= B::UNITS(J)) continue;
-    const int rt = u % B::RT(J), c0 = (u / B::RT(J)) * B::CPG(J);
-    f32x4* acc = dj + i * B::CPG(J);
     if constexpr (N::BF16) {
-      const __bf16* xd = reinterpret_cast<const __bf16*>(lds + B::XD_OFF);
-      const __bf16* xdl = reinterpret_cast<const __bf16*>(lds + B::XDL_OFF);
-      const __bf16* xh = reinterpret_cast<const __bf16*>(lds + B::XH_OFF);
-      const __bf16* xhl = reinterpret_cast<const __bf16*>(lds + B::XHL_OFF);
-      bf16x8 ones, zeros;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        ones[e] = (__bf16)(r16 == 0 ? 1.f : 0.f);
-        zeros[e] = (__bf16)0.f;
-      }
-      // operands of one 32-sample k-step: delta row strip (hi, lo) and the
-      // unit's input tiles (the bias tile contracts with ones); the next
-      // k-step's are requested before this one's products
-      struct KOps {
-        bf16x8 a, al, b[B::CPG(J)], bl[B::DWX ? B::CPG(J) : 1];
-      };
-      auto load = [&](int kk, KOps& o) {
-        const int so = 32 * kk + 8 * kg;
-        o.a = *reinterpret_cast<const bf16x8*>(xd + (16 * rt + r16) * B::XSP + so);
-        if constexpr (B::DWS) o.al = *reinterpret_cast<const bf16x8*>(xdl + (16 * rt + r16) * B::XSP + so);
-#pragma unroll
-        for (int c = 0; c < B::CPG(J); ++c) {
-          const int ct = c0 + c;
-          if (ct < B::CT(J)) o.b[c] = *reinterpret_cast<const bf16x8*>(xh + (16 * ct + r16) * B::XSP + so);
-          else o.b[c] = ones;
-          if constexpr (B::DWX) {
-            if (ct < B::CT(J)) o.bl[c] = *reinterpret_cast<const bf16x8*>(xhl + (16 * ct + r16) * B::XSP + so);
-            else o.bl[c] = zeros;
-          }
-        }
-      };
-      KOps ko[2];
-      load(0, ko[0]);
-#pragma unroll
-      for (int kk = 0; kk < B::XS / 32; ++kk) {
-        if (kk + 1 < B::XS / 32) load(kk + 1, ko[(kk + 1) & 1]);
-        const KOps& o = ko[kk & 1];
-#pragma unroll
-        for (int c = 0; c < B::CPG(J); ++c) {
-          if (c0 + c >= B::CTB(J)) continue;
-          acc[c] = mfma16(o.a, o.b[c], acc[c]);
-          if constexpr (B::DWS) acc[c] = mfma16(o.al, o.b[c], acc[c]);
-          if constexpr (B::DWX) acc[c] = mfma16(o.a, o.bl[c], acc[c]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      dw_unit_of<N, J, 0>(lds, dj + i * B::CPG(J), u % B::RT(J), u / B::RT(J), lane);
     } else {
+      const int rt = u % B::RT(J), c0 = (u / B::RT(J)) * B::CPG(J);
+      f32x4* acc = dj + i * B::CPG(J);
       const float* xd = reinterpret_cast<const float*>(lds + B::XD_OFF);
       const float* xh = reinterpret_cast<const float*>(lds + B::XH_OFF);
       float one = r16 == 0 ? 1.f : 0.f;
@@ -530,7 +552,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   __shared__ int rounds_s[B::NW];
   const Workspace& ws = args.ws;
   const int lane = threadIdx.x % 64;
-  const int q = threadIdx.x / 64;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);   // (wave-uniform: scalar)
   const int col = lane % 32;
   const int g = lane / 32;
   const int colx = 32 * q + col;
