@@ -78,7 +78,14 @@ struct Bwd {
   static constexpr bool G0 = !N::WIDE && staged(NW, 0) > LDS_MAX;
   static constexpr int SKIP = G0 ? N::fwdA_bytes(0) : 0;   // = fwdA_off(1): staged from here
   static constexpr bool GW = N::WIDE || staged(NW, SKIP) > LDS_MAX;
-  static constexpr int LDS = GW ? PLANES : staged(NW, SKIP);
+  // Wide bfloat16 networks: the hi sections of the forward operands of the
+  // first HS layers (as many as fit) are staged beside the planes; the
+  // recompute reads them there (read in both passes, by every block), the
+  // rest from global memory.
+  static constexpr int hs_fit(int s) { return s < N::NL && W_OFF + N::fwd_hi_off(s + 1) <= LDS_MAX ? hs_fit(s + 1) : s; }
+  static constexpr int HS = N::WIDE && N::BF16 ? hs_fit(0) : 0;
+  static constexpr int FL = HS > 0 ? kHiPrefix + HS : kPacked;   // the recompute's operand layout
+  static constexpr int LDS = GW ? (HS > 0 ? W_OFF + N::fwd_hi_off(HS) : PLANES) : staged(NW, SKIP);
   static_assert(LDS <= 160 * 1024, "LDS budget of one workgroup");
   // weight-gradient tiles (16 x 16) of layer j
   static constexpr int inp(int j) { return j == 0 ? N::IN + 1 : N::W; }
@@ -388,10 +395,13 @@ __device__ __forceinline__ bool gate(const Keep<N, LO, HI>& kp, int t) {
   else return (kp.gt[J - HI - 1].w[t / 32] >> (t % 32)) & 1u;
 }
 
-// forward recompute keeping what the backward needs
+// forward recompute keeping what the backward needs (wb: the operands as the
+// layout FL places them, LDS or global; wg: the packed copy the rest is read
+// from)
 template <class N, int J, int LO, int HI>
-__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int lane, Keep<N, LO, HI>& kp,
-                                           f32x16 (&acc)[N::RBH], f32x16& out) {
+__device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wg, int lane,
+                                           Keep<N, LO, HI>& kp, f32x16 (&acc)[N::RBH], f32x16& out) {
+  constexpr int FL = Bwd<N>::FL;
   Act<N, rup(N::HID_KS, N::KGRP)> x;
   relu_to_B<N>(acc, x);
   if constexpr (J >= Keep<N, LO, HI>::H0 && J <= HI) {
@@ -404,21 +414,23 @@ __device__ __forceinline__ void chain_keep(const uint8_t* __restrict__ wb, int l
     gates_of<N>(acc, kp.gt[J - HI - 1]);
   }
   if constexpr (J < N::NL - 1) {
-    layer_fwd<N, J, N::HID_KS>(wb, lane, x, acc);
-    chain_keep<N, J + 1, LO, HI>(wb, lane, kp, acc, out);
+    layer_fwd<N, J, N::HID_KS, FL>(wb, wg, lane, x, acc);
+    chain_keep<N, J + 1, LO, HI>(wb, wg, lane, kp, acc, out);
   } else {
     f32x16 o[1];
-    layer_fwd<N, J, N::HID_KS>(wb, lane, x, o);
+    layer_fwd<N, J, N::HID_KS, FL>(wb, wg, lane, x, o);
     out = o[0];
   }
 }
 
 // (wb0: where the first layer's forward operands are read, which may differ
-// from wb; they are requested before the encoding is computed)
+// from wb; they are requested before the encoding is computed.  wl: the
+// staged hi sections where the layout FL has them, else wb)
 template <class N, int LO, int HI>
 __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wb0,
-                                               int lane, const float ph[3], const float pl[3],
-                                               const float dd[3], Keep<N, LO, HI>& kp) {
+                                               const uint8_t* __restrict__ wl, int lane, const float ph[3],
+                                               const float pl[3], const float dd[3], Keep<N, LO, HI>& kp) {
+  constexpr int FL = Bwd<N>::FL;
   int g = lane / 32;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -429,17 +441,17 @@ __device__ __forceinline__ f32x16 forward_keep(const uint8_t* __restrict__ wb, c
   f32x16 acc[N::RBH];
   {
     FwdOps<N, 0, N::ENC_KS> first;
-    fwd_row_load<N, 0, N::ENC_KS>(wb0, wb0, lane, 0, first);
+    fwd_row_load<N, 0, N::ENC_KS, FL>(FL == kPacked ? wb0 : wl, wb0, lane, 0, first);
     float ev[N::ENC_KS * N::KSTEP];
     encode_input<N>(ph, pl, dd, g, ev);
     Act<N, rup(N::ENC_KS, N::KGRP)> a0;
     enc_to_B<N>(ev, a0);
     // matrix-core stretch: issue ahead of the other wave's vector work
     mfma_priority<N, 1>();
-    layer_fwd_from<N, 0, N::ENC_KS>(wb0, wb0, lane, a0, acc, first);
+    layer_fwd_from<N, 0, N::ENC_KS, FL>(FL == kPacked ? wb0 : wl, wb0, lane, a0, acc, first);
   }
   f32x16 out;
-  chain_keep<N, 1, LO, HI>(wb, lane, kp, acc, out);
+  chain_keep<N, 1, LO, HI>(FL == kPacked ? wb : wl, wb, lane, kp, acc, out);
   mfma_priority<N, 0>();
   return out;
 }
@@ -580,6 +592,15 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
   // wts: the base that the packed offsets of the weights are taken from (LDS
   // for the staged sections); wts0: where the first layer's forward operands
   // are read
+  if constexpr (B::HS > 0) {
+    // the hi sections of layers 0..HS-1 of the forward operands
+    uint4* dst = reinterpret_cast<uint4*>(lds + B::W_OFF);
+#pragma unroll
+    for (int j = 0; j < B::HS; ++j) {
+      const uint4* src = reinterpret_cast<const uint4*>(wglb + N::fwdA_off(j));
+      for (int i = threadIdx.x; i < N::fwdA_single(j) / 16; i += blockDim.x) dst[N::fwd_hi_off(j) / 16 + i] = src[i];
+    }
+  }
   const uint8_t* wts = B::GW ? wglb : lds + B::W_OFF - B::SKIP;
   const uint8_t* wts0 = B::G0 ? wglb : wts;
   // ---- deal the run's hits to the waves (the exchange planes are free here)
@@ -667,7 +688,7 @@ __global__ __launch_bounds__(64 * Bwd<N>::NW) void mlp_backward_kernel(BwdArgs a
     sample_input<N>(ws, hit, k, u, ph, pl, dd);
     const bool last = valid && k == K - 1;
     Keep<N, LO, HI> kp;
-    f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lane, ph, pl, dd, kp);
+    f32x16 o = forward_keep<N, LO, HI>(wts, wts0, lds + B::W_OFF, lane, ph, pl, dd, kp);
 
     // ---- compositing adjoint of the column ----
     const bool used = valid && k < nused;

@@ -196,8 +196,11 @@ using FwdOps = RowOps<N, N::groups(KS), (J > 0)>;
 
 // Where the forward operands are read: kPacked, the packed layout at wb
 // (LDS or global); kHiStaged, the hi sections and biases staged at wb in the
-// fwd_hi_* layout, the lo sections read from the packed copy at wlo.
-enum FwdLayout { kPacked = 0, kHiStaged = 1 };
+// fwd_hi_* layout, the lo sections read from the packed copy at wlo;
+// kHiPrefix + S, the hi sections of layers 0..S-1 staged at wb (fwd_hi_off
+// offsets), everything else (the other hi sections, all lo sections, the
+// biases) read from the packed copy at wlo.
+enum FwdLayout { kPacked = 0, kHiStaged = 1, kHiPrefix = 16 };
 
 template <class N, int J, int KS, int LAYOUT = kPacked>
 __device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, const uint8_t* __restrict__ wlo,
@@ -206,6 +209,13 @@ __device__ __forceinline__ void fwd_row_load(const uint8_t* __restrict__ wb, con
   if constexpr (LAYOUT == kHiStaged) {
     load_row<N, N::groups(KS), (J > 0)>(wb + N::fwd_hi_off(J), wlo + N::fwdA_off(J) + N::fwdA_single(J),
                                         wb + N::fwd_hi_bias(J) + bo, rb, lane, o);
+  } else if constexpr (LAYOUT >= kHiPrefix) {
+    const uint8_t* P = wlo + N::fwdA_off(J);
+    if constexpr (J < LAYOUT - kHiPrefix)
+      load_row<N, N::groups(KS), (J > 0)>(wb + N::fwd_hi_off(J), P + N::fwdA_single(J), wlo + N::bias_off(J) + bo,
+                                          rb, lane, o);
+    else
+      load_row<N, N::groups(KS), (J > 0)>(P, P + N::fwdA_single(J), wlo + N::bias_off(J) + bo, rb, lane, o);
   } else {
     const uint8_t* A = wb + N::fwdA_off(J);
     load_row<N, N::groups(KS), (J > 0)>(A, A + N::fwdA_single(J), wb + N::bias_off(J) + bo, rb, lane, o);
