@@ -55,7 +55,8 @@ struct Bwd {
   // Weights staged in LDS beside the planes.  Where they do not all fit, the
   // first layer's forward operands (requested ahead of the encoding, which
   // covers their latency) are read from global memory instead, L2-resident
-  // while a primitive's work items run; wide networks read all of them there.
+  // while a primitive's work items run; wide networks read there all but the
+  // hi sections staged for their recompute (HS below).
   static constexpr int LDS_MAX = 160 * 1024 - 256;   // (less the static arrays)
   static constexpr int staged(int nw, int skip) { return rup(planes(nw), 256) + N::total_bytes() - skip; }
   // Waves per workgroup.  The bfloat16 forms of networks up to 64 wide run
