@@ -4,8 +4,9 @@
 //
 // Work decomposition as in the forward: one workgroup per run of up to 64
 // hits per wave of one primitive's list, its operands (forward and
-// transposed) staged in LDS, the run dealt to the waves by sample count,
-// each wave walking its hits' samples in 32-column blocks.
+// transposed) staged in LDS as far as they fit beside the exchange planes,
+// the run dealt to the waves by sample count, each wave walking its hits'
+// samples in 32-column blocks.
 // Per block the wave
 //   1. recomputes the network, keeping the hi parts of the layer inputs in
 //      registers (nothing is stored to memory between forward and backward);
@@ -22,7 +23,7 @@
 // publish delta_j and the layer inputs of their blocks to LDS, then each wave
 // accumulates its units of dW_j (a 16-row strip by a few 16-column tiles)
 // over all the workgroup's samples in registers.  Those sums are added to
-// global memory once per work item.
+// global memory once per workgroup.
 #include "mlp_kernels.h"
 
 namespace msplat {
