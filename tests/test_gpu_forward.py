@@ -66,7 +66,9 @@ TOL = {"fp32": 1e-5, "bf16": 2e-3, "bf16x3": 2e-3}
 def test_full_size_sampled_rays(ci, precision):
     """Configs 1 (800x800), 3 (1920x1080, 128-wide networks) and 4 (16 views,
     7 M rays) rendered at full size in one call, as the benchmark launches
-    them, checked on 512 seeded rays against the oracle."""
+    them, checked on 512 seeded rays against the oracle: each sampled ray's
+    hit list (primitives in depth order) bit-exact, its colour within the
+    form's tolerance."""
     tol = TOL[precision]
     cfg = synth.CONFIGS[ci]
     sc = scene(ci)
@@ -75,6 +77,10 @@ def test_full_size_sampled_rays(ci, precision):
     g = gpu_render(ci, precision, sc, o, d, opts)
     idx = np.sort(np.random.default_rng(77).choice(len(o), 512, replace=False))
     ref = oracle_render(ci, sc, o[idx], d[idx], opts, ray_ids=idx)
+    go, ro = g["ray_off"], ref["ray_off"]
+    np.testing.assert_array_equal(go[idx + 1] - go[idx], np.diff(ro))
+    for k, i in enumerate(idx):
+        np.testing.assert_array_equal(g["prim"][go[i]:go[i + 1]], ref["prim"][ro[k]:ro[k + 1]])
     c = compare_rgb(g, ref, tol, opts.t_stop, idx=idx)
     print(f"config {ci} full size {precision}: {c} stats {g['stats']}")
     assert c["max_err"] <= tol
