@@ -352,6 +352,43 @@ def test_samples_are_stratified_in_their_bins():
     assert ((hist - e) ** 2 / e).sum() < 60          # chi2(15) far tail
 
 
+def _pcg_inverse(h):
+    """Inverse of the PCG output permutation (Jarzynski and Olano, JCGT 2020),
+    undone step by step from its published constants: the final xorshift by
+    22 (its own inverse, as 2 x 22 >= 32), the odd multiplier 277803737 (its
+    inverse modulo 2^32), the data-dependent xorshift (the top four bits are
+    unchanged and give the shift back), the LCG step 747796405 v + 2891336453."""
+    m = (1 << 32) - 1
+    out = []
+    for x in (int(v) for v in np.asarray(h, np.uint32)):
+        word = x ^ (x >> 22)
+        y = (word * pow(277803737, -1, 1 << 32)) & m
+        sh = (y >> 28) + 4
+        state, t = y, y >> sh
+        while t:
+            state ^= t
+            t >>= sh
+        out.append(((state - 2891336453) * pow(747796405, -1, 1 << 32)) & m)
+    return np.array(out, np.uint64)
+
+
+def test_pcg_hash_is_the_published_permutation():
+    """The sample-offset hash is a bijection of the 32-bit integers: it is
+    undone by the inverse of each published step, it maps 2^20 distinct
+    inputs to distinct outputs (a random function would collide about 128
+    times), and one flipped input bit changes about half the output bits."""
+    from oracle.pcg import pcg_hash
+    rng = np.random.default_rng(11)
+    v = rng.integers(0, 1 << 32, 4096, dtype=np.uint64).astype(np.uint32)
+    v[:4] = [0, 1, 0xFFFFFFFF, 0x80000000]
+    np.testing.assert_array_equal(_pcg_inverse(pcg_hash(v)), v.astype(np.uint64))
+    h = pcg_hash(np.arange(1 << 20, dtype=np.uint32))
+    assert len(np.unique(h)) == 1 << 20
+    flips = [np.unpackbits((pcg_hash(v) ^ pcg_hash(v ^ np.uint32(1 << b))).view(np.uint8)).sum() / len(v)
+             for b in range(32)]
+    assert 15.0 < min(flips) and max(flips) < 17.0
+
+
 def test_early_termination_stops_after_first_sample_below_threshold():
     m = SMALL
     nprim = 12
