@@ -88,7 +88,9 @@ def test_full_size_sampled_rays(ci, precision):
     if g["feat"] is not None:
         same = ray_nused(g)[idx] == ref["n_used"]
         ferr = float(np.abs(g["feat"][idx] - ref["feat"])[same].max())
-        assert ferr <= 4 * tol * max(1.0, float(np.abs(ref["feat"]).max()))
+        fmax = float(np.abs(ref["feat"]).max())
+        print(f"feature max err {ferr:.3g} (max |feature| {fmax:.3g})")
+        assert ferr <= 4 * tol * max(1.0, fmax)
 
 
 def test_forward_is_deterministic_and_label_invariant():
