@@ -1,7 +1,10 @@
 """GPU parity in the corners of the option space: rays starting inside a
 primitive (chord clipped at t = 0), a non-black background, midpoint samples
-(no jitter), chord-proportional sample counts up to the 128 maximum, and an
-early-termination threshold high enough to cut most rays."""
+(no jitter), chord-proportional sample counts up to the 128 maximum, an
+early-termination threshold high enough to cut most rays, and rays with more
+hits than a register-sorted group holds."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -9,7 +12,7 @@ import torch
 import oracle
 import synth
 from gpu_cases import (compare_rgb, gpu_render, gradient_mask, oracle_model, oracle_opts, oracle_render,
-                       ray_nused, scene)
+                       ray_nused, scene, spec_of, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,3 +72,43 @@ def test_clipped_chords_background_midpoints(precision, t_stop):
         err = float(np.abs(got[k] - grads[k]).max() / max(np.abs(grads[k]).max(), 1e-30))
         print(f"  {k}: {err:.2e}")
         assert err <= TOL[precision], k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("t_stop", [0.0, 1e-4])
+def test_rays_with_more_hits_than_a_sorted_group(precision, t_stop):
+    """600 nested supports around the origin and rays from near it: every ray
+    hits all 600 primitives, more than the 512 hits the fill sorts in
+    registers per group of rays, so every packet takes the per-ray path
+    (appended in primitive order, insertion-sorted in the ray's segment).
+    Hit lists bit-exact, RGB within the form's bar (133 rays: two full
+    packets and a ragged one)."""
+    from paper_2606_03877_amd import Renderer, RenderOpts
+    ci = 0
+    cfg = dataclasses.replace(synth.CONFIGS[ci], num_prims=600)
+    sc = synth.make_scene(cfg, seed=51)
+    rng = np.random.default_rng(52)
+    sc["center"] = rng.uniform(-0.05, 0.05, (600, 3))
+    sc["scale"] = rng.uniform(0.6, 1.0, (600, 3))
+    sc = {k: np.ascontiguousarray(v, np.float32) for k, v in sc.items()}
+    n = 2 * 64 + 5
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = rng.uniform(-0.02, 0.02, (n, 3))
+    o, d = o.astype(np.float32), d.astype(np.float32)
+    opts = RenderOpts(samples_fixed=4, t_stop=t_stop, jitter=1, jitter_seed=53)
+    r = Renderer(spec_of(cfg, precision), opts)
+    t, to, td = to_dev(sc, o, d)
+    rgb, trans, _, ws = r.forward(t["center"], t["scale"], t["quat"], t["mlp"], to, td)
+    torch.cuda.synchronize()
+    off, prim, _, nused = r.hits(ws, n)
+    g = {"rgb": rgb.cpu().numpy(), "trans": trans.cpu().numpy(), "ray_off": off, "prim": prim,
+         "hit_nused": nused}
+    assert np.diff(g["ray_off"]).min() > 512
+    ref = oracle_render(ci, sc, o, d, opts)
+    np.testing.assert_array_equal(g["ray_off"], ref["ray_off"])
+    np.testing.assert_array_equal(g["prim"], ref["prim"])
+    c = compare_rgb(g, ref, TOL[precision], opts.t_stop)
+    print(f"{precision} t_stop={t_stop}: {len(g['prim'])} hits; {c}")
+    assert c["max_err"] <= TOL[precision]
+    assert c["cut_mismatch_err"] <= opts.t_stop + TOL[precision]
