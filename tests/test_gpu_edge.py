@@ -11,8 +11,8 @@ import torch
 
 import oracle
 import synth
-from gpu_cases import (compare_rgb, gpu_render, gradient_mask, oracle_model, oracle_opts, oracle_render,
-                       ray_nused, scene, spec_of, to_dev)
+from gpu_cases import (RELU_AMBIGUOUS, compare_rgb, gpu_render, gradient_mask, oracle_model, oracle_opts,
+                       oracle_render, ray_nused, scene, spec_of, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -81,8 +81,8 @@ def test_rays_with_more_hits_than_a_sorted_group(precision, t_stop):
     hits all 600 primitives, more than the 512 hits the fill sorts in
     registers per group of rays, so every packet takes the per-ray path
     (appended in primitive order, insertion-sorted in the ray's segment).
-    Hit lists bit-exact, RGB within the form's bar (133 rays: two full
-    packets and a ragged one)."""
+    Hit lists bit-exact, RGB and gradients within the form's bar (133 rays:
+    two full packets and a ragged one)."""
     from paper_2606_03877_amd import Renderer, RenderOpts
     ci = 0
     cfg = dataclasses.replace(synth.CONFIGS[ci], num_prims=600)
@@ -112,3 +112,32 @@ def test_rays_with_more_hits_than_a_sorted_group(precision, t_stop):
     print(f"{precision} t_stop={t_stop}: {len(g['prim'])} hits; {c}")
     assert c["max_err"] <= TOL[precision]
     assert c["cut_mismatch_err"] <= opts.t_stop + TOL[precision]
+    if t_stop == 0.0:
+        return
+    # the gradient through 600 hits per ray (the adjoint walks each ray's
+    # chunks from the last hit back).  Rays are left out where the cut falls
+    # on another sample or a ReLU gate of a composited sample is within
+    # rounding of switching (the samples past the cut carry no gradient).
+    p64 = oracle.to_tensors(sc)
+    out_s = oracle.render(p64["center"], p64["scale"], p64["quat"], p64["mlp"],
+                          torch.from_numpy(o.astype(np.float64)), torch.from_numpy(d.astype(np.float64)),
+                          oracle_model(cfg), oracle_opts(opts, precision), keep_samples=True)
+    smp = out_s["samples"]
+    sray = np.asarray(smp["ray"])
+    first = np.searchsorted(sray, np.arange(n))
+    composited = np.arange(len(sray)) - first[sray] < out_s["n_used"][sray]
+    margin = np.full(n, np.inf)
+    np.minimum.at(margin, sray[composited], np.asarray(smp["relu_margin"])[composited])
+    keep = (ray_nused(g) == out_s["n_used"]) & (margin >= RELU_AMBIGUOUS[precision])
+    print(f"rays left out: {n - int(keep.sum())} of {n}")
+    assert n - keep.sum() <= 0.05 * n
+    g_rgb = (np.random.default_rng(54).standard_normal((n, 3)) / n).astype(np.float32)
+    g_rgb[~keep] = 0.0
+    out = r.backward(ws, t["center"], t["scale"], t["quat"], t["mlp"], to, td, torch.from_numpy(g_rgb).cuda())
+    got = dict(zip(KEYS, [x.cpu().numpy() for x in out]))
+    _, _, _, grads, _ = oracle.loss_and_grads(sc, o.astype(np.float64), d.astype(np.float64),
+                                              oracle_model(cfg), oracle_opts(opts, precision), grad_rgb=g_rgb)
+    for k in KEYS:
+        err = float(np.abs(got[k] - grads[k]).max() / max(np.abs(grads[k]).max(), 1e-30))
+        print(f"  {k}: {err:.2e}")
+        assert err <= TOL[precision], k
